@@ -1,0 +1,296 @@
+"""The CPU oracle for the CMB hot path of arXiv 2602.15104.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, independent
+reference against which the HIP library (package ``paper_2602_15104_amd``) is
+checked.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code with the library: its
+tables are built by ``oracle.background`` (Python), its perturbation
+integrator, Bessel functions and quadratures are the C files in this folder,
+compiled with gcc.
+
+Functions
+---------
+build_tables(cosmo, prec, k, n_tau)   background/thermo tables, start times,
+                                      output grid (App. A.2, B.1, B.2, B.4)
+perturb(tab, idx=None, ...)           sources S[k][3][n_tau] (App. B.3, C, B.4)
+los(tab, S, ell_max, pol)             transfer functions (App. B.4)
+cl(tab, DT, DE, ell_max, pol)         C_ell^{TT,TE,EE} (eq. c_ell_def)
+solve(...)                            everything above in order
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+from . import background
+from .background import OracleError, build_tables  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_BUILD = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_BUILD, "liboracle.so")
+_SRCS = [os.path.join(_HERE, "perturb.c"), os.path.join(_HERE, "spectra.c")]
+_lock = threading.Lock()
+_lib = None
+
+STATUS_NAMES = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW", 4: "BAD_INPUT"}
+
+
+def build_c(force: bool = False) -> str:
+    """Compile the oracle's C sources with gcc (-O2, OpenMP, no hand SIMD)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    newest = max(os.path.getmtime(s) for s in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
+        tmp = _LIB + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-o", tmp] + _SRCS + ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OTab(ctypes.Structure):
+    _fields_ = [
+        ("rt_g0", ctypes.c_double), ("rt_ur0", ctypes.c_double), ("rt_c0", ctypes.c_double),
+        ("rt_b0", ctypes.c_double), ("rt_L", ctypes.c_double),
+        ("pref_ncdm", ctypes.c_double), ("m_over_T", ctypes.c_double),
+        ("n_q", ctypes.c_int), ("q", ctypes.c_void_p), ("W", ctypes.c_void_p),
+        ("R_nu", ctypes.c_double),
+        ("n", ctypes.c_int), ("L0", ctypes.c_double), ("dl", ctypes.c_double),
+        ("f_ldk", ctypes.c_void_p), ("M_ldk", ctypes.c_void_p),
+        ("f_kap", ctypes.c_void_p), ("M_kap", ctypes.c_void_p),
+        ("f_lcs", ctypes.c_void_p), ("M_lcs", ctypes.c_void_p),
+        ("f_ltau", ctypes.c_void_p), ("M_ltau", ctypes.c_void_p),
+    ]
+
+
+class _OPrec(ctypes.Structure):
+    _fields_ = [
+        ("lg", ctypes.c_int), ("lp", ctypes.c_int), ("ln", ctypes.c_int), ("nq", ctypes.c_int), ("lq", ctypes.c_int),
+        ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int),
+        ("pcoeff", ctypes.c_double), ("icoeff", ctypes.c_double), ("dcoeff", ctypes.c_double),
+        ("sw", ctypes.c_double), ("isw", ctypes.c_double), ("dop", ctypes.c_double), ("pol", ctypes.c_double),
+        ("grav", ctypes.c_double), ("thom", ctypes.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = build_c()
+            L = ctypes.CDLL(path)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int)
+            L.oracle_perturb.restype = ctypes.c_int
+            L.oracle_perturb.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, ip, ip, dp, ctypes.c_int, dp]
+            L.oracle_rhs.restype = None
+            L.oracle_rhs.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, ctypes.c_double,
+                                     dp, dp]
+            L.oracle_rk4.restype = ctypes.c_int
+            L.oracle_rk4.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_long)]
+            L.oracle_perturb_many.restype = ctypes.c_int
+            L.oracle_perturb_many.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_int, dp, dp,
+                                              dp, dp, ctypes.c_int, dp, dp, ip, ip, ip]
+            L.oracle_state_size.restype = ctypes.c_int
+            L.oracle_state_size.argtypes = [ctypes.POINTER(_OPrec)]
+            L.oracle_bessel.restype = None
+            L.oracle_bessel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_longdouble)]
+            L.oracle_los.restype = None
+            L.oracle_los.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, dp, dp]
+            L.oracle_cl.restype = None
+            L.oracle_cl.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, dp]
+            _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+class _Bound:
+    """ctypes views of a Tables object, keeping the arrays alive."""
+
+    def __init__(self, t):
+        bg = t.bg
+        self.keep = []
+
+        def arr(x):
+            a = np.ascontiguousarray(x, dtype=np.float64)
+            self.keep.append(a)
+            return a.ctypes.data
+
+        self.tab = _OTab(
+            bg.rt_g0, bg.rt_ur0, bg.rt_c0, bg.rt_b0, bg.rt_L, bg.pref_ncdm, bg.m_over_T,
+            len(bg.q), arr(bg.q if len(bg.q) else np.zeros(1)), arr(bg.W if len(bg.W) else np.zeros(1)), bg.R_nu,
+            t.n, t.L0, t.dl,
+            arr(t.cols["ln_dk"]), arr(t.M["ln_dk"]), arr(t.cols["kappa"]), arr(t.M["kappa"]),
+            arr(t.cols["ln_cs2"]), arr(t.M["ln_cs2"]), arr(t.cols["ln_tau"]), arr(t.M["ln_tau"]))
+
+
+def make_prec(prec: dict, nq: int, rtol: float = 0.0, atol: float = 0.0) -> _OPrec:
+    return _OPrec(int(prec["ell_gamma"]), int(prec["ell_pol"]), int(prec["ell_nu"]), int(nq), int(prec["ell_ncdm"]),
+                  rtol, atol, int(prec["max_steps"]), prec["pcoeff"], prec["icoeff"], prec["dcoeff"],
+                  prec["scale_sw"], prec["scale_isw"], prec["scale_dop"], prec["scale_pol"],
+                  prec.get("gravity_scale", 1.0), prec.get("thomson_scale", 1.0))
+
+
+def tolerances(prec: dict, k: np.ndarray):
+    """(rtol, atol) per mode: small-k values below k_split, large-k values
+    at and above it (App. A.2, perturbation solver options)."""
+    small = k < prec["k_split"]
+    rtol = np.where(small, prec["rtol_small"], prec["rtol_large"]).astype(np.float64)
+    atol = np.where(small, prec["atol_small"], prec["atol_large"]).astype(np.float64)
+    return rtol, atol
+
+
+def state_size(prec: dict, nq: int) -> int:
+    return lib().oracle_state_size(ctypes.byref(make_prec(prec, nq)))
+
+
+def perturb(t, idx=None, prec_over: dict | None = None):
+    """Sources for the modes t.k[idx] (all modes by default).
+    Returns (S[n][3][n_tau], status[n], nsteps[n], naccept[n])."""
+    prec = dict(t.prec)
+    if prec_over:
+        prec.update(prec_over)
+    idx = np.arange(len(t.k)) if idx is None else np.asarray(idx, dtype=np.int64)
+    k = np.ascontiguousarray(t.k[idx], dtype=np.float64)
+    lna0 = np.ascontiguousarray(t.lna_i[idx], dtype=np.float64)
+    rtol, atol = tolerances(prec, k)
+    if prec_over and "rtol" in prec_over:
+        rtol[:] = prec_over["rtol"]
+        atol[:] = prec_over["atol"]
+    n_out = len(t.lna_src)
+    S = np.zeros((len(k), 3, n_out))
+    st = np.zeros(len(k), dtype=np.int32)
+    ns = np.zeros(len(k), dtype=np.int32)
+    na = np.zeros(len(k), dtype=np.int32)
+    b = _Bound(t)
+    p = make_prec(prec, len(t.bg.q))
+    lna_out = np.ascontiguousarray(t.lna_src, dtype=np.float64)
+    lib().oracle_perturb_many(ctypes.byref(b.tab), ctypes.byref(p), len(k), _dp(k), _dp(lna0), _dp(rtol), _dp(atol),
+                              n_out, _dp(lna_out), _dp(S), _ip(st), _ip(ns), _ip(na))
+    return S, st, ns, na
+
+
+def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None, y0=None, want_y: bool = False,
+                rtol: float | None = None, atol: float | None = None, acc_cap: int = 0, want_diag: bool = False):
+    """One mode with full control (tests): custom start, output times,
+    initial state, tolerances; optionally the dense-output states and the
+    accepted step sequence."""
+    prec = dict(t.prec)
+    if prec_over:
+        prec.update(prec_over)
+    if rtol is None:
+        r, a = tolerances(prec, np.array([k]))
+        rtol, atol = float(r[0]), float(a[0])
+    p = make_prec(prec, len(t.bg.q), rtol, atol)
+    N = lib().oracle_state_size(ctypes.byref(p))
+    lna_out = np.ascontiguousarray(lna_out, dtype=np.float64)
+    n_out = len(lna_out)
+    S = np.zeros((3, n_out))
+    Y = np.zeros((n_out, N)) if want_y else None
+    y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+    acc = np.zeros(max(acc_cap, 1))
+    ns = ctypes.c_int(0)
+    na = ctypes.c_int(0)
+    D = np.zeros((n_out, 4))
+    b = _Bound(t)
+    st = lib().oracle_perturb(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna0), n_out, _dp(lna_out), _dp(S),
+                              _dp(Y) if want_y else None, _dp(y0a) if y0a is not None else None, ctypes.byref(ns),
+                              ctypes.byref(na), _dp(acc) if acc_cap else None, acc_cap, _dp(D) if want_diag else None)
+    out = {"S": S, "status": st, "nsteps": ns.value, "naccept": na.value, "N": N}
+    if want_diag:
+        out["diag"] = D  # h', eta', alpha, alpha' per output time
+    if want_y:
+        out["y"] = Y
+    if acc_cap:
+        out["accepted_lna"] = acc[: min(na.value, acc_cap)]
+    return out
+
+
+def rk4_one(t, k: float, lna0: float, lna_out, h_max: float = 1e-3, c_stab: float = 0.5, want_y: bool = False,
+            prec_over: dict | None = None):
+    """Brute-force classical RK4 on the same right-hand side (tests)."""
+    prec = dict(t.prec)
+    if prec_over:
+        prec.update(prec_over)
+    p = make_prec(prec, len(t.bg.q), 0.0, 0.0)
+    N = lib().oracle_state_size(ctypes.byref(p))
+    lna_out = np.ascontiguousarray(lna_out, dtype=np.float64)
+    S = np.zeros((3, len(lna_out)))
+    Y = np.zeros((len(lna_out), N)) if want_y else None
+    ns = ctypes.c_long(0)
+    b = _Bound(t)
+    lib().oracle_rk4(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna0), len(lna_out), _dp(lna_out), _dp(S),
+                     _dp(Y) if want_y else None, h_max, c_stab, ctypes.byref(ns))
+    out = {"S": S, "nsteps": ns.value}
+    if want_y:
+        out["y"] = Y
+    return out
+
+
+def rhs(t, k: float, lna: float, y, prec_over: dict | None = None):
+    prec = dict(t.prec)
+    if prec_over:
+        prec.update(prec_over)
+    p = make_prec(prec, len(t.bg.q), 0.0, 0.0)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.zeros_like(y)
+    b = _Bound(t)
+    lib().oracle_rhs(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna), _dp(y), _dp(dy))
+    return dy
+
+
+def bessel(L: int, x: float) -> np.ndarray:
+    """j_0..j_L at x, computed in long double, returned as float64."""
+    buf = (ctypes.c_longdouble * (L + 1))()
+    lib().oracle_bessel(L, float(x), buf)
+    return np.array([float(v) for v in buf])
+
+
+def los(t, S: np.ndarray, ell_max: int, pol: bool, k=None, chi=None, w=None, s_pol: float | None = None):
+    """Transfer functions Delta_T, Delta_E [ell-2][k] for 2 <= ell <= ell_max."""
+    k = np.ascontiguousarray(t.k if k is None else k, dtype=np.float64)
+    chi = np.ascontiguousarray(t.chi_src if chi is None else chi, dtype=np.float64)
+    w = np.ascontiguousarray(t.w_src if w is None else w, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    nl = ell_max - 1
+    DT = np.zeros((nl, len(k)))
+    DE = np.zeros((nl, len(k)))
+    sp = t.prec["scale_pol"] if s_pol is None else s_pol
+    lib().oracle_los(len(k), _dp(k), len(chi), _dp(chi), _dp(w), _dp(S), ell_max, sp, 1 if pol else 0, _dp(DT),
+                     _dp(DE))
+    return DT, DE
+
+
+def cl(k, DT, DE, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: float = 0.05):
+    """C_ell[3][ell_max+1] (TT, TE, EE), zero for ell < 2."""
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    Cl = np.zeros((3, ell_max + 1))
+    DT = np.ascontiguousarray(DT)
+    DE = np.ascontiguousarray(DE)
+    lib().oracle_cl(len(k), _dp(k), ell_max, _dp(DT), _dp(DE), 1 if pol else 0, A_s, n_s, k_pivot, _dp(Cl))
+    return Cl
+
+
+def solve(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, tables=None):
+    """The whole path for one cosmology: tables, sources, transfers, C_ell."""
+    t = build_tables(cosmo, prec, np.asarray(k, dtype=np.float64), n_tau) if tables is None else tables
+    S, st, ns, na = perturb(t)
+    DT, DE = los(t, S, ell_max, pol)
+    C = cl(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    return {"tables": t, "S": S, "status": st, "nsteps": ns, "naccept": na, "DT": DT, "DE": DE, "Cl": C}

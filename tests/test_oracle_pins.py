@@ -1,0 +1,456 @@
+"""Pins for the CPU oracle: checks against closed forms, limits, identities,
+library routines and brute force, chosen so that a dropped term, a wrong
+sign, index or factor in the oracle fails at least one of them.
+
+All CPU-only (not marked gpu).  Citations refer to arXiv 2602.15104.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import gammaln, spherical_jn
+
+import cmb_workloads as W
+import oracle as O
+from oracle import background as B
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+@pytest.fixture(scope="module")
+def tab12():
+    wl = W.small_case(n_k=4, n_tau=50, ell_max=20, ell_g=12)
+    return O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+
+
+def _tau(t, lna):
+    return math.exp(B.spline_eval(t.cols["ln_tau"], t.M["ln_tau"], t.L0, t.dl, lna))
+
+
+# ---------------------------------------------------------------- P1 quadrature
+def test_paper_rules_weight_sums():
+    """App. B.3: with Psi = 1 the printed rules must reproduce
+    int q^4 e^q/(1+e^q)^2 dq = 4 int q^3/(e^q+1) dq = 4 * 7 pi^4/120."""
+    target = 7 * math.pi ** 4 / 120
+    for key in ("howlett_3pt", "gauss_laguerre_5pt"):
+        s = sum(GOLD[key]["K"])
+        assert abs(s / target - 1) < 1e-6, (key, s)
+
+
+@pytest.mark.parametrize("n", [3, 5, 12])
+def test_fermi_dirac_rule_moments(n):
+    """Gauss rule for q^2/(e^q+1): exact for polynomials of degree < 2n,
+    int q^(m+2)/(e^q+1) dq = (1 - 2^-(m+2)) (m+2)! zeta(m+3)."""
+    import mpmath as mp
+    q, w = B.fermi_dirac_rule(n)
+    assert np.all(w > 0) and np.all(np.diff(q) > 0)
+    for m in range(0, 2 * n):
+        ex = float((1 - mp.mpf(2) ** (-(m + 2))) * mp.factorial(m + 2) * mp.zeta(m + 3))
+        assert abs(np.sum(w * q ** m) / ex - 1) < 1e-12, m
+
+
+def test_massive_nu_massless_limit():
+    """rho of a massive species with m -> 0 equals the massless formula
+    N 7 pi^2/120 T^4 a^-4 at the massive temperature (Sec. 2.4)."""
+    c = W.fiducial()
+    c["N_nu_massless"] = 3.0
+    c["N_nu_massive"] = 1.0
+    c["m_nu_massive"] = 1e-12
+    bg = B.Background(c, 12)
+    for a in (1e-6, 1e-3, 1.0):
+        rho, p = bg.rho_ncdm(a)
+        ex = (7 * math.pi ** 2 / 120) * (bg.Tncdm0 ** 4) * bg.to_rt / a ** 4
+        assert abs(rho / ex - 1) < 1e-12
+        assert abs(p / (rho / 3) - 1) < 1e-12
+
+
+def test_neff_split():
+    """eq. Neffdef: Neff = N_massless (T_ml/T_inst)^4 + N_massive (T_m/T_inst)^4."""
+    c = W.fiducial()
+    c["Neff"] = 3.044
+    c["N_nu_massive"] = 1.0
+    bg = B.Background(c, 12)
+    ti = (4 / 11) ** (1 / 3)
+    assert abs(bg.N_massless * (0.71636856 / ti) ** 4 + (0.71611 / ti) ** 4 - 3.044) < 1e-12
+    assert 1.99 < bg.N_massless < 2.01
+    c2 = W.fiducial()
+    c2["Neff"] = 0.5
+    c2["N_nu_massive"] = 1.0
+    with pytest.raises(O.OracleError) as e:
+        B.Background(c2, 12)
+    assert e.value.code == "NEG_NMASSLESS"
+    c3 = W.fiducial()
+    c3["Neff"] = 3.044
+    c3["N_nu_massless"] = 3.0
+    with pytest.raises(O.OracleError) as e:
+        B.Background(c3, 12)
+    assert e.value.code == "CONFLICT"
+
+
+# ---------------------------------------------------------------- P12/P13 tables
+def test_background_closed_forms(tab12):
+    bg = tab12.bg
+    # Friedmann closure at a = 1 and the scaling of each species
+    assert abs(bg.Hc(1.0) / bg.H0 - 1) < 1e-14
+    for a in (1e-7, 1e-3, 0.5):
+        rho, p = bg.rho_tot(a)
+        ex = (bg.rt_g0 + bg.rt_ur0) * a ** -4 + (bg.rt_c0 + bg.rt_b0) * a ** -3 + bg.rt_L
+        assert abs(rho / ex - 1) < 1e-14
+        # H' from its closed form vs a centred difference in ln a
+        h = 1e-5
+        fd = (bg.Hc(a * math.exp(h)) - bg.Hc(a * math.exp(-h))) / (2 * h)
+        assert abs(bg.Hc_prime(a) - fd) < 1e-7 * abs(bg.Hc(a))
+    # photon density: omega_gamma h^2 for T = 2.7255 K is 2.473e-5
+    assert abs(bg.rt_g0 / B.H100_MPC ** 2 / 2.4728e-5 - 1) < 2e-3
+
+
+def test_table_fiducials(tab12):
+    """Loose agreement with the fiducial conformal times printed in App. A.2
+    (our recombination is a three-level atom, not HyRex, and h differs by 0.3%)."""
+    fid = GOLD["fiducials"]
+    t = tab12
+    assert abs(t.tau0 / fid["tau0_fid_Mpc"] - 1) < 0.01
+    g = np.exp(t.cols["ln_dk"] - t.cols["kappa"])
+    j = int(np.argmax(g))
+    assert abs(t.tau_knots[j] / fid["tau_rec_fid_Mpc"] - 1) < 0.02
+    assert 1050 < math.exp(-t.lna[j]) - 1 < 1120
+    # sound horizon at the visibility peak, c_s = 1/sqrt(3(1+R)), R = 3 rho_b / 4 rho_g
+    bg = t.bg
+    rs = 0.0
+    for i in range(j):
+        for l, wgt in ((t.lna[i], 0.5), (t.lna[i + 1], 0.5)):
+            a = math.exp(l)
+            R = 0.75 * bg.rt_b0 / bg.rt_g0 * a
+            rs += wgt * (t.lna[i + 1] - t.lna[i]) / bg.Hc(a) / math.sqrt(3 * (1 + R))
+    assert abs(rs / fid["rs_rec_fid_Mpc"] - 1) < 0.02
+
+
+def test_thermo_identities(tab12):
+    t = tab12
+    assert t.cols["kappa"][-1] == 0.0
+    # visibility integrates to 1 - e^{-kappa(start)} ~ 1 over the output grid
+    g = []
+    for l in t.lna_src:
+        dk, kap, cs2, tau, dkp = B.eval_thermo(t, l)
+        g.append(dk * math.exp(-kap))
+    s = float(np.sum(np.array(g) * t.w_src))
+    assert abs(s - 1) < 0.05
+    # tau_reio re-derived from z_reio equals the input (root find, eq. tau_reion)
+    assert abs(B.tau_reion_of(t.bg, t.z_reio) - t.cosmo["tau_reio"]) < 1e-10
+    # x_e: fully ionised early (H + both He electrons), reionised late
+    assert abs(t.xe[0] - (1 + 2 * t.bg.fHe)) < 1e-6
+    assert abs(t.xe[-1] - (1 + 2 * t.bg.fHe)) < 1e-3
+    # tight-coupling start: Hc tau_c = R_tc there
+    a = math.exp(t.lna_tc)
+    dk = B.xe_early(t.bg, a, t.z_reio) * t.bg.dk_pref / a ** 2
+    assert abs(t.bg.Hc(a) / dk / t.prec["R_tc"] - 1) < 1e-12
+
+
+def test_start_times():
+    """a_i(k) = min(a_tc, a_large(k)); no root of k/Hc = R_large for tiny k."""
+    wl = W.small_case(n_k=6, k_min=1e-5, k_max=0.5)
+    t = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    bg = t.bg
+    for k, l in zip(t.k, t.lna_i):
+        a = math.exp(l)
+        if l < t.lna_tc - 1e-12:
+            assert abs(k / bg.Hc(a) / t.prec["R_large"] - 1) < 1e-10
+        else:
+            assert l == t.lna_tc
+    assert t.lna_i[0] == t.lna_tc  # k = 1e-5: superhorizon until today
+
+
+def test_spline_exact_for_cubic():
+    """The natural spline reproduces a linear function exactly and a smooth
+    function to O(h^4) in the interior."""
+    h = 0.01
+    x = np.arange(0, 201) * h
+    f = 3.0 - 2.0 * x
+    M = B.natural_spline_M(f, h)
+    for xx in (0.0033, 0.5, 1.2345, 1.99):
+        assert abs(B.spline_eval(f, M, 0.0, h, xx) - (3 - 2 * xx)) < 1e-13
+    f = np.sin(x)
+    M = B.natural_spline_M(f, h)
+    v, d = B.spline_eval(f, M, 0.0, h, 1.0005, deriv=True)
+    assert abs(v - math.sin(1.0005)) < 1e-10 and abs(d - math.cos(1.0005)) < 1e-7
+
+
+def test_invalid_inputs():
+    wl = W.small_case()
+    with pytest.raises(O.OracleError):
+        O.build_tables(wl.cosmo, wl.prec, np.array([0.1, 0.01]), 50)
+    c = dict(wl.cosmo)
+    c["z_reio"] = 8.0
+    with pytest.raises(O.OracleError) as e:
+        O.build_tables(c, wl.prec, wl.k, 50)
+    assert e.value.code == "CONFLICT"
+    c = dict(wl.cosmo)
+    c["tau_reio"] = 5.0
+    with pytest.raises(O.OracleError) as e:
+        O.build_tables(c, wl.prec, wl.k, 50)
+    assert e.value.code == "ROOT"
+
+
+# ---------------------------------------------------------------- P2 free streaming
+def test_free_streaming_is_bessel(tab12):
+    """Gravity and Thomson scattering off, F_l(0) = delta_l0: the massless
+    hierarchies (App. C) solve to F_l(tau) = j_l(k (tau - tau_i)) (plane-wave
+    expansion) until the truncation at l_max is felt (k tau ~ l_max)."""
+    t = tab12
+    N = O.state_size(t.prec, 0)
+    lg = t.prec["ell_gamma"]
+    g0 = 3
+    n0 = g0 + lg + 1 + (t.prec["ell_pol"] + 1 if t.prec["ell_pol"] > 0 else 0)
+    k, lna0 = 0.02, -8.0
+    lout = np.linspace(-7.9, -1.0, 150)
+    y0 = np.zeros(N)
+    y0[n0] = 1.0
+    y0[g0] = 1.0
+    r = O.perturb_one(t, k, lna0, lout, prec_over={"gravity_scale": 0.0, "thomson_scale": 0.0, "max_steps": 100000},
+                      y0=y0, want_y=True, rtol=1e-11, atol=1e-14)
+    assert r["status"] == 0
+    x = k * (np.array([_tau(t, l) for l in lout]) - _tau(t, lna0))
+    m = x <= lg / 2
+    Y = r["y"]
+    for l in range(0, lg // 2 - 1):
+        for base in (n0, g0):
+            F = {0: Y[:, base], 1: Y[:, base + 1] * 4 / (3 * k), 2: 2 * Y[:, base + 2]}.get(l, Y[:, base + l])
+            assert np.max(np.abs(F - spherical_jn(l, x))[m]) < 1e-8, (l, base)
+
+
+# ---------------------------------------------------------------- P3 superhorizon
+def test_superhorizon_adiabatic_mode(tab12):
+    """For k tau << 1 the adiabatic growing mode keeps eta constant to
+    O((k tau)^2) across equality, with delta_gamma/delta_c = 4/3 and
+    delta_b = delta_c (Ma & Bertschinger 1995, eq. 96)."""
+    t = tab12
+    N = O.state_size(t.prec, 0)
+    for k in (1e-6, 5e-7):
+        lout = np.linspace(t.lna_tc + 0.01, 0.0, 80)
+        r = O.perturb_one(t, k, t.lna_tc, lout, want_y=True, rtol=1e-10, atol=1e-14, prec_over={"max_steps": 100000})
+        y = r["y"]
+        kt2 = (k * np.array([_tau(t, l) for l in lout])) ** 2
+        dev = 1.0 - y[:, N - 1]
+        assert np.all(np.abs(dev) <= 0.05 * kt2 + 1e-9)
+        # radiation era: eta = 1 - (5 + 4 R_nu)/(12 (15 + 4 R_nu)) (k tau)^2
+        Rn = t.bg.R_nu
+        c_rd = (5 + 4 * Rn) / (12 * (15 + 4 * Rn))
+        assert abs(dev[0] / (c_rd * kt2[0]) - 1) < 0.2
+        j = int(np.argmin(np.abs(lout + math.log(1001))))
+        assert abs(y[j, 3] / y[j, 0] - 4 / 3) < 1e-7
+        assert abs(y[j, 1] / y[j, 0] - 1) < 1e-7
+
+
+# ---------------------------------------------------------------- P4 tight coupling
+def test_tight_coupling_slip(tab12):
+    """In tight coupling the photon-baryon slip (theta_b - theta_g)/theta_g is
+    proportional to Hc tau_c / R (R = 4 rho_g/3 rho_b), and halves when the
+    Thomson rate doubles."""
+    t = tab12
+    k = 0.05
+    lout = np.linspace(-12.5, -9.5, 31)
+    slips = []
+    for thom in (1.0, 2.0):
+        r = O.perturb_one(t, k, -13.0, lout, want_y=True, rtol=1e-10, atol=1e-16,
+                          prec_over={"max_steps": 100000, "thomson_scale": thom})
+        y = r["y"]
+        slips.append((y[:, 2] - y[:, 4]) / y[:, 4])
+    a = np.exp(lout)
+    R = 4 * t.bg.rt_g0 / (3 * t.bg.rt_b0) / a
+    htc = np.array([t.bg.Hc(math.exp(l)) / B.eval_thermo(t, l)[0] for l in lout])
+    p = np.polyfit(np.log(htc / R), np.log(np.abs(slips[0])), 1)
+    assert abs(p[0] - 1) < 0.05
+    ratio = slips[1][:10] / slips[0][:10]
+    assert np.all(np.abs(ratio - 0.5) < 0.01)
+
+
+# ---------------------------------------------------------------- P5 alpha'
+def test_alpha_prime_closed_form(tab12):
+    """alpha' from the traceless Einstein equation equals the derivative of
+    alpha = Hc (h' + 6 eta')/(2k^2) along the solution."""
+    t = tab12
+    lout = np.linspace(-7.0, -0.5, 3001)
+    r = O.perturb_one(t, 0.01, -10.0, lout, want_diag=True, rtol=1e-10, atol=1e-14, prec_over={"max_steps": 100000})
+    assert r["status"] == 0
+    al, alp = r["diag"][:, 2], r["diag"][:, 3]
+    fd = np.gradient(al, lout)
+    assert np.max(np.abs(fd[5:-5] - alp[5:-5])) < 1e-4 * np.max(np.abs(alp))
+
+
+# ---------------------------------------------------------------- P6 brute force
+@pytest.mark.parametrize("k", [1e-5, 1e-4, 1e-3])
+def test_esdirk_matches_brute_force_rk4(tab12, k):
+    """The ESDIRK stepper at rtol 1e-11 against classical RK4 with a step far
+    below every time scale (h <= 5e-4 and h |lambda| <= 1/4), compared at the
+    ESDIRK's own accepted step points (no interpolation involved)."""
+    t = tab12
+    e = O.perturb_one(t, k, t.lna_tc, t.lna_src, rtol=1e-11, atol=1e-15, prec_over={"max_steps": 200000},
+                      acc_cap=100000)
+    acc = e["accepted_lna"][::7]
+    e2 = O.perturb_one(t, k, t.lna_tc, acc, rtol=1e-11, atol=1e-15, prec_over={"max_steps": 200000}, want_y=True)
+    rb = O.rk4_one(t, k, t.lna_tc, acc, h_max=5e-4, c_stab=0.25, want_y=True)
+    sc = np.max(np.abs(rb["y"]), axis=0)
+    big = sc > 1e-8 * sc.max()
+    err = np.abs(e2["y"] - rb["y"])[:, big] / sc[big]
+    assert np.max(err) < 1e-7
+    # the sources through the dense output agree to the interpolation level
+    rs = O.rk4_one(t, k, t.lna_tc, t.lna_src, h_max=5e-4, c_stab=0.25)
+    for i in range(3):
+        assert np.max(np.abs(rs["S"][i] - e["S"][i])) < 5e-6 * np.max(np.abs(rs["S"][i]))
+
+
+def test_esdirk_order_and_step_control(tab12):
+    """Global error falls with rtol roughly like rtol (tolerance
+    proportionality) and the step count grows like rtol^-1/4 or slower."""
+    t = tab12
+    k = 0.02
+    ref = O.perturb_one(t, k, -10.0, t.lna_src, rtol=1e-11, atol=1e-15, prec_over={"max_steps": 200000})
+    errs, steps = [], []
+    for rt in (1e-5, 1e-7):
+        r = O.perturb_one(t, k, -10.0, t.lna_src, rtol=rt, atol=rt * 1e-4, prec_over={"max_steps": 200000})
+        errs.append(np.max(np.abs(r["S"][0] - ref["S"][0])) / np.max(np.abs(ref["S"][0])))
+        steps.append(r["nsteps"])
+    assert errs[1] < errs[0] / 10
+    assert steps[1] < steps[0] * 100 ** 0.3
+
+
+# ---------------------------------------------------------------- P7 Sachs-Wolfe
+def test_sachs_wolfe_plateau():
+    """n_s = 1: l(l+1) C_l/(2 pi A_s) approaches 1/25 on large scales
+    (Sachs-Wolfe), within the effects of finite recombination, early and late
+    ISW (15% with all terms for 10 <= l <= 20; 40% with the SW group alone)."""
+    c = W.fiducial()
+    c["N_nu_massless"] = 3.0
+    c["n_s"] = 1.0
+    k = np.concatenate([np.geomspace(1e-6, 1e-4, 40, endpoint=False), np.linspace(1e-4, 4e-3, 300)])
+    l = np.arange(21)
+    r = O.solve(c, W.prec_for(12, 0, 12), k, 400, 20, False)
+    v = 25 * l * (l + 1) * r["Cl"][0] / (2 * math.pi * c["A_s"])
+    assert np.all(np.abs(v[10:21] - 1) < 0.15)
+    r = O.solve(c, W.prec_for(12, 0, 12, scale_isw=0.0, scale_dop=0.0, scale_pol=0.0), k, 400, 20, False)
+    v = 25 * l * (l + 1) * r["Cl"][0] / (2 * math.pi * c["A_s"])
+    assert np.all(np.abs(v[2:21] - 1) < 0.4)
+
+
+# ---------------------------------------------------------------- P8 spike source
+@pytest.mark.parametrize("ns", [1.0, 0.965])
+def test_spike_source_closed_form(tab12, ns):
+    """A unit-weight spike of S_T0 at one output time gives Delta_l(k) =
+    j_l(k chi*), and C_l = 4 pi int dk/k P(k) j_l^2(k chi*) has the closed form
+    4 pi A_s (k_p chi*)^(1-n_s) 2^(n_s-4) pi Gamma(3-n_s) Gamma(l+(n_s-1)/2)
+    / (Gamma((4-n_s)/2)^2 Gamma(l+(5-n_s)/2)); for n_s = 1, 2 pi A_s/(l(l+1))."""
+    t = tab12
+    j = 30
+    chis = t.chi_src[j]
+    kk = np.linspace(1e-7, 2000 / chis, 40000)
+    S = np.zeros((len(kk), 3, len(t.chi_src)))
+    S[:, 0, j] = 1.0 / t.w_src[j]
+    DT, DE = O.los(t, S, 20, False, k=kk)
+    C = O.cl(kk, DT, DE, 20, False, 2e-9, ns, 0.05)
+    L = np.arange(21)
+    I = 2 ** (ns - 4) * math.pi * np.exp(gammaln(3 - ns) + gammaln(L + (ns - 1) / 2) - 2 * gammaln((4 - ns) / 2)
+                                         - gammaln(L + (5 - ns) / 2))
+    ex = 4 * math.pi * 2e-9 * (1 / 0.05) ** (ns - 1) * chis ** (1 - ns) * I
+    assert np.max(np.abs(C[0, 2:] / ex[2:] - 1)) < 1e-3
+    # Delta itself is the Bessel function (weights applied exactly once)
+    jj = 777
+    assert np.allclose(DT[:, jj], spherical_jn(np.arange(2, 21), kk[jj] * chis), rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P9/P10 Bessel
+@pytest.mark.parametrize("x", [1e-3, 0.7, 3.3, 17.0, 150.0, 999.5, 2400.0, 2520.0, 7000.0])
+def test_bessel_vs_mpmath(x):
+    import mpmath as mp
+    mp.mp.dps = 40
+    L = 2501
+    j = O.bessel(L, x)
+    up = None
+    if x > L:
+        # all orders below x: 40-digit upward recurrence is exact enough
+        X = mp.mpf(x)
+        up = [mp.sin(X) / X, mp.sin(X) / X ** 2 - mp.cos(X) / X]
+        for l in range(1, L):
+            up.append((2 * l + 1) / X * up[l] - up[l - 1])
+    for l in sorted(set([0, 1, 2, 3, 10, 100, 1000, 2000, 2400, 2450, 2500, 2501] +
+                        [int(x) - 1, int(x), int(x) + 1, int(x) + 40])):
+        if l < 0 or l > L:
+            continue
+        if up is not None:
+            ex = float(up[l])
+        else:
+            ex = float(mp.sqrt(mp.pi / (2 * mp.mpf(x))) * mp.besselj(l + mp.mpf(1) / 2, mp.mpf(x)))
+        if abs(ex) > 1e-290:
+            assert abs(j[l] - ex) <= 1e-12 * abs(ex), (l, j[l], ex)
+        else:
+            assert abs(j[l]) < 1e-280
+
+
+def test_bessel_identities():
+    for x in (0.5, 12.0, 480.0, 3000.0):
+        j = O.bessel(600, x)
+        assert abs(j[0] - math.sin(x) / x) < 1e-15
+        assert abs(j[1] - (math.sin(x) / x ** 2 - math.cos(x) / x)) < 1e-14
+        assert abs(j[2] - ((3 / x ** 2 - 1) * math.sin(x) / x - 3 * math.cos(x) / x ** 2)) < 1e-14
+        if x < 500:
+            assert abs(np.sum((2 * np.arange(601) + 1) * j ** 2) - 1) < 1e-12
+        assert np.allclose(j[:200], spherical_jn(np.arange(200), x), rtol=1e-10, atol=1e-300)
+    j0 = O.bessel(10, 0.0)
+    assert j0[0] == 1.0 and np.all(j0[1:] == 0.0)
+
+
+def test_los_x_zero_limits(tab12):
+    """x = 0 (tau = tau_0): j_l = j' = 0, (3j''+j)/2 = delta_l2/5,
+    j_l/x^2 = delta_l2/15, and c_2 = sqrt(3 4! / 8 0!) = 3."""
+    t = tab12
+    n = len(t.chi_src)
+    chi = np.zeros(n)
+    w = np.zeros(n)
+    w[-1] = 1.0
+    S = np.zeros((1, 3, n))
+    S[0, 2, -1] = 1.0
+    DT, DE = O.los(t, S, 6, True, k=np.array([0.1]), chi=chi, w=w, s_pol=1.0)
+    assert abs(DT[0, 0] - 0.2) < 1e-15 and np.all(DT[1:, 0] == 0)
+    assert abs(DE[0, 0] - 3 * math.sqrt(6) / 15) < 1e-15 and np.all(DE[1:, 0] == 0)
+
+
+def test_los_matches_direct_sum(tab12):
+    """Delta_T and Delta_E against a direct sum with scipy's spherical_jn and
+    its derivative (same trapezoid weights)."""
+    t = tab12
+    rng = np.random.Generator(np.random.PCG64(3))
+    n = len(t.chi_src)
+    k = np.array([0.003, 0.02, 0.07])
+    S = rng.standard_normal((3, 3, n))
+    DT, DE = O.los(t, S, 30, True, k=k, s_pol=0.7)
+    for ik, kk in enumerate(k):
+        x = kk * t.chi_src
+        for l in (2, 5, 17, 30):
+            xs = np.where(x > 0, x, 1.0)
+            j = spherical_jn(l, x)
+            jp = spherical_jn(l, x, derivative=True)
+            jpp = -2 * jp / xs + (l * (l + 1) / xs ** 2 - 1) * j
+            r2 = np.where(x > 0, 0.5 * (3 * jpp + j), 0.2 if l == 2 else 0.0)
+            je = np.where(x > 0, j / xs ** 2, 1 / 15 if l == 2 else 0.0)
+            T = np.sum(t.w_src * (S[ik, 0] * j + S[ik, 1] * jp + 0.7 * S[ik, 2] * r2))
+            cl = math.sqrt(3 * (l + 2) * (l + 1) * l * (l - 1) / 8)
+            E = cl * np.sum(t.w_src * math.sqrt(6) * S[ik, 2] * je)
+            assert abs(DT[l - 2, ik] - T) < 1e-10 * np.sum(np.abs(t.w_src * S[ik, 0])) + 1e-14
+            assert abs(DE[l - 2, ik] - E) < 1e-10 * abs(cl) * np.sum(np.abs(t.w_src * S[ik, 2])) + 1e-14
+
+
+def test_physical_spectrum_shape():
+    """Sanity of the whole oracle on a fine k grid: first acoustic peak of
+    D_l^TT near l = 220 at 5000-6500 uK^2; TE positive near l = 300; EE
+    reionisation bump at l = 2 (loose, unpinned accuracy)."""
+    c = W.fiducial()
+    c["N_nu_massless"] = 3.0
+    k = np.linspace(2e-5, 0.04, 700)
+    r = O.solve(c, W.prec_for(12, 8, 12, max_steps=8000), k, 600, 320, True)
+    l = np.arange(321)
+    D = l * (l + 1) * r["Cl"] / (2 * math.pi) * 2.7255e6 ** 2
+    lp = 150 + int(np.argmax(D[0, 150:320]))
+    assert 190 < lp < 250 and 5000 < D[0, lp] < 6500
+    assert D[1, 300] > 50
+    assert D[2, 2] > D[2, 8]
