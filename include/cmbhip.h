@@ -1,0 +1,171 @@
+/*
+ * cmbhip: FP64 hot path of a linear Einstein-Boltzmann CMB solver on AMD
+ * Instinct MI355X (gfx950), after arXiv 2602.15104 (ABCMB).
+ *
+ * The calls follow the paper's problem statement (App. A.2): cosmological
+ * parameters, static precision options, a wavenumber grid and ell_max in;
+ * source functions, transfer functions and C_ell^{TT,TE,EE} out.
+ *
+ * Threading: every call is thread-safe with respect to distinct handles.
+ * cmb_last_error() is thread-local.  No exception crosses this boundary; each
+ * int-returning call returns CMB_OK (0) or one of the CMB_E_* codes below.
+ */
+#ifndef CMBHIP_H
+#define CMBHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMB_ABI_VERSION 1
+
+/* call-level return codes */
+enum {
+    CMB_OK = 0,
+    CMB_E_INVALID = 1,        /* NULL pointer, NaN/non-positive parameter, bad size, unsorted k */
+    CMB_E_CONFLICT = 2,       /* Neff and N_nu_massless both given, or tau_reio and z_reio both
+                                 given (Sec. 2.4; App. A.2, tau_reion) */
+    CMB_E_NEG_NMASSLESS = 3,  /* Neff too small for the other species (Sec. 2.4) */
+    CMB_E_ROOT = 4,           /* a root find was not bracketed (z_reion from tau_reio, start times) */
+    CMB_E_DEVICE = 5,         /* HIP runtime error */
+    CMB_E_NOMEM = 6,          /* device memory budget of the context exceeded */
+    CMB_E_UNSUPPORTED = 7     /* option combination not built into this library */
+};
+
+/* per-mode integration status written to the status array by the solver */
+enum {
+    CMB_K_OK = 0,
+    CMB_K_MAX_STEPS = 1,      /* max_steps attempted steps before ln a = 0 */
+    CMB_K_NONFINITE = 2,      /* NaN/Inf in the error estimate */
+    CMB_K_STEP_UNDERFLOW = 3  /* step size fell below 1e-12 in ln a */
+};
+
+/* Cosmological parameters (App. A.2, "Cosmological parameters").  NaN means
+ * "not given" for tau_reio/z_reio (exactly one must be given) and for
+ * Neff/N_nu_massless (at most one; neither means N_nu_massless = 3). */
+typedef struct cmb_cosmo {
+    double h, omega_b, omega_cdm, A_s, n_s;
+    double tau_reio, z_reio;
+    double Delta_z_reio, z_reio_He, Delta_z_reio_He, exp_reio;
+    double YHe, TCMB0;               /* TCMB0 in eV */
+    double Neff, N_nu_massless, T_nu_massless;
+    double N_nu_massive, m_nu_massive, T_nu_massive; /* m in eV */
+} cmb_cosmo;
+
+/* Static options (App. A.2, "Initialization options").  ell_pol = 0 means no
+ * polarisation hierarchy (temperature only: no E, Pi = 2 sigma_gamma). */
+typedef struct cmb_prec {
+    int ell_gamma, ell_pol, ell_nu, n_q, ell_ncdm;
+    int max_steps, n_tab;
+    double rtol_small, rtol_large, atol_small, atol_large, k_split;
+    double R_tc, R_large, k_pivot;
+    double pcoeff, icoeff, dcoeff;
+    double scale_sw, scale_isw, scale_dop, scale_pol;
+    double gravity_scale, thomson_scale; /* test knobs: 1 = physical */
+} cmb_prec;
+
+/* ABI version integer (CMB_ABI_VERSION). */
+int cmb_abi_version(void);
+
+/* Fill *c and *p with the paper's defaults (App. A.2).  Either may be NULL
+ * only if the other is not; both NULL -> CMB_E_INVALID. */
+int cmb_defaults(cmb_cosmo *c, cmb_prec *p);
+
+/* Message for the last failing call on this thread ("" if none).  The
+ * pointer stays valid until the next call on the same thread. */
+const char *cmb_last_error(void);
+
+/* ---------------------------------------------------------------- tables */
+/* Host-built background, recombination and thermodynamics tables for one
+ * cosmology (App. A.2 derived parameters, App. B.1 recombination, App. B.2
+ * reionisation, App. B.4 kappa and visibility, App. C species), the start
+ * time of every mode (App. A.2, eqs. k_start_small/k_start_large) and the
+ * output-time grid with its line-of-sight weights.  CPU only.
+ *   k:     n_k >= 1 wavenumbers [Mpc^-1], positive, strictly increasing
+ *          (copied; the caller keeps ownership of its array)
+ *   n_tau: >= 3 output times
+ * On success *out is a library-owned immutable handle, shareable between
+ * threads, released by cmb_tables_destroy.  Errors: CMB_E_INVALID,
+ * CMB_E_CONFLICT, CMB_E_NEG_NMASSLESS, CMB_E_ROOT, CMB_E_UNSUPPORTED. */
+typedef struct cmb_tables cmb_tables;
+int cmb_tables_build(const cmb_cosmo *c, const cmb_prec *p, const double *k, int n_k, int n_tau,
+                     cmb_tables **out);
+void cmb_tables_destroy(cmb_tables *t);
+
+/* Read-only view of a table (no ownership transfer; valid while t lives).
+ * Knot arrays have n_tab + 1 entries on the uniform grid
+ * ln a_j = L0 + j * dlna (j < n_tab), ln a_n_tab = 0.  Spline columns are
+ * natural cubic splines given by knot values and second derivatives. */
+typedef struct cmb_table_view {
+    int n_k, n_tau, n_tab, n_q;
+    double L0, dlna, tau0, z_reio, lna_tc, N_massless, Neff, R_nu;
+    const double *k, *lna_start;                      /* [n_k] */
+    const double *lna_src, *tau_src, *chi_src, *w_src; /* [n_tau] */
+    const double *xe, *tm;                            /* [n_tab+1] */
+    const double *ln_dk, *kappa, *ln_cs2, *ln_tau;    /* [n_tab+1] knot values */
+    const double *M_ln_dk, *M_kappa, *M_ln_cs2, *M_ln_tau; /* [n_tab+1] second derivatives */
+    const double *q, *W;                              /* [n_q] momentum rule */
+    double rt_g0, rt_ur0, rt_c0, rt_b0, rt_L, pref_ncdm, m_over_T, H0;
+} cmb_table_view;
+int cmb_tables_export(const cmb_tables *t, cmb_table_view *out);
+
+/* ---------------------------------------------------------------- device */
+/* A context binds one HIP device and owns the device workspace (table
+ * copies, integrator scratch), grown on demand up to hbm_budget_bytes
+ * (0 = 16 GiB).  One context per host thread.  Errors: CMB_E_DEVICE,
+ * CMB_E_INVALID. */
+typedef struct cmb_ctx cmb_ctx;
+int cmb_ctx_create(int device, size_t hbm_budget_bytes, cmb_ctx **out);
+void cmb_ctx_destroy(cmb_ctx *ctx);
+
+/* Device bytes cmb_solve needs for this batch (tables + integrator scratch),
+ * excluding the caller's output buffers.  Used for admission by footprint. */
+size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo);
+
+/*
+ * Perturbations and sources (App. B.3, App. C, App. B.4 eq. source_functions)
+ * for n_cosmo cosmologies that share n_k, n_tau and the hierarchy sizes.
+ *   d_S:      device, [n_cosmo][n_k][3][n_tau] doubles: S_T0, S_T1, S_T2
+ *             (S_E = sqrt(6) S_T2), zero before each mode's start time;
+ *   d_status: device, [n_cosmo][n_k] int32 (CMB_K_*);
+ *   d_nsteps: device, [n_cosmo][n_k] int32 attempted steps (may be NULL).
+ * Asynchronous on hip_stream (a hipStream_t; NULL = default stream).  Buffers
+ * are caller-owned and must stay valid until the stream reaches this work.
+ */
+int cmb_perturb(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                int32_t *d_nsteps, void *hip_stream);
+
+/*
+ * Line-of-sight projection (App. B.4, transfer integrals; trapezoid in ln a):
+ * from sources d_S (layout above, any values) to
+ *   d_Delta: device, [n_cosmo][2][ell_max-1][n_k] doubles (Delta_T, Delta_E
+ *            for ell = 2..ell_max, k fastest); the E plane is written as 0
+ *            when the tables have no polarisation hierarchy.
+ * Bessel functions by recurrence on the GPU; ell_max in [2, 10000].
+ */
+int cmb_los(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
+            double *d_Delta, void *hip_stream);
+
+/*
+ * k quadrature (eq. c_ell_def, eq. PK_pivot; trapezoid in k on the mode grid):
+ *   d_Cl: device, [n_cosmo][3][ell_max+1] doubles (TT, TE, EE; dimensionless;
+ *         entries ell < 2 are 0).
+ */
+int cmb_cl(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta,
+           double *d_Cl, void *hip_stream);
+
+/*
+ * The whole path: cmb_perturb, cmb_los, cmb_cl in order on hip_stream.
+ * d_S and d_Delta may be NULL (then context scratch is used).  Cosmologies in
+ * one call must share n_k, n_tau and the static options' hierarchy sizes.
+ */
+int cmb_solve(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_S, double *d_Delta,
+              double *d_Cl, int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMBHIP_H */

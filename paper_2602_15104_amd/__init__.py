@@ -1,0 +1,264 @@
+"""Python binding of libcmbhip (FP64 CMB Boltzmann hot path on MI355X).
+
+Argument marshalling only: every step of the path runs in the C++ host table
+builder and the HIP kernels of ``libcmbhip.so``.  PyTorch provides device
+memory and the current HIP stream.  The library is loaded from this folder;
+if it is missing the import fails loudly (build it with
+``python -m paper_2602_15104_amd.build``).
+
+Names follow include/cmbhip.h:
+    defaults(), build_tables(), Tables.export(), Context,
+    Context.perturb(), Context.los(), Context.cl(), Context.solve(),
+and the convenience ``solve_batch`` that allocates torch outputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmbhip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libcmbhip.so not found at {LIB_PATH}; build it with `python -m paper_2602_15104_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CMB_OK = 0
+ERRORS = {1: "CMB_E_INVALID", 2: "CMB_E_CONFLICT", 3: "CMB_E_NEG_NMASSLESS", 4: "CMB_E_ROOT", 5: "CMB_E_DEVICE",
+          6: "CMB_E_NOMEM", 7: "CMB_E_UNSUPPORTED"}
+MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
+
+# exported symbols (kept in step with include/cmbhip.h; a CPU test checks this)
+EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
+           "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
+           "cmb_los", "cmb_cl", "cmb_solve"]
+
+
+class CmbError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.cmb_last_error().decode()
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class CCosmo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "h", "omega_b", "omega_cdm", "A_s", "n_s", "tau_reio", "z_reio", "Delta_z_reio", "z_reio_He",
+        "Delta_z_reio_He", "exp_reio", "YHe", "TCMB0", "Neff", "N_nu_massless", "T_nu_massless", "N_nu_massive",
+        "m_nu_massive", "T_nu_massive")]
+
+
+class CPrec(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int) for n in ("ell_gamma", "ell_pol", "ell_nu", "n_q", "ell_ncdm", "max_steps",
+                                             "n_tab")] +
+                [(n, ctypes.c_double) for n in ("rtol_small", "rtol_large", "atol_small", "atol_large", "k_split",
+                                                "R_tc", "R_large", "k_pivot", "pcoeff", "icoeff", "dcoeff",
+                                                "scale_sw", "scale_isw", "scale_dop", "scale_pol", "gravity_scale",
+                                                "thomson_scale")])
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class CTableView(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int) for n in ("n_k", "n_tau", "n_tab", "n_q")] +
+                [(n, ctypes.c_double) for n in ("L0", "dlna", "tau0", "z_reio", "lna_tc", "N_massless", "Neff",
+                                                "R_nu")] +
+                [(n, _dp) for n in ("k", "lna_start", "lna_src", "tau_src", "chi_src", "w_src", "xe", "tm", "ln_dk",
+                                    "kappa", "ln_cs2", "ln_tau", "M_ln_dk", "M_kappa", "M_ln_cs2", "M_ln_tau", "q",
+                                    "W")] +
+                [(n, ctypes.c_double) for n in ("rt_g0", "rt_ur0", "rt_c0", "rt_b0", "rt_L", "pref_ncdm", "m_over_T",
+                                                "H0")])
+
+
+_vp = ctypes.c_void_p
+_lib.cmb_abi_version.restype = ctypes.c_int
+_lib.cmb_defaults.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec)]
+_lib.cmb_last_error.restype = ctypes.c_char_p
+_lib.cmb_tables_build.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec), _dp, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(_vp)]
+_lib.cmb_tables_destroy.argtypes = [_vp]
+_lib.cmb_tables_destroy.restype = None
+_lib.cmb_tables_export.argtypes = [_vp, ctypes.POINTER(CTableView)]
+_lib.cmb_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]
+_lib.cmb_ctx_destroy.argtypes = [_vp]
+_lib.cmb_ctx_destroy.restype = None
+_lib.cmb_solve_workspace_bytes.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+_lib.cmb_solve_workspace_bytes.restype = ctypes.c_size_t
+_lib.cmb_perturb.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp]
+_lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+
+
+def _check(rc: int, where: str):
+    if rc != CMB_OK:
+        raise CmbError(rc, where)
+
+
+def abi_version() -> int:
+    return _lib.cmb_abi_version()
+
+
+def defaults():
+    """(cosmo dict, prec dict) with the paper's defaults (App. A.2)."""
+    c, p = CCosmo(), CPrec()
+    _check(_lib.cmb_defaults(ctypes.byref(c), ctypes.byref(p)), "cmb_defaults")
+    return {n: getattr(c, n) for n, _ in CCosmo._fields_}, {n: getattr(p, n) for n, _ in CPrec._fields_}
+
+
+def _cosmo_struct(c: dict) -> CCosmo:
+    d, _ = defaults()
+    d.update({k: v for k, v in c.items() if k in d})
+    # map workload key names
+    if "z_reio" in c:
+        d["z_reio"] = c["z_reio"]
+    s = CCosmo()
+    for n, _ in CCosmo._fields_:
+        setattr(s, n, float(d[n]))
+    return s
+
+
+def _prec_struct(p: dict) -> CPrec:
+    _, d = defaults()
+    d.update({k: v for k, v in p.items() if k in d})
+    s = CPrec()
+    for n, t in CPrec._fields_:
+        setattr(s, n, int(d[n]) if t is ctypes.c_int else float(d[n]))
+    return s
+
+
+class Tables:
+    """Host tables of one cosmology (cmb_tables_build)."""
+
+    def __init__(self, cosmo: dict, prec: dict, k, n_tau: int):
+        self.cosmo = dict(cosmo)
+        self.prec = dict(prec)
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        self.k = k
+        self.n_tau = int(n_tau)
+        h = _vp()
+        cs, ps = _cosmo_struct(cosmo), _prec_struct(prec)
+        _check(_lib.cmb_tables_build(ctypes.byref(cs), ctypes.byref(ps), k.ctypes.data_as(_dp), len(k), int(n_tau),
+                                     ctypes.byref(h)), "cmb_tables_build")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self) -> dict:
+        v = CTableView()
+        _check(_lib.cmb_tables_export(self._h, ctypes.byref(v)), "cmb_tables_export")
+        n1 = v.n_tab + 1
+
+        def arr(ptr, n):
+            return np.ctypeslib.as_array(ptr, shape=(n,)).copy() if n else np.zeros(0)
+
+        out = {f: getattr(v, f) for f in ("n_k", "n_tau", "n_tab", "n_q", "L0", "dlna", "tau0", "z_reio", "lna_tc",
+                                          "N_massless", "Neff", "R_nu", "rt_g0", "rt_ur0", "rt_c0", "rt_b0", "rt_L",
+                                          "pref_ncdm", "m_over_T", "H0")}
+        for f in ("k", "lna_start"):
+            out[f] = arr(getattr(v, f), v.n_k)
+        for f in ("lna_src", "tau_src", "chi_src", "w_src"):
+            out[f] = arr(getattr(v, f), v.n_tau)
+        for f in ("xe", "tm", "ln_dk", "kappa", "ln_cs2", "ln_tau", "M_ln_dk", "M_kappa", "M_ln_cs2", "M_ln_tau"):
+            out[f] = arr(getattr(v, f), n1)
+        for f in ("q", "W"):
+            out[f] = arr(getattr(v, f), v.n_q)
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.cmb_tables_destroy(h)
+            self._h = None
+
+
+def build_tables(cosmo: dict, prec: dict, k, n_tau: int) -> Tables:
+    return Tables(cosmo, prec, k, n_tau)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _handles(tabs):
+    arr = (_vp * len(tabs))(*[t.handle for t in tabs])
+    return arr
+
+
+class Context:
+    """Device context (cmb_ctx_create): one HIP device, a workspace budget."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = _vp()
+        _check(_lib.cmb_ctx_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)), "cmb_ctx_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.cmb_ctx_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def perturb(self, tabs, S, status, nsteps=None, stream=None):
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _stream(stream)),
+               "cmb_perturb")
+
+    def los(self, tabs, ell_max, S, Delta, stream=None):
+        hs = _handles(tabs)
+        _check(_lib.cmb_los(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _stream(stream)), "cmb_los")
+
+    def cl(self, tabs, ell_max, Delta, Cl, stream=None):
+        hs = _handles(tabs)
+        _check(_lib.cmb_cl(self._h, hs, len(tabs), int(ell_max), _ptr(Delta), _ptr(Cl), _stream(stream)), "cmb_cl")
+
+    def solve(self, tabs, ell_max, Cl, status, S=None, Delta=None, nsteps=None, stream=None):
+        hs = _handles(tabs)
+        _check(_lib.cmb_solve(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _ptr(Cl), _ptr(status),
+                              _ptr(nsteps), _stream(stream)), "cmb_solve")
+
+
+def workspace_bytes(tabs) -> int:
+    return int(_lib.cmb_solve_workspace_bytes(_handles(tabs), len(tabs)))
+
+
+def alloc_outputs(tabs, ell_max: int, device: str = "cuda:0", keep_S: bool = True, keep_Delta: bool = True):
+    """torch device tensors for one batch, laid out as include/cmbhip.h states."""
+    import torch
+    B = len(tabs)
+    n_k, n_tau = len(tabs[0].k), tabs[0].n_tau
+    out = {
+        "Cl": torch.empty((B, 3, ell_max + 1), dtype=torch.float64, device=device),
+        "status": torch.empty((B, n_k), dtype=torch.int32, device=device),
+        "nsteps": torch.empty((B, n_k), dtype=torch.int32, device=device),
+    }
+    out["S"] = torch.empty((B, n_k, 3, n_tau), dtype=torch.float64, device=device) if keep_S else None
+    out["Delta"] = torch.empty((B, 2, ell_max - 1, n_k), dtype=torch.float64, device=device) if keep_Delta else None
+    return out
+
+
+def solve_batch(ctx: Context, tabs, ell_max: int, keep_S: bool = True, keep_Delta: bool = True, stream=None):
+    """Run the whole path for a batch of tables; returns torch tensors."""
+    dev = f"cuda:{ctx.device}"
+    out = alloc_outputs(tabs, ell_max, dev, keep_S, keep_Delta)
+    ctx.solve(tabs, ell_max, out["Cl"], out["status"], S=out["S"], Delta=out["Delta"], nsteps=out["nsteps"],
+              stream=stream)
+    return out

@@ -1,0 +1,536 @@
+// C ABI of libcmbhip: argument validation, device contexts, table upload and
+// the ordering of the three stages on the caller's HIP stream.
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "cmbhip_internal.h"
+
+struct cmb_tables {
+    cmbhip::Tables t;
+};
+
+struct cmb_ctx {
+    int device = 0;
+    size_t budget = 0;
+    // device buffers (grown on demand within the budget)
+    void *tab_buf = nullptr;
+    size_t tab_cap = 0;
+    void *ws_buf = nullptr;
+    size_t ws_cap = 0;
+    void *s_buf = nullptr;
+    size_t s_cap = 0;
+    void *d_buf = nullptr;
+    size_t d_cap = 0;
+    void *st_buf = nullptr;
+    size_t st_cap = 0;
+    // host staging for uploads (pinned)
+    void *h_stage = nullptr;
+    size_t h_cap = 0;
+    // cache key of the resident tables
+    std::vector<unsigned long long> resident;
+    cmbhip::DevTab *d_tabs = nullptr;
+    std::mutex mu;
+};
+
+namespace cmbhip {
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+static std::atomic<unsigned long long> g_uid{1};
+}  // namespace cmbhip
+
+using cmbhip::set_error;
+
+static int herr(hipError_t e, const char *what) {
+    if (e == hipSuccess) return CMB_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return CMB_E_DEVICE;
+}
+
+extern "C" {
+
+int cmb_abi_version(void) { return CMB_ABI_VERSION; }
+
+const char *cmb_last_error(void) { return cmbhip::g_err.c_str(); }
+
+int cmb_defaults(cmb_cosmo *c, cmb_prec *p) {
+    if (!c && !p) {
+        set_error("cmb_defaults: both pointers NULL");
+        return CMB_E_INVALID;
+    }
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    if (c) {
+        // App. A.2 defaults
+        c->h = 0.6736;
+        c->omega_b = 0.02237;
+        c->omega_cdm = 0.120;
+        c->A_s = 2.1e-9;
+        c->n_s = 0.9649;
+        c->tau_reio = 0.05430842;
+        c->z_reio = nan;
+        c->Delta_z_reio = 0.5;
+        c->z_reio_He = 3.5;
+        c->Delta_z_reio_He = 0.5;
+        c->exp_reio = 1.5;
+        c->YHe = 0.245;
+        c->TCMB0 = 2.34865418e-4;
+        c->Neff = nan;
+        c->N_nu_massless = nan;
+        c->T_nu_massless = 0.71636856;
+        c->N_nu_massive = 0.0;
+        c->m_nu_massive = 0.06;
+        c->T_nu_massive = 0.71611;
+    }
+    if (p) {
+        p->ell_gamma = 12;
+        p->ell_pol = 10;
+        p->ell_nu = 17;
+        p->n_q = 0;
+        p->ell_ncdm = 17;
+        p->max_steps = 2048;
+        p->n_tab = 8192;
+        p->rtol_small = 1e-5;
+        p->rtol_large = 1e-4;
+        p->atol_small = 1e-10;
+        p->atol_large = 1e-6;
+        p->k_split = 1e-2;
+        p->R_tc = 1.5e-3;
+        p->R_large = 7e-2;
+        p->k_pivot = 0.05;
+        p->pcoeff = 0.25;
+        p->icoeff = 0.8;
+        p->dcoeff = 0.0;
+        p->scale_sw = p->scale_isw = p->scale_dop = p->scale_pol = 1.0;
+        p->gravity_scale = p->thomson_scale = 1.0;
+    }
+    set_error("");
+    return CMB_OK;
+}
+
+int cmb_tables_build(const cmb_cosmo *c, const cmb_prec *p, const double *k, int n_k, int n_tau, cmb_tables **out) {
+    if (!c || !p || !k || !out) {
+        set_error("cmb_tables_build: NULL argument");
+        return CMB_E_INVALID;
+    }
+    *out = nullptr;
+    cmb_tables *t = new (std::nothrow) cmb_tables;
+    if (!t) {
+        set_error("out of host memory");
+        return CMB_E_INVALID;
+    }
+    int rc;
+    try {
+        rc = cmbhip::build_tables(*c, *p, k, n_k, n_tau, t->t);
+    } catch (const std::exception &e) {
+        set_error(std::string("table build failed: ") + e.what());
+        rc = CMB_E_INVALID;
+    }
+    if (rc != CMB_OK) {
+        delete t;
+        return rc;
+    }
+    t->t.uid = cmbhip::g_uid.fetch_add(1);
+    *out = t;
+    set_error("");
+    return CMB_OK;
+}
+
+void cmb_tables_destroy(cmb_tables *t) { delete t; }
+
+int cmb_tables_export(const cmb_tables *tt, cmb_table_view *v) {
+    if (!tt || !v) {
+        set_error("cmb_tables_export: NULL argument");
+        return CMB_E_INVALID;
+    }
+    const cmbhip::Tables &t = tt->t;
+    std::memset(v, 0, sizeof(*v));
+    v->n_k = (int)t.k.size();
+    v->n_tau = (int)t.lna_src.size();
+    v->n_tab = t.n_tab;
+    v->n_q = (int)t.q.size();
+    v->L0 = t.L0;
+    v->dlna = t.dl;
+    v->tau0 = t.tau0;
+    v->z_reio = t.z_reio;
+    v->lna_tc = t.lna_tc;
+    v->N_massless = t.N_massless;
+    v->Neff = t.Neff;
+    v->R_nu = t.R_nu;
+    v->k = t.k.data();
+    v->lna_start = t.lna_start.data();
+    v->lna_src = t.lna_src.data();
+    v->tau_src = t.tau_src.data();
+    v->chi_src = t.chi_src.data();
+    v->w_src = t.w_src.data();
+    v->xe = t.xe.data();
+    v->tm = t.tm.data();
+    v->ln_dk = t.col[0].data();
+    v->kappa = t.col[1].data();
+    v->ln_cs2 = t.col[2].data();
+    v->ln_tau = t.col[3].data();
+    v->M_ln_dk = t.M[0].data();
+    v->M_kappa = t.M[1].data();
+    v->M_ln_cs2 = t.M[2].data();
+    v->M_ln_tau = t.M[3].data();
+    v->q = t.q.data();
+    v->W = t.W.data();
+    v->rt_g0 = t.rt_g0;
+    v->rt_ur0 = t.rt_ur0;
+    v->rt_c0 = t.rt_c0;
+    v->rt_b0 = t.rt_b0;
+    v->rt_L = t.rt_L;
+    v->pref_ncdm = t.pref_ncdm;
+    v->m_over_T = t.m_over_T;
+    v->H0 = t.H0;
+    return CMB_OK;
+}
+
+int cmb_ctx_create(int device, size_t budget, cmb_ctx **out) {
+    if (!out) {
+        set_error("cmb_ctx_create: NULL out");
+        return CMB_E_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        set_error("no HIP device available");
+        return CMB_E_DEVICE;
+    }
+    if (device < 0 || device >= n) {
+        set_error("device index out of range");
+        return CMB_E_INVALID;
+    }
+    cmb_ctx *c = new (std::nothrow) cmb_ctx;
+    if (!c) return CMB_E_INVALID;
+    c->device = device;
+    c->budget = budget ? budget : (size_t)16 << 30;
+    *out = c;
+    set_error("");
+    return CMB_OK;
+}
+
+void cmb_ctx_destroy(cmb_ctx *c) {
+    if (!c) return;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf}) hipFree(p);
+    if (c->h_stage) hipHostFree(c->h_stage);
+    hipSetDevice(prev);
+    delete c;
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t total_bytes(const cmb_ctx *c) { return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap; }
+
+int grow(cmb_ctx *c, void **buf, size_t *cap, size_t need, hipStream_t s) {
+    if (need <= *cap) return CMB_OK;
+    size_t newcap = need + need / 4;
+    if (total_bytes(c) - *cap + newcap > c->budget) {
+        newcap = need;
+        if (total_bytes(c) - *cap + newcap > c->budget) {
+            set_error("device memory budget of the context exceeded");
+            return CMB_E_NOMEM;
+        }
+    }
+    if (*buf) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+        hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    hipError_t e = hipMalloc(buf, newcap);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return CMB_E_NOMEM;
+    }
+    *cap = newcap;
+    return CMB_OK;
+}
+
+struct Batch {
+    int n_k = 0, n_tau = 0;
+    cmbhip::DevPrec prec{};
+    int polar = 0;
+    double s_pol = 1.0;
+};
+
+int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
+    if (!tabs || n_cosmo < 1) {
+        set_error("tables array NULL or n_cosmo < 1");
+        return CMB_E_INVALID;
+    }
+    for (int i = 0; i < n_cosmo; ++i)
+        if (!tabs[i]) {
+            set_error("NULL table in batch");
+            return CMB_E_INVALID;
+        }
+    const cmbhip::Tables &t0 = tabs[0]->t;
+    b.n_k = (int)t0.k.size();
+    b.n_tau = (int)t0.lna_src.size();
+    const cmb_prec &p = t0.prec;
+    for (int i = 1; i < n_cosmo; ++i) {
+        const cmbhip::Tables &t = tabs[i]->t;
+        const cmb_prec &q = t.prec;
+        if ((int)t.k.size() != b.n_k || (int)t.lna_src.size() != b.n_tau || q.ell_gamma != p.ell_gamma ||
+            q.ell_pol != p.ell_pol || q.ell_nu != p.ell_nu || q.n_q != p.n_q || q.max_steps != p.max_steps ||
+            q.pcoeff != p.pcoeff || q.icoeff != p.icoeff || q.dcoeff != p.dcoeff || q.scale_sw != p.scale_sw ||
+            q.scale_isw != p.scale_isw || q.scale_dop != p.scale_dop || q.scale_pol != p.scale_pol ||
+            q.gravity_scale != p.gravity_scale || q.thomson_scale != p.thomson_scale) {
+            set_error("cosmologies in one call must share n_k, n_tau and the static options");
+            return CMB_E_INVALID;
+        }
+    }
+    b.prec.lg = p.ell_gamma;
+    b.prec.lp = p.ell_pol;
+    b.prec.ln = p.ell_nu;
+    b.prec.max_steps = p.max_steps;
+    b.prec.pcoeff = p.pcoeff;
+    b.prec.icoeff = p.icoeff;
+    b.prec.dcoeff = p.dcoeff;
+    b.prec.sw = p.scale_sw;
+    b.prec.isw = p.scale_isw;
+    b.prec.dop = p.scale_dop;
+    b.prec.pol = p.scale_pol;
+    b.prec.grav = p.gravity_scale;
+    b.prec.thom = p.thomson_scale;
+    b.polar = p.ell_pol > 0;
+    b.s_pol = p.scale_pol;
+    return CMB_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t table_bytes(const cmbhip::Tables &t) {
+    size_t n = t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size();
+    return align256(n * sizeof(double));
+}
+
+// Upload the batch's tables (skipped when the same tables are resident).
+int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s) {
+    std::vector<unsigned long long> key(n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) key[i] = tabs[i]->t.uid;
+    if (key == c->resident) return CMB_OK;
+    size_t bytes = align256(sizeof(cmbhip::DevTab) * n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) bytes += table_bytes(tabs[i]->t);
+    int rc = grow(c, &c->tab_buf, &c->tab_cap, bytes, s);
+    if (rc) return rc;
+    if (bytes > c->h_cap) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+        if (c->h_stage) hipHostFree(c->h_stage);
+        c->h_stage = nullptr;
+        c->h_cap = 0;
+        e = hipHostMalloc(&c->h_stage, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return herr(e, "hipHostMalloc");
+        c->h_cap = bytes;
+    } else {
+        // the staging buffer may still be read by a previous upload
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    }
+    char *h = (char *)c->h_stage;
+    char *d = (char *)c->tab_buf;
+    size_t off = align256(sizeof(cmbhip::DevTab) * n_cosmo);
+    cmbhip::DevTab *dt = (cmbhip::DevTab *)h;
+    for (int i = 0; i < n_cosmo; ++i) {
+        const cmbhip::Tables &t = tabs[i]->t;
+        double *hp = (double *)(h + off);
+        const double *dp = (const double *)(d + off);
+        size_t o = 0;
+        auto put = [&](const std::vector<double> &v) {
+            std::memcpy(hp + o, v.data(), v.size() * sizeof(double));
+            const double *r = dp + o;
+            o += v.size();
+            return r;
+        };
+        cmbhip::DevTab &x = dt[i];
+        std::memset(&x, 0, sizeof(x));
+        x.poly = put(t.poly);
+        x.k = put(t.k);
+        x.lna_start = put(t.lna_start);
+        x.lna_src = put(t.lna_src);
+        x.chi_src = put(t.chi_src);
+        x.w_src = put(t.w_src);
+        x.L0 = t.L0;
+        x.inv_dl = 1.0 / t.dl;
+        x.n_tab = t.n_tab;
+        x.n_k = (int)t.k.size();
+        x.n_tau = (int)t.lna_src.size();
+        x.tau0 = t.tau0;
+        x.R_nu = t.R_nu;
+        x.rt_g0 = t.rt_g0;
+        x.rt_ur0 = t.rt_ur0;
+        x.rt_c0 = t.rt_c0;
+        x.rt_b0 = t.rt_b0;
+        x.rt_L = t.rt_L;
+        x.A_s = t.cosmo.A_s;
+        x.n_s = t.cosmo.n_s;
+        x.k_pivot = t.prec.k_pivot;
+        x.rtol_small = t.prec.rtol_small;
+        x.rtol_large = t.prec.rtol_large;
+        x.atol_small = t.prec.atol_small;
+        x.atol_large = t.prec.atol_large;
+        x.k_split = t.prec.k_split;
+        off += table_bytes(t);
+    }
+    hipError_t e = hipMemcpyAsync(c->tab_buf, c->h_stage, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return herr(e, "hipMemcpyAsync (tables)");
+    c->d_tabs = (cmbhip::DevTab *)c->tab_buf;
+    c->resident = key;
+    return CMB_OK;
+}
+
+struct DeviceGuard {
+    int prev = 0;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (ok) hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo) {
+    Batch b;
+    if (check_batch(tabs, n_cosmo, b)) return 0;
+    size_t bytes = align256(sizeof(cmbhip::DevTab) * n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) bytes += table_bytes(tabs[i]->t);
+    bytes += cmbhip::perturb_ws_doubles(n_cosmo, b.n_k, b.prec) * sizeof(double);
+    return bytes;
+}
+
+int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                int32_t *d_nsteps, void *stream) {
+    if (!c || !d_S || !d_status) {
+        set_error("cmb_perturb: NULL argument");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    size_t need = cmbhip::perturb_ws_doubles(n_cosmo, b.n_k, b.prec) * sizeof(double);
+    rc = grow(c, &c->ws_buf, &c->ws_cap, need, s);
+    if (rc) return rc;
+    int32_t *ns = d_nsteps;
+    if (!ns) {
+        rc = grow(c, &c->st_buf, &c->st_cap, sizeof(int32_t) * (size_t)n_cosmo * b.n_k, s);
+        if (rc) return rc;
+        ns = (int32_t *)c->st_buf;
+    }
+    rc = cmbhip::launch_perturb(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, (double *)c->ws_buf, d_S, d_status, ns,
+                                stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_los(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S, double *d_Delta,
+            void *stream) {
+    if (!c || !d_S || !d_Delta) {
+        set_error("cmb_los: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    if (b.n_tau > cmbhip::los_max_tau()) {
+        set_error("n_tau above the line-of-sight kernel's limit");
+        return CMB_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    rc = upload(c, tabs, n_cosmo, (hipStream_t)stream);
+    if (rc) return rc;
+    rc = cmbhip::launch_los(c->d_tabs, n_cosmo, b.n_k, b.n_tau, ell_max, b.polar, b.s_pol, d_S, d_Delta, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_cl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta, double *d_Cl,
+           void *stream) {
+    if (!c || !d_Delta || !d_Cl) {
+        set_error("cmb_cl: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    rc = upload(c, tabs, n_cosmo, (hipStream_t)stream);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl(c->d_tabs, n_cosmo, b.n_k, ell_max, d_Delta, d_Cl, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_solve(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_S, double *d_Delta,
+              double *d_Cl, int32_t *d_status, int32_t *d_nsteps, void *stream) {
+    if (!c || !d_Cl || !d_status) {
+        set_error("cmb_solve: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_S) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        DeviceGuard g(c->device);
+        rc = grow(c, &c->s_buf, &c->s_cap, sizeof(double) * (size_t)n_cosmo * b.n_k * 3 * b.n_tau, s);
+        if (rc) return rc;
+        d_S = (double *)c->s_buf;
+    }
+    if (!d_Delta) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        DeviceGuard g(c->device);
+        rc = grow(c, &c->d_buf, &c->d_cap, sizeof(double) * (size_t)n_cosmo * 2 * (ell_max - 1) * b.n_k, s);
+        if (rc) return rc;
+        d_Delta = (double *)c->d_buf;
+    }
+    rc = cmb_perturb(c, tabs, n_cosmo, d_S, d_status, d_nsteps, stream);
+    if (rc) return rc;
+    rc = cmb_los(c, tabs, n_cosmo, ell_max, d_S, d_Delta, stream);
+    if (rc) return rc;
+    return cmb_cl(c, tabs, n_cosmo, ell_max, d_Delta, d_Cl, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal types shared by the host table builder, the C ABI and the kernel
+// launchers of libcmbhip.  Not part of the public interface.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/cmbhip.h"
+
+namespace cmbhip {
+
+// Host tables of one cosmology (see tables.cpp).
+struct Tables {
+    cmb_cosmo cosmo{};
+    cmb_prec prec{};
+    std::vector<double> k, lna_start;
+    int n_tab = 0;
+    double L0 = 0, dl = 0, tau0 = 0, z_reio = 0, lna_tc = 0, N_massless = 0, Neff = 0, R_nu = 0;
+    double rt_g0 = 0, rt_ur0 = 0, rt_c0 = 0, rt_b0 = 0, rt_L = 0, pref_ncdm = 0, m_over_T = 0, H0 = 0;
+    std::vector<double> q, W;
+    std::vector<double> xe, tm;
+    std::vector<double> col[4], M[4];  // ln dk, kappa, ln cs2, ln tau: knot values, second derivatives
+    std::vector<double> poly;          // [n_tab][4 columns][4 coefficients]
+    std::vector<double> lna_src, tau_src, chi_src, w_src;
+    unsigned long long uid = 0;
+    double eval(int column, double lna) const;
+};
+
+int build_tables(const cmb_cosmo &c, const cmb_prec &p, const double *k, int n_k, int n_tau, Tables &T);
+void set_error(const std::string &msg);
+
+// Per-cosmology view the kernels read (device pointers into the context's
+// table buffer, plus scalars).
+struct DevTab {
+    const double *poly;       // [n_tab][16]
+    const double *k;          // [n_k]
+    const double *lna_start;  // [n_k]
+    const double *lna_src;    // [n_tau]
+    const double *chi_src;    // [n_tau]
+    const double *w_src;      // [n_tau]
+    double L0, inv_dl;
+    int n_tab, n_k, n_tau, pad;
+    double tau0, R_nu;
+    double rt_g0, rt_ur0, rt_c0, rt_b0, rt_L;
+    double A_s, n_s, k_pivot;
+    double rtol_small, rtol_large, atol_small, atol_large, k_split;
+};
+
+// Static options shared by one launch.
+struct DevPrec {
+    int lg, lp, ln, max_steps;
+    double pcoeff, icoeff, dcoeff;
+    double sw, isw, dop, pol, grav, thom;
+};
+
+// kernel launchers (hipStream_t passed as void*)
+int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_ws,
+                   double *d_S, int *d_status, int *d_nsteps, void *stream);
+size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
+int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E, double s_pol,
+               const double *d_S, double *d_Delta, void *stream);
+int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
+              void *stream);
+int los_max_tau();
+int ell_cut(double x);  // host copy of the Bessel cut rule (tests)
+
+}  // namespace cmbhip

@@ -1,0 +1,233 @@
+// K2: spherical Bessel functions by recurrence and the line-of-sight
+// projection (arXiv 2602.15104, App. B.4, transfer integrals).
+//
+//   Delta_T(l,k) = sum_j w_j [S_T0 j_l + S_T1 j_l' + s_pol S_T2 (3 j_l'' + j_l)/2](x_j)
+//   Delta_E(l,k) = sqrt(3 (l+2)!/(8 (l-2)!)) sum_j w_j sqrt(6) S_T2 j_l(x_j)/x_j^2
+// with x_j = k (tau_0 - tau_j) and trapezoid weights w_j in ln a.  With the
+// downward recurrence the kernel carries (j_{l+1}, j_l); Bessel's equation
+// gives j' = (l/x) j_l - j_{l+1} and (3j''+j)/2 = -(3/x) j' + (3l(l+1)/(2x^2) - 1) j,
+// so each (l, k, tau) term is  j_l (A + l(l+1) B + l D) - j_{l+1} C  with
+// A, B, C, D fixed per (k, tau).
+//
+// Work decomposition: one workgroup (256 lanes) per (cosmology, k); each lane
+// owns M output times (tau_j, j = lane + 256 m, coalesced loads of S).  Every
+// lane first seeds its recurrences:
+//   * x > l_max + 32: upward recurrence from j_0, j_1 (stable for l < x);
+//   * otherwise: Miller's downward recurrence from l_s(x) = x + 16 x^{1/3} + 24
+//     to l = 0, normalised by j_0 = sin x/x (or j_1), recording the pair at
+//     l_act = min(l_max, l_cut(x)); above l_cut(x) = x + 11 x^{1/3} + 12 every
+//     |j_l(x)| < 1e-15 and the term is skipped.
+// Then all lanes walk l downwards together; a lane joins at its own l_act.
+// Per-l partial sums go through LDS in batches of 12 multipoles and are
+// reduced in a fixed order (bitwise reproducible, independent of batch
+// mates).  The walk starts at the workgroup's largest l_act, so small k
+// (x << l_max) costs only the multipoles it can reach.
+#include <hip/hip_runtime.h>
+
+#include "cmbhip_internal.h"
+
+namespace cmbhip {
+
+__host__ __device__ inline int ell_cut_rule(double x) { return (int)ceil(x + 11.0 * cbrt(x) + 12.0); }
+__host__ __device__ inline int ell_start_rule(double x) { return (int)ceil(x + 16.0 * cbrt(x) + 24.0); }
+
+int ell_cut(double x) { return ell_cut_rule(x); }
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int LB = 12;  // multipoles per reduction batch (LDS stays below 64 KiB)
+constexpr int PAD = 1;
+
+template <int M>
+__global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
+                                                    int ell_max, int want_E, double s_pol,
+                                                    const double *__restrict__ S, double *__restrict__ Delta) {
+    __shared__ double red[2][LB][BLOCK + PAD];
+    __shared__ int s_lstart;
+    const int tid = threadIdx.x;
+    const int c = blockIdx.x % n_cosmo;
+    const int ik = n_k - 1 - (int)(blockIdx.x / n_cosmo);
+    const DevTab &tb = tabs[c];
+    const double k = tb.k[ik];
+    const double *S0 = S + ((size_t)c * n_k + ik) * 3 * n_tau;
+    const double *S1 = S0 + n_tau;
+    const double *S2 = S1 + n_tau;
+    const int nl = ell_max - 1;
+    double *DT = Delta + (size_t)c * 2 * nl * n_k;
+    double *DE = DT + (size_t)nl * n_k;
+    const int ltop = ell_max + 1;
+
+    double cA[M], cB[M], cC[M], cD[M], cE[M], rx[M], jl[M], jp[M];
+    int lact[M];
+    double t2_extra = 0.0, e2_extra = 0.0;  // x = 0 limits (only l = 2)
+    int my_lmax = 1;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int j = tid + m * BLOCK;
+        lact[m] = 1;
+        cA[m] = cB[m] = cC[m] = cD[m] = cE[m] = rx[m] = jl[m] = jp[m] = 0.0;
+        if (j >= n_tau) continue;
+        double x = k * tb.chi_src[j];
+        double w = tb.w_src[j];
+        double s0 = S0[j], s1 = S1[j], s2 = S2[j];
+        double p2 = s_pol * s2;
+        if (x == 0.0) {
+            // j_l = j_l' = 0, (3j''+j)/2 = delta_l2/5, j_l/x^2 = delta_l2/15
+            t2_extra += w * p2 * 0.2;
+            e2_extra += w * s2 * (2.449489742783178098 / 15.0);
+            continue;
+        }
+        double ix = 1.0 / x;
+        rx[m] = ix;
+        cA[m] = w * (s0 - p2);
+        cB[m] = 1.5 * w * p2 * ix * ix;
+        cC[m] = w * s1 - 3.0 * w * p2 * ix;
+        cD[m] = cC[m] * ix;
+        cE[m] = 2.449489742783178098 * w * s2 * ix * ix;
+        double sx, cx;
+        sincos(x, &sx, &cx);
+        double j0 = sx * ix, j1 = (sx * ix - cx) * ix;
+        if (x >= ltop + 32) {
+            // upward: (a, b) = (j_{l-1}, j_l)
+            double a = j0, b = j1;
+            for (int l = 1; l < ltop; ++l) {
+                double nb = (2.0 * l + 1.0) * ix * b - a;
+                a = b;
+                b = nb;
+            }
+            jp[m] = b;  // j_{ltop}
+            jl[m] = a;  // j_{ell_max}
+            lact[m] = ell_max;
+        } else {
+            int lc = ell_cut_rule(x);
+            int la = lc < ell_max ? lc : ell_max;
+            int ls = ell_start_rule(x);
+            double hi = 0.0, lo = 1e-200;  // J_{l+1}, J_l at l = ls
+            double rp = 0.0, rl = 0.0;
+            for (int l = ls; l > 0; --l) {
+                double nlo = (2.0 * l + 1.0) * ix * lo - hi;
+                hi = lo;
+                lo = nlo;
+                if (l - 1 == la) {
+                    rp = hi;
+                    rl = lo;
+                }
+                if (fabs(lo) > 1e250) {
+                    lo *= 1e-250;
+                    hi *= 1e-250;
+                    rp *= 1e-250;
+                    rl *= 1e-250;
+                }
+            }
+            // lo = J_0, hi = J_1
+            double sc = (fabs(j0) >= fabs(j1)) ? j0 / lo : j1 / hi;
+            jp[m] = rp * sc;
+            jl[m] = rl * sc;
+            lact[m] = la;
+        }
+        my_lmax = lact[m] > my_lmax ? lact[m] : my_lmax;
+    }
+    if (tid == 0) s_lstart = 1;
+    __syncthreads();
+    atomicMax(&s_lstart, my_lmax);
+    __syncthreads();
+    int lstart = s_lstart;
+    if (t2_extra != 0.0 || e2_extra != 0.0) lstart = lstart < 2 ? 2 : lstart;
+    // there may be an x = 0 point in any lane: make l = 2 always visited
+    lstart = lstart < 2 ? 2 : lstart;
+    // zeros above the walk
+    for (int l = ell_max - tid; l > lstart; l -= BLOCK) {
+        DT[(size_t)(l - 2) * n_k + ik] = 0.0;
+        DE[(size_t)(l - 2) * n_k + ik] = 0.0;
+    }
+    const int sum_id = tid >> 3, sub = tid & 7;  // 32 sums x 8 lanes in the reduction
+    for (int lb = lstart; lb >= 2; lb -= LB) {
+        int nb = lb - 1 < LB ? lb - 1 : LB;  // multipoles in this batch: lb, lb-1, ..., lb-nb+1
+        for (int i = 0; i < nb; ++i) {
+            int l = lb - i;
+            double fl = (double)l;
+            double q = fl * (fl + 1.0);
+            double c21 = 2.0 * fl + 1.0;
+            double tacc = 0.0, eacc = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (l <= lact[m]) {
+                    double j = jl[m], j1 = jp[m];
+                    double P = fma(q, cB[m], fma(fl, cD[m], cA[m]));
+                    tacc = fma(j, P, fma(-j1, cC[m], tacc));
+                    eacc = fma(cE[m], j, eacc);
+                    double jm = fma(c21 * rx[m], j, -j1);
+                    jp[m] = j;
+                    jl[m] = jm;
+                }
+            }
+            if (l == 2) {
+                tacc += t2_extra;
+                eacc += e2_extra;
+            }
+            red[0][i][tid] = tacc;
+            red[1][i][tid] = eacc;
+        }
+        __syncthreads();
+        {
+            int v = sum_id / LB, i = sum_id % LB;
+            bool valid = v < 2 && i < nb;
+            double a = 0.0;
+            if (valid) {
+                for (int r = 0; r < BLOCK / 8; ++r) a += red[v][i][sub + 8 * r];
+            }
+            a += __shfl_xor(a, 1, 8);
+            a += __shfl_xor(a, 2, 8);
+            a += __shfl_xor(a, 4, 8);
+            if (sub == 0 && valid) {
+                int l = lb - i;
+                if (v == 0) {
+                    DT[(size_t)(l - 2) * n_k + ik] = a;
+                } else {
+                    double cl = sqrt(3.0 * (l + 2.0) * (l + 1.0) * l * (l - 1.0) / 8.0);
+                    DE[(size_t)(l - 2) * n_k + ik] = want_E ? cl * a : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int los_max_tau() { return BLOCK * 16; }
+
+int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E, double s_pol,
+               const double *d_S, double *d_Delta, void *stream) {
+    dim3 grid((unsigned)(n_cosmo * n_k)), block(BLOCK);
+    hipStream_t s = (hipStream_t)stream;
+    int M = (n_tau + BLOCK - 1) / BLOCK;
+    if (M <= 1)
+        hipLaunchKernelGGL(los_kernel<1>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol, d_S,
+                           d_Delta);
+    else if (M <= 2)
+        hipLaunchKernelGGL(los_kernel<2>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol, d_S,
+                           d_Delta);
+    else if (M <= 4)
+        hipLaunchKernelGGL(los_kernel<4>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol, d_S,
+                           d_Delta);
+    else if (M <= 8)
+        hipLaunchKernelGGL(los_kernel<8>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol, d_S,
+                           d_Delta);
+    else if (M <= 16)
+        hipLaunchKernelGGL(los_kernel<16>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol, d_S,
+                           d_Delta);
+    else {
+        set_error("n_tau too large for the line-of-sight kernel");
+        return CMB_E_UNSUPPORTED;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("los launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+}  // namespace cmbhip

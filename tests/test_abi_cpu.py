@@ -1,0 +1,155 @@
+"""CPU tests of the library's host side: the C ABI loads and exports what
+include/cmbhip.h declares, argument validation and error codes, and parity of
+the host-built tables (background, recombination, thermodynamics, start
+times, output grid) with the oracle's independently built tables.
+
+No GPU call is made here."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import cmb_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmbhip.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2602_15104_amd as L
+    return L
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmb_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_match_header(lib):
+    declared = header_functions()
+    assert len(declared) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cmb_[a-z_]+)\b", out))
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    assert sorted(lib.EXPORTS) == declared
+
+
+def test_abi_version_and_defaults(lib):
+    assert lib.abi_version() == 1
+    c, p = lib.defaults()
+    # App. A.2 defaults
+    assert c["omega_b"] == 0.02237 and c["omega_cdm"] == 0.120 and c["h"] == 0.6736
+    assert c["A_s"] == 2.1e-9 and c["n_s"] == 0.9649 and c["YHe"] == 0.245
+    assert c["TCMB0"] == 2.34865418e-4 and c["T_nu_massless"] == 0.71636856 and c["T_nu_massive"] == 0.71611
+    assert math.isnan(c["Neff"]) and math.isnan(c["N_nu_massless"]) and math.isnan(c["z_reio"])
+    assert p["ell_gamma"] == 12 and p["ell_pol"] == 10 and p["ell_nu"] == 17 and p["max_steps"] == 2048
+    assert p["rtol_small"] == 1e-5 and p["rtol_large"] == 1e-4 and p["atol_small"] == 1e-10
+    assert p["atol_large"] == 1e-6 and p["k_split"] == 1e-2 and p["R_tc"] == 1.5e-3 and p["R_large"] == 7e-2
+    assert p["pcoeff"] == 0.25 and p["icoeff"] == 0.8 and p["dcoeff"] == 0.0 and p["k_pivot"] == 0.05
+
+
+@pytest.mark.parametrize("case,code", [
+    ("unsorted_k", "CMB_E_INVALID"),
+    ("nan_h", "CMB_E_INVALID"),
+    ("neg_omega_b", "CMB_E_INVALID"),
+    ("n_tau_2", "CMB_E_INVALID"),
+    ("both_neff", "CMB_E_CONFLICT"),
+    ("both_tau_z", "CMB_E_CONFLICT"),
+    ("neither_tau_z", "CMB_E_INVALID"),
+    ("neg_nmassless", "CMB_E_NEG_NMASSLESS"),
+    ("tau_not_bracketed", "CMB_E_ROOT"),
+    ("zero_width", "CMB_E_INVALID"),
+    ("lmax_too_small", "CMB_E_INVALID"),
+])
+def test_table_errors(lib, case, code):
+    wl = W.small_case()
+    c, p, k, nt = dict(wl.cosmo), dict(wl.prec), wl.k.copy(), wl.n_tau
+    if case == "unsorted_k":
+        k = k[::-1].copy()
+    elif case == "nan_h":
+        c["h"] = float("nan")
+    elif case == "neg_omega_b":
+        c["omega_b"] = -0.02
+    elif case == "n_tau_2":
+        nt = 2
+    elif case == "both_neff":
+        c["Neff"] = 3.044
+    elif case == "both_tau_z":
+        c["z_reio"] = 8.0
+    elif case == "neither_tau_z":
+        c["tau_reio"] = float("nan")
+    elif case == "neg_nmassless":
+        c["N_nu_massless"] = float("nan")
+        c["Neff"] = -1.0
+    elif case == "tau_not_bracketed":
+        c["tau_reio"] = 5.0
+    elif case == "zero_width":
+        c["Delta_z_reio"] = 0.0
+    elif case == "lmax_too_small":
+        p["ell_gamma"] = 2
+    with pytest.raises(lib.CmbError) as e:
+        lib.Tables(c, p, k, nt)
+    assert e.value.name == code
+    assert len(str(e.value)) > 20
+
+
+def _pair(wl):
+    import oracle as O
+    import paper_2602_15104_amd as L
+    to = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    tp = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau).export()
+    return to, tp
+
+
+@pytest.mark.parametrize("name", ["config0", "config1", "box"])
+def test_table_parity_with_oracle(name):
+    """Row a1: the library's host tables against the oracle's, built by
+    independent code from the same discretisation.  Agreement is at the
+    rounding level (relative 1e-11 on knot values; spline second derivatives
+    to 1e-13 of max|f| 6/h^2, the factor by which they amplify rounding)."""
+    if name == "config0":
+        wl = W.config0()
+    elif name == "config1":
+        wl = W.config1()
+        wl.k = wl.k[::20].copy()
+    else:
+        wl = W.small_case(n_k=8, k_min=1e-5, k_max=0.5)
+        wl.cosmo.update(W.box_cosmologies(1, seed=11)[0])
+    to, tp = _pair(wl)
+    assert tp["n_tab"] == to.n
+    assert abs(tp["L0"] - to.L0) <= 1e-13 * abs(to.L0)
+    assert abs(tp["z_reio"] - to.z_reio) < 1e-10
+    assert abs(tp["tau0"] / to.tau0 - 1) < 1e-12
+    assert abs(tp["lna_tc"] - to.lna_tc) < 1e-12
+    np.testing.assert_allclose(tp["lna_start"], to.lna_i, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(tp["lna_src"], to.lna_src)
+    np.testing.assert_allclose(tp["chi_src"], to.chi_src, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(tp["w_src"], to.w_src, rtol=1e-12)
+    np.testing.assert_allclose(tp["xe"], to.xe, rtol=1e-11)
+    np.testing.assert_allclose(tp["tm"], to.Tm, rtol=1e-11)
+    for col, key in (("ln_dk", "ln_dk"), ("kappa", "kappa"), ("ln_cs2", "ln_cs2"), ("ln_tau", "ln_tau")):
+        np.testing.assert_allclose(tp[col], to.cols[key], rtol=1e-11, atol=1e-12)
+        # M = 6 (f_{j+1} - 2 f_j + f_{j-1})/h^2 amplifies knot rounding by 6/h^2
+        scale = np.max(np.abs(to.cols[key])) * 6.0 / to.dl ** 2
+        assert np.max(np.abs(tp["M_" + col] - to.M[key])) < 1e-13 * scale, col
+    assert abs(tp["R_nu"] - to.bg.R_nu) < 1e-14
+    assert abs(tp["rt_L"] / to.bg.rt_L - 1) < 1e-13
+
+
+def test_massive_neutrinos_reported_unsupported(lib):
+    wl = W.small_case()
+    c = dict(wl.cosmo)
+    c["N_nu_massless"] = float("nan")
+    c["Neff"] = 3.044
+    c["N_nu_massive"] = 1.0
+    p = dict(wl.prec)
+    p["n_q"] = 12
+    with pytest.raises(lib.CmbError) as e:
+        lib.Tables(c, p, wl.k, wl.n_tau)
+    assert e.value.name == "CMB_E_UNSUPPORTED"
