@@ -22,7 +22,7 @@
  *     order-3 embedded estimate; every implicit stage is one linear solve of
  *     (I - h gamma A) Y = R because the system is linear, done here on the
  *     dense matrix A (built column by column from f) by Gaussian elimination
- *     with partial pivoting;
+ *     with partial pivoting and two steps of iterative refinement;
  *   - RMS error norm with scale atol + rtol max(|y_n|,|y_n+1|), PID step
  *     controller with coefficients (pcoeff, icoeff, dcoeff) (App. A.2,
  *     perturbation solver options) on error order 4, safety 0.9, step factor
@@ -279,38 +279,70 @@ static void matvec(int N, const double *A, const double *x, double *y) {
     }
 }
 
-/* Solve M x = r with Gaussian elimination and partial pivoting; M is destroyed. */
-static int lu_solve(int N, double *M, double *r) {
+/* Gaussian elimination with partial pivoting: M (N x N, row major) is
+   overwritten by its LU factors, piv records the row swaps. */
+static int lu_factor(int N, double *M, int *piv) {
     for (int c = 0; c < N; ++c) {
-        int piv = c;
+        int p = c;
         double best = fabs(M[c * N + c]);
         for (int i = c + 1; i < N; ++i)
             if (fabs(M[i * N + c]) > best) {
                 best = fabs(M[i * N + c]);
-                piv = i;
+                p = i;
             }
         if (best == 0.0) return -1;
-        if (piv != c) {
+        piv[c] = p;
+        if (p != c)
             for (int j = 0; j < N; ++j) {
-                double tmp = M[c * N + j];
-                M[c * N + j] = M[piv * N + j];
-                M[piv * N + j] = tmp;
+                double t = M[c * N + j];
+                M[c * N + j] = M[p * N + j];
+                M[p * N + j] = t;
             }
-            double tmp = r[c];
-            r[c] = r[piv];
-            r[piv] = tmp;
-        }
         for (int i = c + 1; i < N; ++i) {
             double m = M[i * N + c] / M[c * N + c];
+            M[i * N + c] = m;
             if (m == 0.0) continue;
-            for (int j = c; j < N; ++j) M[i * N + j] -= m * M[c * N + j];
-            r[i] -= m * r[c];
+            for (int j = c + 1; j < N; ++j) M[i * N + j] -= m * M[c * N + j];
         }
     }
+    return 0;
+}
+
+static void lu_apply(int N, const double *LU, const int *piv, double *r) {
+    /* P r (the swaps in the order they were made), then L and U */
+    for (int c = 0; c < N; ++c)
+        if (piv[c] != c) {
+            double t = r[c];
+            r[c] = r[piv[c]];
+            r[piv[c]] = t;
+        }
+    for (int c = 0; c < N; ++c)
+        for (int i = c + 1; i < N; ++i) r[i] -= LU[i * N + c] * r[c];
     for (int i = N - 1; i >= 0; --i) {
         double s = r[i];
-        for (int j = i + 1; j < N; ++j) s -= M[i * N + j] * r[j];
-        r[i] = s / M[i * N + i];
+        for (int j = i + 1; j < N; ++j) s -= LU[i * N + j] * r[j];
+        r[i] = s / LU[i * N + i];
+    }
+}
+
+/* Solve M x = r (x returned in r): LU with partial pivoting followed by two
+   steps of iterative refinement with residuals accumulated in long double.
+   The stage matrices are badly scaled (the eta' row carries 1/k^2), and the
+   refinement brings the solve to rounding level. */
+static int lu_solve(int N, const double *M, double *r, double *LU, int *piv, double *res) {
+    memcpy(LU, M, sizeof(double) * N * N);
+    if (lu_factor(N, LU, piv) != 0) return -1;
+    double *b = res + N;
+    memcpy(b, r, sizeof(double) * N);
+    lu_apply(N, LU, piv, r);
+    for (int it = 0; it < 2; ++it) {
+        for (int i = 0; i < N; ++i) {
+            long double acc = b[i];
+            for (int j = 0; j < N; ++j) acc -= (long double)M[i * N + j] * r[j];
+            res[i] = (double)acc;
+        }
+        lu_apply(N, LU, piv, res);
+        for (int i = 0; i < N; ++i) r[i] += res[i];
     }
     return 0;
 }
@@ -390,11 +422,13 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
     int N = L.N;
     if (p->lg < 3 || p->ln < 3 || (p->lp != 0 && p->lp < 3) || (p->nq > 0 && p->lq < 3) || p->nq > MAXQ || k <= 0)
         return O_BAD_INPUT;
-    double *work = (double *)calloc((size_t)N * N * 2 + (size_t)N * 20, sizeof(double));
+    double *work = (double *)calloc((size_t)N * N * 3 + (size_t)N * 22, sizeof(double));
+    int *piv = (int *)calloc((size_t)N, sizeof(int));
     double *A = work, *Mm = A + N * N;
     double *y = Mm + N * N, *f = y + N, *ynew = f + N, *R = ynew + N, *err = R + N, *e = err + N, *col = e + N;
     double *K = col + N; /* 6 vectors */
     double *tmp = K + 6 * N, *ytmp = tmp + N, *dyt = ytmp + N;
+    double *LU = dyt + N, *res = LU + (size_t)N * N; /* res holds 2N */
     for (int i = 0; i < 3 * n_out; ++i) S[i] = 0.0;
     int status = O_OK;
     int ns = 0, na = 0;
@@ -459,7 +493,7 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
             build_A(tb, p, &L, k, &bs, A, e, col);
             for (int i = 0; i < N * N; ++i) Mm[i] = -h * gam * A[i];
             for (int i = 0; i < N; ++i) Mm[i * N + i] += 1.0;
-            if (lu_solve(N, Mm, R) != 0) {
+            if (lu_solve(N, Mm, R, LU, piv, res) != 0) {
                 status = O_NONFINITE;
                 break;
             }
@@ -517,6 +551,7 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
     *nsteps = ns;
     *naccept = na;
     free(work);
+    free(piv);
     return status;
 }
 
