@@ -20,7 +20,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcmbhip.so")
+LIB_PATH = os.environ.get("CMBHIP_LIBRARY") or os.path.join(_HERE, "libcmbhip.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcmbhip.so not found at {LIB_PATH}; build it with `python -m paper_2602_15104_amd.build`")

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -433,6 +434,19 @@ int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
+    const char *variant = std::getenv("CMBHIP_K1");
+    bool lane_variant = variant && std::string(variant) == "lane";
+    if (!lane_variant && cmbhip::perturb2_supported(b.prec)) {
+        int32_t *ns2 = d_nsteps;
+        if (!ns2) {
+            rc = grow(c, &c->st_buf, &c->st_cap, sizeof(int32_t) * (size_t)n_cosmo * b.n_k, s);
+            if (rc) return rc;
+            ns2 = (int32_t *)c->st_buf;
+        }
+        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, stream);
+        if (rc == CMB_OK) set_error("");
+        return rc;
+    }
     size_t need = cmbhip::perturb_ws_doubles(n_cosmo, b.n_k, b.prec) * sizeof(double);
     rc = grow(c, &c->ws_buf, &c->ws_cap, need, s);
     if (rc) return rc;

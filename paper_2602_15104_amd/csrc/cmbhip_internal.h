@@ -57,6 +57,9 @@ struct DevPrec {
 int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_ws,
                    double *d_S, int *d_status, int *d_nsteps, void *stream);
 size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
+int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
+                    int *d_status, int *d_nsteps, void *stream);
+bool perturb2_supported(const DevPrec &p);
 int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E, double s_pol,
                const double *d_S, double *d_Delta, void *stream);
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,

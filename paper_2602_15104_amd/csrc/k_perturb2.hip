@@ -1,0 +1,746 @@
+// K1 (cooperative variant): synchronous-gauge perturbations and CMB sources,
+// one group of G lanes per (cosmology, k) mode.
+//
+// Same method as k_perturb.hip (ESDIRK4(3)6L[2]SA, RMS norm, PID control,
+// Hermite dense output, source functions of App. B.4 of arXiv 2602.15104;
+// equations of App. B.3 and App. C), mapped differently onto the hardware:
+//
+//  * a mode's state rows are spread over a group of G lanes (G = 16 for the
+//    79-row TT/TE/EE hierarchy, R = 5 rows per lane); every working vector
+//    (state, six stage derivatives, new state, stage right-hand side) lives
+//    in registers of the lane that owns the row, so no workspace traffic;
+//  * row-parallel work (stage right-hand sides, matrix entries of
+//    I - h gamma A, K = (Y - R)/(h gamma), error norm, dense output) is
+//    spread over the group's lanes;
+//  * the three multipole chains (photon T + baryons, photon P, neutrinos)
+//    are reduced by one lane each, highest multipole first, reading the
+//    entries the row lanes left in LDS; the chains share one instruction
+//    stream, so they advance in lock-step;
+//  * one lane solves the 3x3 system of the couplings h', eta', Pi, then the
+//    chain lanes substitute downwards and the row lanes pick up their rows;
+//  * a wavefront holds 64/G modes; lanes exchange data through LDS with
+//    wave-scope fences (a workgroup is one wavefront), so modes of one
+//    wavefront may branch independently.
+#include <hip/hip_runtime.h>
+
+#include "cmbhip_internal.h"
+
+namespace cmbhip {
+
+namespace {
+
+__device__ constexpr double Kc[6] = {0.0, 0.5, 83.0 / 250.0, 31.0 / 50.0, 17.0 / 20.0, 1.0};
+__device__ constexpr double Ka[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0.25, 0.25, 0, 0, 0, 0},
+    {8611.0 / 62500.0, -1743.0 / 31250.0, 0.25, 0, 0, 0},
+    {5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, 0.25, 0, 0},
+    {15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0, 2285395.0 / 8070912.0,
+     0.25, 0},
+    {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, 0.25}};
+__device__ constexpr double Ke[6] = {
+    82889.0 / 524892.0 - 4586570599.0 / 29645900160.0, 0.0, 15625.0 / 83664.0 - 178811875.0 / 945068544.0,
+    69875.0 / 102672.0 - 814220225.0 / 1159782912.0, -2260.0 / 8211.0 + 3700637.0 / 11593932.0,
+    0.25 - 61727.0 / 225920.0};
+constexpr double GAMMA = 0.25;
+
+// Exchange point between the lanes of a wavefront: wait for this wave's LDS
+// operations to complete; the memory clobber keeps the compiler from moving
+// any load or store across it.  (A workgroup is one wavefront and LDS
+// operations of a wavefront execute in order, so no s_barrier is needed and
+// groups of a wavefront may sit in different branches.)
+__device__ inline void wsync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+struct Bk {  // background and per-stage constants at one ln a
+    double a, Hc, Hcp, rg, rur, rc, rb;
+    double dk, dkp, kap, cs2, tau;
+    double invHc, kH, k2H, T, R, trunc, cH1, cH2, cE;
+};
+
+__device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, Bk &s) {
+    double a = exp(lna);
+    s.a = a;
+    double a2 = a * a, a3 = a2 * a, a4 = a2 * a2;
+    s.rg = tb.rt_g0 / a4;
+    s.rur = tb.rt_ur0 / a4;
+    s.rc = tb.rt_c0 / a3;
+    s.rb = tb.rt_b0 / a3;
+    double rho = s.rg + s.rur + s.rc + s.rb + tb.rt_L;
+    double pr = (s.rg + s.rur) * (1.0 / 3.0) - tb.rt_L;
+    s.Hc = a * sqrt(rho);
+    s.Hcp = s.Hc * (1.0 - 1.5 * (rho + pr) / rho);
+    double u = (lna - tb.L0) * tb.inv_dl;
+    int j = (int)floor(u);
+    j = j < 0 ? 0 : (j > tb.n_tab - 1 ? tb.n_tab - 1 : j);
+    double t = u - j;
+    const double *o = tb.poly + (size_t)j * 16;
+    double l0 = ((o[3] * t + o[2]) * t + o[1]) * t + o[0];
+    double d0 = ((3.0 * o[3] * t + 2.0 * o[2]) * t + o[1]) * tb.inv_dl;
+    s.dk = exp(l0);
+    s.dkp = s.dk * d0;
+    s.kap = ((o[7] * t + o[6]) * t + o[5]) * t + o[4];
+    s.cs2 = exp(((o[11] * t + o[10]) * t + o[9]) * t + o[8]);
+    s.tau = exp(((o[15] * t + o[14]) * t + o[13]) * t + o[12]);
+    s.invHc = 1.0 / s.Hc;
+    s.kH = k * s.invHc;
+    s.k2H = k * s.kH;
+    s.T = p.thom * s.dk * s.invHc;
+    s.R = (4.0 / 3.0) * s.rg / s.rb;
+    s.trunc = s.invHc / s.tau;
+    double ih2 = s.invHc * s.invHc;
+    s.cH1 = p.grav * 2.0 * k * k * ih2;
+    s.cH2 = p.grav * 3.0 * a2 * ih2;
+    s.cE = p.grav * 1.5 * a2 * s.invHc / (k * k);
+}
+
+// Row layout: [F chain | G chain | nu chain | delta_c, eta, delta_g], padded.
+struct Lay {
+    int N, nF, nG, nV, bG, bV, rDC, rETA, rDG, nch;
+};
+__device__ inline Lay make_lay(const DevPrec &p) {
+    Lay L;
+    L.nF = p.lg + 2;
+    L.nG = p.lp > 0 ? p.lp + 1 : 0;
+    L.nV = p.ln + 1;
+    L.bG = L.nF;
+    L.bV = L.nF + L.nG;
+    L.rDC = L.bV + L.nV;
+    L.rETA = L.rDC + 1;
+    L.rDG = L.rDC + 2;
+    L.N = L.rDC + 3;
+    L.nch = L.nG ? 3 : 2;
+    return L;
+}
+
+struct RowCo {
+    double a, d, c, uH, uE, uP;
+};
+
+// y'_row = a y_{row-1} + d y_row + c y_{row+1} + uH h' + uE eta' + uP Pi
+// (chain rows; for the isolated rows only the coupling terms are used and
+// the delta_g leaf term of the theta_g row is added by the caller).
+__device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p) {
+    RowCo r{0, 0, 0, 0, 0, 0};
+    int ch, j, n;
+    if (row < L.bG) {
+        ch = 0;
+        j = row;
+        n = L.nF;
+    } else if (row < L.bV) {
+        ch = 1;
+        j = row - L.bG;
+        n = L.nG;
+    } else if (row < L.rDC) {
+        ch = 2;
+        j = row - L.bV;
+        n = L.nV;
+    } else {
+        if (row == L.rDC) r.uH = -0.5;
+        if (row == L.rETA) r.uE = 1.0;
+        if (row == L.rDG) r.uH = -2.0 / 3.0;
+        return r;
+    }
+    // generic multipole row: l from the chain, Thomson damping for photons
+    int l = (ch == 0) ? j - 1 : j;
+    bool thom = ch != 2;
+    int low = (ch == 0) ? 4 : (ch == 1 ? 0 : 3);  // first row of the generic form
+    if (j >= low) {
+        double f2 = (l == 3 && ch != 1) ? 2.0 : 1.0;  // F_2 = 2 sigma
+        double damp = thom ? -s.T : 0.0;
+        if (j == n - 1) {
+            r.a = f2 * s.kH;
+            r.d = -(l + 1.0) * s.trunc + damp;
+        } else {
+            double w = s.kH / (2.0 * l + 1.0);
+            r.a = f2 * l * w;
+            r.d = damp;
+            r.c = -(l + 1.0) * w;
+            if (ch == 1 && l == 0) r.uP = 0.5 * s.T;
+            if (ch == 1 && l == 2) r.uP = 0.1 * s.T;
+        }
+        return r;
+    }
+    if (ch == 0) {
+        if (j == 0) {
+            r.c = -s.invHc;
+            r.uH = -0.5;
+        } else if (j == 1) {
+            r.a = s.cs2 * s.k2H;
+            r.d = -1.0 - s.R * s.T;
+            r.c = s.R * s.T;
+        } else if (j == 2) {
+            r.a = s.T;
+            r.d = -s.T;
+            r.c = -s.k2H;
+        } else {
+            r.a = (4.0 / 15.0) * s.invHc;
+            r.c = -0.3 * s.kH;
+            r.uH = 2.0 / 15.0;
+            r.uE = 0.8;
+            if (p.lp > 0) {
+                r.d = -s.T;
+                r.uP = 0.05 * s.T;
+            } else {
+                r.d = -0.9 * s.T;
+            }
+        }
+    } else {  // neutrinos
+        if (j == 0) {
+            r.c = -(4.0 / 3.0) * s.invHc;
+            r.uH = -2.0 / 3.0;
+        } else if (j == 1) {
+            r.a = 0.25 * s.k2H;
+            r.c = -s.k2H;
+        } else {
+            r.a = (4.0 / 15.0) * s.invHc;
+            r.c = -0.3 * s.kH;
+            r.uH = 2.0 / 15.0;
+            r.uE = 0.8;
+        }
+    }
+    return r;
+}
+
+// LDS slab of one mode
+struct Slab {
+    double *AL, *BE, *GA, *RY, *AX;
+    int NP;
+};
+
+constexpr int AXN = 64;  // exchange area doubles per mode
+
+// Couplings (h', eta', Pi) from the state rows held in RY.
+__device__ void aux_from_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, double &H, double &E,
+                              double &P) {
+    const double *y = m.RY;
+    H = s.cH1 * y[L.rETA] + s.cH2 * (s.rc * y[L.rDC] + s.rb * y[0] + s.rg * y[L.rDG] + s.rur * y[L.bV]);
+    E = s.cE * (s.rb * y[1] + (4.0 / 3.0) * s.rg * y[2] + (4.0 / 3.0) * s.rur * y[L.bV + 1]);
+    P = (p.lp > 0) ? 2.0 * y[3] + y[L.bG] + y[L.bG + 2] : 0.0;
+}
+
+template <int R>
+struct Rows {
+    double y[R], yn[R], K[6][R], rr[R];
+};
+
+// f = A y for this lane's rows; y already in m.RY (all rows), couplings in AX[0..2].
+template <int R>
+__device__ void rhs_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, int gl, double *f) {
+    double H = m.AX[0], E = m.AX[1], P = m.AX[2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int row = gl * R + r;
+        double v = 0.0;
+        if (row < L.N) {
+            RowCo c = row_coef(row, L, s, p);
+            if (row < L.rDC) {
+                int n_start = (row < L.bG) ? 0 : (row < L.bV ? L.bG : L.bV);
+                int n_end = (row < L.bG) ? L.bG : (row < L.bV ? L.bV : L.rDC);
+                double ym = row > n_start ? m.RY[row - 1] : 0.0;
+                double yp = row + 1 < n_end ? m.RY[row + 1] : 0.0;
+                v = c.a * ym + c.d * m.RY[row] + c.c * yp;
+                if (row == 2) v += 0.25 * s.k2H * m.RY[L.rDG];
+            } else if (row == L.rDG) {
+                v = -(4.0 / 3.0) * s.invHc * m.RY[2];
+            }
+            v += c.uH * H + c.uE * E + c.uP * P;
+        }
+        f[r] = v;
+    }
+}
+
+struct Aff {
+    double v0, vH, vE, vP;
+};
+
+__device__ inline double aff(const Aff &a, double H, double E, double P) { return a.v0 + a.vH * H + a.vE * E + a.vP * P; }
+
+template <int R>
+__global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
+                                                      DevPrec p, int G, double *__restrict__ Sout,
+                                                      int *__restrict__ status, int *__restrict__ nsteps) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int gl = lane % G;
+    const int grp = lane / G;
+    const int spw = 64 / G;
+    const int n_sys = n_cosmo * n_k;
+    const int lin = blockIdx.x * spw + grp;
+    const Lay L = make_lay(p);
+    const int NP = G * R;
+    Slab m;
+    {
+        double *base = lds + (size_t)grp * (4 * NP + AXN);
+        m.AL = base;
+        m.BE = base + NP;
+        m.GA = base + 2 * NP;
+        m.RY = base + 3 * NP;
+        m.AX = base + 4 * NP;
+        m.NP = NP;
+    }
+    if (lin >= n_sys) return;  // whole group idle (no cross-group dependence)
+    const int sys = n_sys - 1 - lin;  // largest k first, cosmology fastest
+    const int c = sys % n_cosmo;
+    const int ik = sys / n_cosmo;
+    const DevTab &tb = tabs[c];
+    const double k = tb.k[ik];
+    const double t0 = tb.lna_start[ik];
+    const bool small = k < tb.k_split;
+    const double rtol = small ? tb.rtol_small : tb.rtol_large;
+    const double atol = small ? tb.atol_small : tb.atol_large;
+    double *So = Sout + ((size_t)c * n_k + ik) * 3 * n_tau;
+    const double *lo = tb.lna_src;
+    const int ch = gl;  // chain handled by this lane in the sweeps
+    const bool sweeper = ch < L.nch;
+    int cb = 0, cn = 0;  // chain start row and length
+    if (sweeper) {
+        cb = ch == 0 ? 0 : (ch == 1 && L.nG ? L.bG : L.bV);
+        cn = ch == 0 ? L.nF : (ch == 1 && L.nG ? L.nG : L.nV);
+    }
+    const int N = L.N;
+
+    Rows<R> w;
+    // every register vector starts at zero: the stage sums below multiply the
+    // not-yet-computed derivatives by zero weights, which must not meet NaN bits
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        w.y[r] = w.yn[r] = w.rr[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) w.K[j][r] = 0.0;
+    }
+    Bk s;
+    bk_at(tb, p, k, t0, s);
+    // initial conditions (Ma & Bertschinger 1995 growing mode, eta -> 1)
+    {
+        double x = k * s.tau, Rn = tb.R_nu;
+        double dg = -x * x / 3.0, tg = -k * x * x * x / 36.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int row = gl * R + r;
+            double v = 0.0;
+            if (row == 0) v = 0.75 * dg;
+            if (row == 1 || row == 2) v = tg;
+            if (row == L.bV) v = dg;
+            if (row == L.bV + 1) v = (23.0 + 4.0 * Rn) / (15.0 + 4.0 * Rn) * tg;
+            if (row == L.bV + 2) v = 2.0 / (3.0 * (15.0 + 4.0 * Rn)) * x * x;
+            if (row == L.rDC) v = 0.75 * dg;
+            if (row == L.rDG) v = dg;
+            if (row == L.rETA) v = 1.0 - (5.0 + 4.0 * Rn) / (12.0 * (15.0 + 4.0 * Rn)) * x * x;
+            w.y[r] = v;
+        }
+    }
+    // f0 = A y0
+    auto full_rhs = [&](const double *yv, double *f, const Bk &bs) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) m.RY[gl * R + r] = yv[r];
+        wsync();
+        if (gl == 0) {
+            double H, E, P;
+            aux_from_rows(m, L, bs, p, H, E, P);
+            m.AX[0] = H;
+            m.AX[1] = E;
+            m.AX[2] = P;
+        }
+        wsync();
+        rhs_rows<R>(m, L, bs, p, gl, f);
+        wsync();
+    };
+    full_rhs(w.y, w.K[0], s);
+
+    auto group_sum = [&](double v) {
+        for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+        return v;
+    };
+    auto rms = [&](const double *v, const double *y1, const double *y2) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (gl * R + r < N) {
+                double yy = fabs(y1[r]);
+                if (y2) yy = fmax(yy, fabs(y2[r]));
+                double q = v[r] / (atol + rtol * yy);
+                acc += q * q;
+            }
+        }
+        return sqrt(group_sum(acc) / N);
+    };
+
+    int jo = 0;
+    if (gl == 0) {
+        while (jo < n_tau && lo[jo] < t0) {
+            So[jo] = 0.0;
+            So[n_tau + jo] = 0.0;
+            So[2 * n_tau + jo] = 0.0;
+            ++jo;
+        }
+    } else {
+        while (jo < n_tau && lo[jo] < t0) ++jo;
+    }
+    double t = t0;
+    double h;
+    {
+        double d0 = rms(w.y, w.y, nullptr);
+        double d1 = rms(w.K[0], w.y, nullptr);
+        double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+        if (h0 > -t) h0 = -t;
+        double y1[R], f1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) y1[r] = w.y[r] + h0 * w.K[0][r];
+        Bk s1;
+        bk_at(tb, p, k, t + h0, s1);
+        full_rhs(y1, f1, s1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) f1[r] -= w.K[0][r];
+        double d2 = rms(f1, w.y, nullptr) / h0;
+        double dm = fmax(d1, d2);
+        double hh = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+        h = fmin(100.0 * h0, hh);
+    }
+    const double b1 = (p.pcoeff + p.icoeff + p.dcoeff) / 4.0;
+    const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / 4.0;
+    const double b3 = p.dcoeff / 4.0;
+    double Ep = 1.0, Epp = 1.0;
+    int ns = 0, st = CMB_K_OK;
+
+    while (t < 0.0) {
+        if (ns >= p.max_steps) {
+            st = CMB_K_MAX_STEPS;
+            break;
+        }
+        bool last = false;
+        if (h >= -t) {
+            h = -t;
+            last = true;
+        }
+        const double g = h * GAMMA;
+        for (int si = 1; si < 6; ++si) {
+            double ts = (si == 5) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
+            bk_at(tb, p, k, ts, s);
+            // stage weights h a_sj for j < s (zero otherwise): fixed-length sums keep
+            // every register index static
+            double hA[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
+            // (A) stage right-hand side and matrix entries of I - g A, row-parallel
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int row = gl * R + r;
+                double acc = w.y[r];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) acc += hA[j] * w.K[j][r];
+                w.rr[r] = acc;
+                m.RY[row] = acc;
+                if (row < L.rDC) {
+                    RowCo cc = row_coef(row, L, s, p);
+                    m.AL[row] = -g * cc.a;
+                    m.BE[row] = 1.0 - g * cc.d;
+                    m.GA[row] = -g * cc.c;
+                }
+            }
+            wsync();
+            // (B) upward elimination of each chain, one lane per chain
+            Aff top[4];
+            if (sweeper) {
+                double bp = 0.0, rp = 0.0, alb = 0.0;
+                for (int j = cn - 1; j >= 4; --j) {
+                    int row = cb + j;
+                    double be = m.BE[row], ga = m.GA[row], rho = m.RY[row];
+                    if (j < cn - 1) {
+                        double mm = ga / bp;
+                        be -= mm * alb;
+                        rho -= mm * rp;
+                    }
+                    bp = be;
+                    rp = rho;
+                    alb = m.AL[row];
+                    m.BE[row] = 1.0 / be;
+                    m.GA[row] = rho;
+                }
+                double eH = 0.0, eE = 0.0, eP = 0.0;
+                double ib[4], r0[4], rH[4], rE[4], rP[4], al[4];
+#pragma unroll
+                for (int j = 3; j >= 0; --j) {
+                    int row = cb + j;
+                    RowCo cc = row_coef(row, L, s, p);
+                    double be = m.BE[row], ga = m.GA[row], rho = m.RY[row];
+                    double xH = -g * cc.uH, xE = -g * cc.uE, xP = -g * cc.uP;
+                    if (ch == 0 && j == 2) {
+                        // delta_g = R_dg - g (4/3)/Hc theta_g - (2g/3) h' eliminated into theta_g
+                        double cl = g * 0.25 * s.k2H;
+                        be += cl * g * (4.0 / 3.0) * s.invHc;
+                        xH += cl * g * (2.0 / 3.0);
+                        rho += cl * m.RY[L.rDG];
+                    }
+                    if (j < cn - 1) {
+                        double mm = ga / bp;
+                        be -= mm * alb;
+                        rho -= mm * rp;
+                        xH -= mm * eH;
+                        xE -= mm * eE;
+                        xP -= mm * eP;
+                    }
+                    bp = be;
+                    rp = rho;
+                    eH = xH;
+                    eE = xE;
+                    eP = xP;
+                    alb = m.AL[row];
+                    ib[j] = 1.0 / be;
+                    r0[j] = rho;
+                    rH[j] = xH;
+                    rE[j] = xE;
+                    rP[j] = xP;
+                    al[j] = m.AL[row];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    double v0 = r0[j], vH = -rH[j], vE = -rE[j], vP = -rP[j];
+                    if (j > 0) {
+                        v0 -= al[j] * top[j - 1].v0;
+                        vH -= al[j] * top[j - 1].vH;
+                        vE -= al[j] * top[j - 1].vE;
+                        vP -= al[j] * top[j - 1].vP;
+                    }
+                    top[j] = Aff{v0 * ib[j], vH * ib[j], vE * ib[j], vP * ib[j]};
+                    m.AX[4 + 16 * ch + 4 * j + 0] = top[j].v0;
+                    m.AX[4 + 16 * ch + 4 * j + 1] = top[j].vH;
+                    m.AX[4 + 16 * ch + 4 * j + 2] = top[j].vE;
+                    m.AX[4 + 16 * ch + 4 * j + 3] = top[j].vP;
+                }
+            }
+            wsync();
+            // (C) couplings: 3x3 (2x2 without polarisation) system, one lane
+            if (gl == 0) {
+                auto T = [&](int chn, int j) {
+                    const double *q = m.AX + 4 + 16 * chn + 4 * j;
+                    return Aff{q[0], q[1], q[2], q[3]};
+                };
+                const int cv = L.nG ? 2 : 1;
+                Aff F0 = T(0, 0), F1 = T(0, 1), F2 = T(0, 2), F3 = T(0, 3), V0 = T(cv, 0), V1 = T(cv, 1);
+                double Rdc = m.RY[L.rDC], Reta = m.RY[L.rETA], Rdg = m.RY[L.rDG];
+                Aff dc{Rdc, -0.5 * g, 0.0, 0.0};
+                Aff eta{Reta, 0.0, g, 0.0};
+                double cg = -g * (4.0 / 3.0) * s.invHc;
+                Aff dg{Rdg + cg * F2.v0, cg * F2.vH - (2.0 / 3.0) * g, cg * F2.vE, cg * F2.vP};
+                Aff eH, eE;
+                eH.v0 = s.cH1 * eta.v0 + s.cH2 * (s.rc * dc.v0 + s.rb * F0.v0 + s.rg * dg.v0 + s.rur * V0.v0);
+                eH.vH = s.cH1 * eta.vH + s.cH2 * (s.rc * dc.vH + s.rb * F0.vH + s.rg * dg.vH + s.rur * V0.vH);
+                eH.vE = s.cH1 * eta.vE + s.cH2 * (s.rc * dc.vE + s.rb * F0.vE + s.rg * dg.vE + s.rur * V0.vE);
+                eH.vP = s.cH1 * eta.vP + s.cH2 * (s.rc * dc.vP + s.rb * F0.vP + s.rg * dg.vP + s.rur * V0.vP);
+                const double f43 = 4.0 / 3.0;
+                eE.v0 = s.cE * (s.rb * F1.v0 + f43 * s.rg * F2.v0 + f43 * s.rur * V1.v0);
+                eE.vH = s.cE * (s.rb * F1.vH + f43 * s.rg * F2.vH + f43 * s.rur * V1.vH);
+                eE.vE = s.cE * (s.rb * F1.vE + f43 * s.rg * F2.vE + f43 * s.rur * V1.vE);
+                eE.vP = s.cE * (s.rb * F1.vP + f43 * s.rg * F2.vP + f43 * s.rur * V1.vP);
+                double H, E, P;
+                if (L.nG) {
+                    Aff G0 = T(1, 0), G2 = T(1, 2);
+                    Aff eP{2.0 * F3.v0 + G0.v0 + G2.v0, 2.0 * F3.vH + G0.vH + G2.vH, 2.0 * F3.vE + G0.vE + G2.vE,
+                           2.0 * F3.vP + G0.vP + G2.vP};
+                    double mm[3][4] = {{1.0 - eH.vH, -eH.vE, -eH.vP, eH.v0},
+                                       {-eE.vH, 1.0 - eE.vE, -eE.vP, eE.v0},
+                                       {-eP.vH, -eP.vE, 1.0 - eP.vP, eP.v0}};
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        int piv = cc;
+#pragma unroll
+                        for (int rr = cc + 1; rr < 3; ++rr)
+                            if (fabs(mm[rr][cc]) > fabs(mm[piv][cc])) piv = rr;
+                        if (piv != cc) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                double tt = mm[cc][q];
+                                mm[cc][q] = mm[piv][q];
+                                mm[piv][q] = tt;
+                            }
+                        }
+#pragma unroll
+                        for (int rr = cc + 1; rr < 3; ++rr) {
+                            double f = mm[rr][cc] / mm[cc][cc];
+#pragma unroll
+                            for (int q = cc; q < 4; ++q) mm[rr][q] -= f * mm[cc][q];
+                        }
+                    }
+                    P = mm[2][3] / mm[2][2];
+                    E = (mm[1][3] - mm[1][2] * P) / mm[1][1];
+                    H = (mm[0][3] - mm[0][1] * E - mm[0][2] * P) / mm[0][0];
+                } else {
+                    double a11 = 1.0 - eH.vH, a12 = -eH.vE, a21 = -eE.vH, a22 = 1.0 - eE.vE;
+                    double det = a11 * a22 - a12 * a21;
+                    H = (eH.v0 * a22 - a12 * eE.v0) / det;
+                    E = (a11 * eE.v0 - a21 * eH.v0) / det;
+                    P = 0.0;
+                }
+                m.AX[0] = H;
+                m.AX[1] = E;
+                m.AX[2] = P;
+                m.RY[L.rDC] = aff(dc, H, E, P);
+                m.RY[L.rETA] = aff(eta, H, E, P);
+                m.RY[L.rDG] = aff(dg, H, E, P);
+            }
+            wsync();
+            // (D) downward substitution, one lane per chain
+            if (sweeper) {
+                double H = m.AX[0], E = m.AX[1], P = m.AX[2];
+                double yprev = 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    yprev = aff(top[j], H, E, P);
+                    m.RY[cb + j] = yprev;
+                }
+                for (int j = 4; j < cn; ++j) {
+                    int row = cb + j;
+                    double y = (m.GA[row] - m.AL[row] * yprev) * m.BE[row];
+                    m.RY[row] = y;
+                    yprev = y;
+                }
+            }
+            wsync();
+            // (E) row lanes: K = (Y - R)/g
+            const double ig = 1.0 / g;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int row = gl * R + r;
+                double y = row < N ? m.RY[row] : 0.0;
+                double kv = (y - w.rr[r]) * ig;
+#pragma unroll
+                for (int j = 1; j < 6; ++j)
+                    if (si == j) w.K[j][r] = kv;
+                if (si == 5) w.yn[r] = y;
+            }
+            wsync();
+        }
+        // error estimate
+        double ev[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double e = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) e += Ke[j] * w.K[j][r];
+            ev[r] = h * e;
+        }
+        double E = rms(ev, w.y, w.yn);
+        ++ns;
+        if (!isfinite(E)) {
+            st = CMB_K_NONFINITE;
+            break;
+        }
+        double fac;
+        if (E <= 1.0) {
+            double tn = last ? 0.0 : t + h;
+            if (tn >= 0.0) tn = 0.0;
+            double hh = tn - t;
+            while (jo < n_tau && lo[jo] <= tn) {
+                double th = hh > 0.0 ? (lo[jo] - t) / hh : 1.0;
+                double th2 = th * th, th3 = th2 * th;
+                double h00 = 2.0 * th3 - 3.0 * th2 + 1.0, h10 = th3 - 2.0 * th2 + th;
+                double h01 = -2.0 * th3 + 3.0 * th2, h11 = th3 - th2;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    m.RY[gl * R + r] = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
+                wsync();
+                if (gl == 0) {
+                    Bk so;
+                    bk_at(tb, p, k, lo[jo], so);
+                    const double *y = m.RY;
+                    double k2 = k * k;
+                    double Hh = so.cH1 * y[L.rETA] +
+                                so.cH2 * (so.rc * y[L.rDC] + so.rb * y[0] + so.rg * y[L.rDG] + so.rur * y[L.bV]);
+                    double Ee = so.cE * (so.rb * y[1] + (4.0 / 3.0) * so.rg * y[2] + (4.0 / 3.0) * so.rur * y[L.bV + 1]);
+                    double tbp = so.cs2 * so.k2H * y[0] + (-1.0 - so.R * so.T) * y[1] + so.R * so.T * y[2];
+                    double ek = exp(-so.kap);
+                    double gv = so.dk * ek;
+                    double gp = (so.dkp + so.dk * so.dk * so.invHc) * ek;
+                    double Hc = so.Hc;
+                    double alpha = Hc * (Hh + 6.0 * Ee) / (2.0 * k2);
+                    double rps = (4.0 / 3.0) * (so.rg * y[3] + so.rur * y[L.bV + 2]);
+                    double alphap = -2.0 * alpha + (y[L.rETA] - 4.5 * so.a * so.a * rps / k2) * so.invHc;
+                    double Pi = 2.0 * y[3] + (L.nG ? y[L.bG] + y[L.bG + 2] : 0.0);
+                    double eta = y[L.rETA];
+                    So[jo] = p.sw * gv * (0.25 * y[L.rDG] + Hc * alphap) +
+                             p.isw * (gv * (eta - Hc * alphap - 2.0 * Hc * alpha) +
+                                      2.0 * Hc * ek * (Ee - so.Hcp * alpha - Hc * alphap)) +
+                             p.dop * Hc * (gv * (tbp / k2 + alphap) + gp * (y[1] / k2 + alpha));
+                    So[n_tau + jo] = p.isw * ek * k * (Hc * alphap + 2.0 * Hc * alpha - eta);
+                    So[2 * n_tau + jo] = gv * Pi * 0.125;
+                }
+                wsync();
+                ++jo;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                w.y[r] = w.yn[r];
+                w.K[0][r] = w.K[5][r];
+            }
+            t = tn;
+            double Ef = fmax(E, 1e-10);
+            fac = 0.9 * pow(Ef, -b1) * pow(Ep, -b2) * pow(Epp, -b3);
+            fac = fmin(10.0, fmax(0.2, fac));
+            Epp = Ep;
+            Ep = Ef;
+        } else {
+            fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -0.25)));
+        }
+        h *= fac;
+        if (t < 0.0 && h < 1e-12) {
+            st = CMB_K_STEP_UNDERFLOW;
+            break;
+        }
+    }
+    if (gl == 0) {
+        for (; jo < n_tau; ++jo) {
+            So[jo] = 0.0;
+            So[n_tau + jo] = 0.0;
+            So[2 * n_tau + jo] = 0.0;
+        }
+        status[(size_t)c * n_k + ik] = st;
+        nsteps[(size_t)c * n_k + ik] = ns;
+    }
+}
+
+}  // namespace
+
+// Rows per lane and group size for a hierarchy of N rows: R = 5 and the
+// smallest power-of-two group holding the rows (at most one wavefront).
+static void group_shape(const DevPrec &p, int &R, int &G) {
+    int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + 3;
+    R = (N <= 32) ? 2 : 5;
+    int need = (N + R - 1) / R;
+    G = 4;
+    while (G < need) G <<= 1;
+}
+
+bool perturb2_supported(const DevPrec &p) {
+    int R, G;
+    group_shape(p, R, G);
+    return G <= 64;
+}
+
+int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
+                    int *d_status, int *d_nsteps, void *stream) {
+    int R, G;
+    group_shape(p, R, G);
+    if (G > 64) {
+        set_error("hierarchy too large for the cooperative perturbation kernel");
+        return CMB_E_UNSUPPORTED;
+    }
+    int spw = 64 / G;
+    long n_sys = (long)n_cosmo * n_k;
+    dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
+    size_t lds = (size_t)spw * (4 * G * R + AXN) * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    if (R == 2)
+        hipLaunchKernelGGL(perturb2_kernel<2>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,
+                           d_nsteps);
+    else
+        hipLaunchKernelGGL(perturb2_kernel<5>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,
+                           d_nsteps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+}  // namespace cmbhip

@@ -223,7 +223,8 @@ def test_max_steps_flag(ctx):
 
 
 def test_single_mode_and_lmax2(ctx):
-    """Degenerate sizes: one mode and ell_max = 2."""
+    """Degenerate sizes: one mode (its trapezoid k-weight is zero, so C_ell is
+    exactly zero on both sides) and ell_max = 2 with two modes."""
     import oracle as O
     import paper_2602_15104_amd as L
     wl = W.small_case(n_k=1, n_tau=30, ell_max=2, k_min=0.01, k_max=0.01)
@@ -232,6 +233,14 @@ def test_single_mode_and_lmax2(ctx):
     g = run_gpu(ctx, [tab], 2)
     r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, 2, True)
     assert src_err(g["S"][0], r["S"]) <= 1e-8
+    assert np.all(g["Cl"][0] == 0) and np.all(r["Cl"] == 0)
+    D = g["Delta"][0]
+    den = np.max(np.abs(r["DT"]))
+    assert np.max(np.abs(D[0] - r["DT"])) <= 1e-9 * den
+    wl.k = np.array([0.005, 0.01])
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    g = run_gpu(ctx, [tab], 2)
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, 2, True)
     tt, te, ee = cl_err(g["Cl"][0], r["Cl"])
     assert tt <= 1e-6 and ee <= 1e-6 and te <= 1e-6
 
@@ -259,3 +268,37 @@ def test_config1_full_size(ctx):
         tt, te, ee = cl_err(g["Cl"][0], Co)
         _say("cl err", tt, te, ee)
         assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+
+
+def test_lane_per_mode_variant_parity(ctx):
+    """The lane-per-mode perturbation kernel (CMBHIP_K1=lane) gives the same
+    sources as the oracle and as the default cooperative kernel."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=9, n_tau=80, ell_max=30, polarization=True)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    coop = run_gpu(ctx, [tab], wl.ell_max)
+    os.environ["CMBHIP_K1"] = "lane"
+    try:
+        lane = run_gpu(ctx, [tab], wl.ell_max)
+    finally:
+        del os.environ["CMBHIP_K1"]
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
+    assert src_err(lane["S"][0], r["S"]) <= 1e-8
+    assert src_err(coop["S"][0], lane["S"][0]) <= 1e-10
+    assert np.array_equal(lane["nsteps"], coop["nsteps"])
+
+
+def test_config1_repeat_bitwise(ctx):
+    """Two solves of the full-size TT/TE/EE workload after other kernels have
+    used the GPU: every mode finishes and the results repeat bit for bit."""
+    import paper_2602_15104_amd as L
+    wl = W.config1()
+    cosmos = W.perturbed_cosmologies(2, seed=99)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    a = run_gpu(ctx, tabs, wl.ell_max)
+    b = run_gpu(ctx, tabs, wl.ell_max)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["Cl"], b["Cl"])
