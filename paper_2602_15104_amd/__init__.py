@@ -22,10 +22,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CMBHIP_LIBRARY") or os.path.join(_HERE, "libcmbhip.so")
 
-if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libcmbhip.so not found at {LIB_PATH}; build it with `python -m paper_2602_15104_amd.build`")
 
-_lib = ctypes.CDLL(LIB_PATH)
+class _MissingLibrary:
+    """Stands in for the library until it is built; every use raises."""
+
+    def __getattr__(self, name):
+        raise RuntimeError(f"libcmbhip.so not found at {LIB_PATH}: build it with "
+                           f"`python -m paper_2602_15104_amd.build` (no CPU fallback exists)")
+
+
+_lib = ctypes.CDLL(LIB_PATH) if os.path.exists(LIB_PATH) else _MissingLibrary()
 
 CMB_OK = 0
 ERRORS = {1: "CMB_E_INVALID", 2: "CMB_E_CONFLICT", 3: "CMB_E_NEG_NMASSLESS", 4: "CMB_E_ROOT", 5: "CMB_E_DEVICE",
@@ -77,23 +83,29 @@ class CTableView(ctypes.Structure):
 
 
 _vp = ctypes.c_void_p
-_lib.cmb_abi_version.restype = ctypes.c_int
-_lib.cmb_defaults.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec)]
-_lib.cmb_last_error.restype = ctypes.c_char_p
-_lib.cmb_tables_build.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec), _dp, ctypes.c_int, ctypes.c_int,
-                                  ctypes.POINTER(_vp)]
-_lib.cmb_tables_destroy.argtypes = [_vp]
-_lib.cmb_tables_destroy.restype = None
-_lib.cmb_tables_export.argtypes = [_vp, ctypes.POINTER(CTableView)]
-_lib.cmb_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]
-_lib.cmb_ctx_destroy.argtypes = [_vp]
-_lib.cmb_ctx_destroy.restype = None
-_lib.cmb_solve_workspace_bytes.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
-_lib.cmb_solve_workspace_bytes.restype = ctypes.c_size_t
-_lib.cmb_perturb.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp]
-_lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
-_lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
-_lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+
+
+def _declare(lib):
+    lib.cmb_defaults.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec)]
+    lib.cmb_last_error.restype = ctypes.c_char_p
+    lib.cmb_tables_build.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec), _dp, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(_vp)]
+    lib.cmb_tables_destroy.argtypes = [_vp]
+    lib.cmb_tables_destroy.restype = None
+    lib.cmb_tables_export.argtypes = [_vp, ctypes.POINTER(CTableView)]
+    lib.cmb_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]
+    lib.cmb_ctx_destroy.argtypes = [_vp]
+    lib.cmb_ctx_destroy.restype = None
+    lib.cmb_solve_workspace_bytes.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+    lib.cmb_solve_workspace_bytes.restype = ctypes.c_size_t
+    lib.cmb_perturb.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+
+
+if not isinstance(_lib, _MissingLibrary):
+    _declare(_lib)
 
 
 def _check(rc: int, where: str):

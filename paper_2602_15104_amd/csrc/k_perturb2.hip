@@ -44,6 +44,16 @@ __device__ constexpr double Ke[6] = {
     0.25 - 61727.0 / 225920.0};
 constexpr double GAMMA = 0.25;
 
+// 1/b: hardware reciprocal refined by two Newton steps (relative error at the
+// level of rounding), shorter on the dependent path than IEEE division.
+__device__ inline double rcp(double b) {
+    // hardware estimate, then x (1 + e + e^2) with e = 1 - b x: the relative
+    // error of the estimate enters cubed
+    const double x = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, x, 1.0);
+    return fma(x, fma(e, e, e), x);
+}
+
 // Exchange point between the lanes of a wavefront: wait for this wave's LDS
 // operations to complete; the memory clobber keeps the compiler from moving
 // any load or store across it.  (A workgroup is one wavefront and LDS
@@ -202,20 +212,129 @@ __device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p) 
 }
 
 // LDS slab of one mode
+// Per-row record in LDS (STR doubles, 16-byte aligned so that neighbouring
+// fields pair into 128-bit accesses): stage rhs / solution, the
+// time-independent multipliers of the row, the scaled continuants of the
+// upward sweep and the coefficients of the downward one.
+constexpr int STR = 10;
+constexpr int F_RY = 0, F_CC = 1, F_CP = 2, F_CA = 3, F_M = 4, F_MN = 5, F_U = 6, F_V = 7, F_CD = 8;
+constexpr int PADR = 8;  // spare records before row 0 and after the last row
+
 struct Slab {
-    double *AL, *BE, *GA, *RY, *AX;
-    int NP;
+    double *base;  // record of row r at base + (r + PADR) * STR
+    double *AX;    // exchange area
+    __device__ double *rec(int row) const { return base + (row + PADR) * STR; }
+    __device__ double &ry(int row) const { return base[(row + PADR) * STR + F_RY]; }
 };
 
 constexpr int AXN = 64;  // exchange area doubles per mode
+// doubles of LDS per mode for NP rows
+__host__ __device__ constexpr int slab_doubles(int NP) { return (NP + 2 * PADR) * STR + AXN; }
+
+// Time-independent multipliers of a generic chain row (fifth row of its chain
+// onward): a = CA kH, c = CC kH, d = CD trunc - T (photon chains) or CD trunc,
+// and CP = -CC_j CA_{j+1} >= 0, so that -c_j a_{j+1} = (kH)^2 CP_j.  The first
+// four rows of each chain and the isolated rows get zeros; their entries come
+// from the full row formulas (top_coef).
+__device__ void row_static1(int row, const Lay &L, double &ca, double &cc, double &cd) {
+    ca = cc = cd = 0.0;
+    int ch, j, n;
+    if (row < L.bG) {
+        ch = 0;
+        j = row;
+        n = L.nF;
+    } else if (row < L.bV) {
+        ch = 1;
+        j = row - L.bG;
+        n = L.nG;
+    } else if (row < L.rDC) {
+        ch = 2;
+        j = row - L.bV;
+        n = L.nV;
+    } else {
+        return;
+    }
+    if (j < 4) return;
+    const int l = (ch == 0) ? j - 1 : j;
+    const double f2 = (l == 3 && ch != 1) ? 2.0 : 1.0;  // the l = 2 neighbour is stored as sigma = F_2 / 2
+    if (j == n - 1) {
+        ca = f2;
+        cd = -(l + 1.0);
+    } else {
+        ca = f2 * l / (2.0 * l + 1.0);
+        cc = -(l + 1.0) / (2.0 * l + 1.0);
+    }
+}
+
+__device__ void row_static(int row, const Lay &L, double &ca, double &cc, double &cd, double &cp) {
+    row_static1(row, L, ca, cc, cd);
+    double ca1, cc1, cd1;
+    row_static1(row + 1, L, ca1, cc1, cd1);
+    cp = (cc != 0.0) ? -cc * ca1 : 0.0;  // cc != 0 only when row + 1 is in the same chain
+}
+
+// Entries of the first four rows (j = 0..3) of chain type ty (0 photon T +
+// baryons, 1 photon polarisation, 2 massless neutrinos), in the form of
+// row_coef, evaluated for every type and selected without branching.
+__device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const DevPrec &p) {
+    RowCo f{0, 0, 0, 0, 0, 0}, gp{0, 0, 0, 0, 0, 0}, v{0, 0, 0, 0, 0, 0};
+    if (j == 0) {
+        f.c = -s.invHc;
+        f.uH = -0.5;
+        v.c = -(4.0 / 3.0) * s.invHc;
+        v.uH = -2.0 / 3.0;
+    } else if (j == 1) {
+        f.a = s.cs2 * s.k2H;
+        f.d = -1.0 - s.R * s.T;
+        f.c = s.R * s.T;
+        v.a = 0.25 * s.k2H;
+        v.c = -s.k2H;
+    } else if (j == 2) {
+        f.a = s.T;
+        f.d = -s.T;
+        f.c = -s.k2H;
+        v.a = (4.0 / 15.0) * s.invHc;
+        v.c = -0.3 * s.kH;
+        v.uH = 2.0 / 15.0;
+        v.uE = 0.8;
+    } else {
+        f.a = (4.0 / 15.0) * s.invHc;
+        f.c = -0.3 * s.kH;
+        f.uH = 2.0 / 15.0;
+        f.uE = 0.8;
+        f.d = p.lp > 0 ? -s.T : -0.9 * s.T;
+        f.uP = p.lp > 0 ? 0.05 * s.T : 0.0;
+        // neutrino l = 3 (its l = 2 neighbour is sigma = F_2 / 2)
+        const bool vlast = L.nV == 4;
+        v.a = vlast ? 2.0 * s.kH : (6.0 / 7.0) * s.kH;
+        v.c = vlast ? 0.0 : -(4.0 / 7.0) * s.kH;
+        v.d = vlast ? -4.0 * s.trunc : 0.0;
+    }
+    {  // polarisation, l = j
+        const double l = j;
+        const bool last = j == L.nG - 1;
+        gp.a = last ? s.kH : l / (2.0 * l + 1.0) * s.kH;
+        gp.c = last ? 0.0 : -(l + 1.0) / (2.0 * l + 1.0) * s.kH;
+        gp.d = last ? -s.T - (l + 1.0) * s.trunc : -s.T;
+        gp.uP = (j == 0) ? 0.5 * s.T : (j == 2 ? 0.1 * s.T : 0.0);
+    }
+    RowCo r;
+    r.a = ty == 0 ? f.a : (ty == 1 ? gp.a : v.a);
+    r.d = ty == 0 ? f.d : (ty == 1 ? gp.d : v.d);
+    r.c = ty == 0 ? f.c : (ty == 1 ? gp.c : v.c);
+    r.uH = ty == 0 ? f.uH : (ty == 1 ? gp.uH : v.uH);
+    r.uE = ty == 0 ? f.uE : (ty == 1 ? gp.uE : v.uE);
+    r.uP = ty == 0 ? f.uP : (ty == 1 ? gp.uP : v.uP);
+    return r;
+}
 
 // Couplings (h', eta', Pi) from the state rows held in RY.
 __device__ void aux_from_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, double &H, double &E,
                               double &P) {
-    const double *y = m.RY;
-    H = s.cH1 * y[L.rETA] + s.cH2 * (s.rc * y[L.rDC] + s.rb * y[0] + s.rg * y[L.rDG] + s.rur * y[L.bV]);
-    E = s.cE * (s.rb * y[1] + (4.0 / 3.0) * s.rg * y[2] + (4.0 / 3.0) * s.rur * y[L.bV + 1]);
-    P = (p.lp > 0) ? 2.0 * y[3] + y[L.bG] + y[L.bG + 2] : 0.0;
+    auto y = [&](int r) { return m.ry(r); };
+    H = s.cH1 * y(L.rETA) + s.cH2 * (s.rc * y(L.rDC) + s.rb * y(0) + s.rg * y(L.rDG) + s.rur * y(L.bV));
+    E = s.cE * (s.rb * y(1) + (4.0 / 3.0) * s.rg * y(2) + (4.0 / 3.0) * s.rur * y(L.bV + 1));
+    P = (p.lp > 0) ? 2.0 * y(3) + y(L.bG) + y(L.bG + 2) : 0.0;
 }
 
 template <int R>
@@ -223,7 +342,7 @@ struct Rows {
     double y[R], yn[R], K[6][R], rr[R];
 };
 
-// f = A y for this lane's rows; y already in m.RY (all rows), couplings in AX[0..2].
+// f = A y for this lane's rows; y already in the records (all rows), couplings in AX[0..2].
 template <int R>
 __device__ void rhs_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, int gl, double *f) {
     double H = m.AX[0], E = m.AX[1], P = m.AX[2];
@@ -236,12 +355,12 @@ __device__ void rhs_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec
             if (row < L.rDC) {
                 int n_start = (row < L.bG) ? 0 : (row < L.bV ? L.bG : L.bV);
                 int n_end = (row < L.bG) ? L.bG : (row < L.bV ? L.bV : L.rDC);
-                double ym = row > n_start ? m.RY[row - 1] : 0.0;
-                double yp = row + 1 < n_end ? m.RY[row + 1] : 0.0;
-                v = c.a * ym + c.d * m.RY[row] + c.c * yp;
-                if (row == 2) v += 0.25 * s.k2H * m.RY[L.rDG];
+                double ym = row > n_start ? m.ry(row - 1) : 0.0;
+                double yp = row + 1 < n_end ? m.ry(row + 1) : 0.0;
+                v = c.a * ym + c.d * m.ry(row) + c.c * yp;
+                if (row == 2) v += 0.25 * s.k2H * m.ry(L.rDG);
             } else if (row == L.rDG) {
-                v = -(4.0 / 3.0) * s.invHc * m.RY[2];
+                v = -(4.0 / 3.0) * s.invHc * m.ry(2);
             }
             v += c.uH * H + c.uE * E + c.uP * P;
         }
@@ -270,13 +389,24 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int NP = G * R;
     Slab m;
     {
-        double *base = lds + (size_t)grp * (4 * NP + AXN);
-        m.AL = base;
-        m.BE = base + NP;
-        m.GA = base + 2 * NP;
-        m.RY = base + 3 * NP;
-        m.AX = base + 4 * NP;
-        m.NP = NP;
+        double *base = lds + (size_t)grp * slab_doubles(NP);
+        m.base = base;
+        m.AX = base + (NP + 2 * PADR) * STR;
+        // every record, pads included, starts from zero; then the multipliers
+        for (int i = gl; i < (NP + 2 * PADR) * STR; i += G) base[i] = 0.0;
+        wsync();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            double ca, cc, cd, cp;
+            row_static(row, L, ca, cc, cd, cp);
+            double *q = m.rec(row);
+            q[F_CA] = ca;
+            q[F_CC] = cc;
+            q[F_CD] = cd;
+            q[F_CP] = cp;
+        }
+        wsync();
     }
     if (lin >= n_sys) return;  // whole group idle (no cross-group dependence)
     const int sys = n_sys - 1 - lin;  // largest k first, cosmology fastest
@@ -297,6 +427,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         cb = ch == 0 ? 0 : (ch == 1 && L.nG ? L.bG : L.bV);
         cn = ch == 0 ? L.nF : (ch == 1 && L.nG ? L.nG : L.nV);
     }
+    const int ty = ch == 0 ? 0 : (ch == 1 && L.nG ? 1 : 2);  // chain type swept by this lane
+    const bool photon_chain = ty != 2;
     const int N = L.N;
 
     Rows<R> w;
@@ -332,7 +464,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     // f0 = A y0
     auto full_rhs = [&](const double *yv, double *f, const Bk &bs) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) m.RY[gl * R + r] = yv[r];
+        for (int r = 0; r < R; ++r) m.ry(gl * R + r) = yv[r];
         wsync();
         if (gl == 0) {
             double H, E, P;
@@ -399,7 +531,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double b1 = (p.pcoeff + p.icoeff + p.dcoeff) / 4.0;
     const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / 4.0;
     const double b3 = p.dcoeff / 4.0;
-    double Ep = 1.0, Epp = 1.0;
+    double lEp = 0.0, lEpp = 0.0;  // logs of the previous two accepted error norms
     int ns = 0, st = CMB_K_OK;
 
     while (t < 0.0) {
@@ -421,76 +553,126 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             double hA[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
-            // (A) stage right-hand side and matrix entries of I - g A, row-parallel
+            const double gkH = g * s.kH, igkH = rcp(gkH), gT_ph = g * s.T, gtr = g * s.trunc;
+            // (A) stage right-hand sides, row-parallel
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                int row = gl * R + r;
                 double acc = w.y[r];
 #pragma unroll
                 for (int j = 0; j < 5; ++j) acc += hA[j] * w.K[j][r];
                 w.rr[r] = acc;
-                m.RY[row] = acc;
-                if (row < L.rDC) {
-                    RowCo cc = row_coef(row, L, s, p);
-                    m.AL[row] = -g * cc.a;
-                    m.BE[row] = 1.0 - g * cc.d;
-                    m.GA[row] = -g * cc.c;
-                }
+                m.ry(gl * R + r) = acc;
             }
             wsync();
             // (B) upward elimination of each chain, one lane per chain
             Aff top[4];
             if (sweeper) {
-                double bp = 0.0, rp = 0.0, alb = 0.0;
-                for (int j = cn - 1; j >= 4; --j) {
-                    int row = cb + j;
-                    double be = m.BE[row], ga = m.GA[row], rho = m.RY[row];
-                    if (j < cn - 1) {
-                        double mm = ga / bp;
-                        be -= mm * alb;
-                        rho -= mm * rp;
+                const double gT = photon_chain ? gT_ph : 0.0;
+                // Generic rows cn-1 .. 4 in continuant form.  With N_cn = 1,
+                // N_{cn+1} = 0, N_j = b_j N_{j+1} - c_j a_{j+1} N_{j+2} and
+                // T_j = r_j N_{j+1} - c_j T_{j+1}, the eliminated pivot and rhs
+                // are N_j / N_{j+1} and T_j / N_{j+1}.  Kept as M_j = N_j u^(j-cn),
+                // S_j = T_j u^(j+1-cn) with u = g kH, both recurrences take two
+                // operations a row:
+                //   M_j = (b_j / u) M_{j+1} + CP_j M_{j+2},  S_j = r_j M_{j+1} + CC_j S_{j+1}.
+                // Every M_j >= M_{j+1} > 0 (b_j >= 1, CP_j >= 0): no cancellation, no
+                // division on the dependent path; M, S are rescaled by 2^-332 per
+                // block whenever M passes 2^332.  Blocks of four rows always run
+                // whole: rows above the fifth only receive values nobody reads.
+                if (cn >= 5) {
+                    const double bq = (1.0 + gT) * igkH;
+                    double *rl = m.rec(cb + cn - 1);
+                    double M1 = fma(-gtr, rl[F_CD], 1.0 + gT) * igkH, M2 = 1.0, S1 = rl[F_RY];
+                    rl[F_M] = M1;
+                    rl[F_MN] = M2;
+                    rl[F_U] = S1;
+                    // prefetched (RY, CC) and CP of the next block, rows j0 .. j0-3
+                    double pr[4], pc[4], pp[4];
+                    const double *pb = m.rec(cb + cn - 5);  // row j0 - 3 of the first block
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pr[q] = pb[(3 - q) * STR + F_RY];
+                        pc[q] = pb[(3 - q) * STR + F_CC];
+                        pp[q] = pb[(3 - q) * STR + F_CP];
                     }
-                    bp = be;
-                    rp = rho;
-                    alb = m.AL[row];
-                    m.BE[row] = 1.0 / be;
-                    m.GA[row] = rho;
+                    for (int j0 = cn - 2; j0 >= 4; j0 -= 4) {
+                        double *cbk = m.rec(j0 - 3 + cb);
+                        double cr[4], cc[4], cp[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            cr[q] = pr[q];
+                            cc[q] = pc[q];
+                            cp[q] = pp[q];
+                        }
+                        const double *nb = cbk - 4 * STR;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            pr[q] = nb[(3 - q) * STR + F_RY];
+                            pc[q] = nb[(3 - q) * STR + F_CC];
+                            pp[q] = nb[(3 - q) * STR + F_CP];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double M0 = fma(bq, M1, cp[q] * M2);
+                            const double S0 = fma(cr[q], M1, cc[q] * S1);
+                            M2 = M1;
+                            M1 = M0;
+                            S1 = S0;
+                            double *rq = cbk + (3 - q) * STR;
+                            rq[F_M] = M1;
+                            rq[F_MN] = M2;
+                            rq[F_U] = S1;
+                        }
+                        const double f = M1 > 0x1p332 ? 0x1p-332 : 1.0;
+                        M1 *= f;
+                        M2 *= f;
+                        S1 *= f;
+                    }
+                }
+                // top rows 3 .. 0 carry the couplings; the row below is held as
+                // 1/pivot (ibp), eliminated rhs / pivot (rpi) and subdiagonal (alb)
+                double ibp = 0.0, rpi = 0.0, alb = 0.0;
+                if (cn >= 5) {
+                    const double *r4 = m.rec(cb + 4);
+                    const double iM = rcp(r4[F_M]) * igkH;
+                    ibp = r4[F_MN] * iM;
+                    rpi = r4[F_U] * iM;
+                    alb = -gkH * r4[F_CA];
                 }
                 double eH = 0.0, eE = 0.0, eP = 0.0;
                 double ib[4], r0[4], rH[4], rE[4], rP[4], al[4];
 #pragma unroll
                 for (int j = 3; j >= 0; --j) {
-                    int row = cb + j;
-                    RowCo cc = row_coef(row, L, s, p);
-                    double be = m.BE[row], ga = m.GA[row], rho = m.RY[row];
+                    const RowCo cc = top_coef(ty, j, L, s, p);
+                    double be = 1.0 - g * cc.d, ga = -g * cc.c, rho = m.ry(cb + j);
                     double xH = -g * cc.uH, xE = -g * cc.uE, xP = -g * cc.uP;
-                    if (ch == 0 && j == 2) {
-                        // delta_g = R_dg - g (4/3)/Hc theta_g - (2g/3) h' eliminated into theta_g
-                        double cl = g * 0.25 * s.k2H;
-                        be += cl * g * (4.0 / 3.0) * s.invHc;
-                        xH += cl * g * (2.0 / 3.0);
-                        rho += cl * m.RY[L.rDG];
+                    if (j == 2) {
+                        // photon chain: delta_g = R_dg - g (4/3)/Hc theta_g - (2g/3) h'
+                        // eliminated into the theta_g row
+                        const double cl = ty == 0 ? g * 0.25 * s.k2H : 0.0;
+                        be = fma(cl * g * (4.0 / 3.0), s.invHc, be);
+                        xH = fma(cl, g * (2.0 / 3.0), xH);
+                        rho = fma(cl, m.ry(L.rDG), rho);
                     }
-                    if (j < cn - 1) {
-                        double mm = ga / bp;
-                        be -= mm * alb;
-                        rho -= mm * rp;
-                        xH -= mm * eH;
-                        xE -= mm * eE;
-                        xP -= mm * eP;
-                    }
-                    bp = be;
-                    rp = rho;
+                    // (for a four-row chain the row below j = 3 is absent: ibp = rpi = 0)
+                    const double mm = ga * ibp;
+                    be = fma(-mm, alb, be);
+                    rho = fma(-ga, rpi, rho);
+                    xH = fma(-mm, eH, xH);
+                    xE = fma(-mm, eE, xE);
+                    xP = fma(-mm, eP, xP);
+                    ibp = rcp(be);
+                    rpi = rho * ibp;
                     eH = xH;
                     eE = xE;
                     eP = xP;
-                    alb = m.AL[row];
-                    ib[j] = 1.0 / be;
+                    alb = -g * cc.a;
+                    ib[j] = ibp;
                     r0[j] = rho;
                     rH[j] = xH;
                     rE[j] = xE;
                     rP[j] = xP;
-                    al[j] = m.AL[row];
+                    al[j] = alb;
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -509,6 +691,21 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 }
             }
             wsync();
+            // (D0) row lanes turn the continuants of the generic rows into the
+            // downward recurrence y_j = U_j - V_j y_{j-1}:
+            // U_j = T_j / N_j = S_j / (u M_j),  V_j = a_j N_{j+1} / N_j = -CA_j M_{j+1} / M_j
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double *q = m.rec(gl * R + r);
+                const double ca = q[F_CA];
+                if (ca != 0.0) {
+                    const double iM = rcp(q[F_M]);
+                    const double u = q[F_U] * iM * igkH;
+                    const double v = -ca * q[F_MN] * iM;
+                    q[F_U] = u;
+                    q[F_V] = v;
+                }
+            }
             // (C) couplings: 3x3 (2x2 without polarisation) system, one lane
             if (gl == 0) {
                 auto T = [&](int chn, int j) {
@@ -517,7 +714,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 };
                 const int cv = L.nG ? 2 : 1;
                 Aff F0 = T(0, 0), F1 = T(0, 1), F2 = T(0, 2), F3 = T(0, 3), V0 = T(cv, 0), V1 = T(cv, 1);
-                double Rdc = m.RY[L.rDC], Reta = m.RY[L.rETA], Rdg = m.RY[L.rDG];
+                double Rdc = m.ry(L.rDC), Reta = m.ry(L.rETA), Rdg = m.ry(L.rDG);
                 Aff dc{Rdc, -0.5 * g, 0.0, 0.0};
                 Aff eta{Reta, 0.0, g, 0.0};
                 double cg = -g * (4.0 / 3.0) * s.invHc;
@@ -554,29 +751,30 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                                 mm[piv][q] = tt;
                             }
                         }
+                        const double ipv = rcp(mm[cc][cc]);
 #pragma unroll
                         for (int rr = cc + 1; rr < 3; ++rr) {
-                            double f = mm[rr][cc] / mm[cc][cc];
+                            double f = mm[rr][cc] * ipv;
 #pragma unroll
                             for (int q = cc; q < 4; ++q) mm[rr][q] -= f * mm[cc][q];
                         }
                     }
-                    P = mm[2][3] / mm[2][2];
-                    E = (mm[1][3] - mm[1][2] * P) / mm[1][1];
-                    H = (mm[0][3] - mm[0][1] * E - mm[0][2] * P) / mm[0][0];
+                    P = mm[2][3] * rcp(mm[2][2]);
+                    E = (mm[1][3] - mm[1][2] * P) * rcp(mm[1][1]);
+                    H = (mm[0][3] - mm[0][1] * E - mm[0][2] * P) * rcp(mm[0][0]);
                 } else {
                     double a11 = 1.0 - eH.vH, a12 = -eH.vE, a21 = -eE.vH, a22 = 1.0 - eE.vE;
-                    double det = a11 * a22 - a12 * a21;
-                    H = (eH.v0 * a22 - a12 * eE.v0) / det;
-                    E = (a11 * eE.v0 - a21 * eH.v0) / det;
+                    const double idet = rcp(a11 * a22 - a12 * a21);
+                    H = (eH.v0 * a22 - a12 * eE.v0) * idet;
+                    E = (a11 * eE.v0 - a21 * eH.v0) * idet;
                     P = 0.0;
                 }
                 m.AX[0] = H;
                 m.AX[1] = E;
                 m.AX[2] = P;
-                m.RY[L.rDC] = aff(dc, H, E, P);
-                m.RY[L.rETA] = aff(eta, H, E, P);
-                m.RY[L.rDG] = aff(dg, H, E, P);
+                m.ry(L.rDC) = aff(dc, H, E, P);
+                m.ry(L.rETA) = aff(eta, H, E, P);
+                m.ry(L.rDG) = aff(dg, H, E, P);
             }
             wsync();
             // (D) downward substitution, one lane per chain
@@ -586,13 +784,42 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     yprev = aff(top[j], H, E, P);
-                    m.RY[cb + j] = yprev;
+                    m.ry(cb + j) = yprev;
                 }
-                for (int j = 4; j < cn; ++j) {
-                    int row = cb + j;
-                    double y = (m.GA[row] - m.AL[row] * yprev) * m.BE[row];
-                    m.RY[row] = y;
-                    yprev = y;
+                // generic rows: y_j = U_j - V_j y_{j-1}, four at a time with the
+                // next block's U, V already in flight (reads stay inside the slab)
+                // (rows past the chain end are computed too and their results
+                // sent to a spare record)
+                double pu[4], pv[4];
+                {
+                    const double *pb = m.rec(cb + 4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pu[q] = pb[q * STR + F_U];
+                        pv[q] = pb[q * STR + F_V];
+                    }
+                }
+                double *const spare = m.rec(-1);
+                for (int j0 = 4; j0 < cn; j0 += 4) {
+                    double cu[4], cv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        cu[q] = pu[q];
+                        cv[q] = pv[q];
+                    }
+                    double *cbk = m.rec(cb + j0);
+                    const double *nb = cbk + 4 * STR;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pu[q] = nb[q * STR + F_U];
+                        pv[q] = nb[q * STR + F_V];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        yprev = fma(-cv[q], yprev, cu[q]);
+                        double *dst = (j0 + q < cn) ? cbk + q * STR : spare;
+                        dst[F_RY] = yprev;
+                    }
                 }
             }
             wsync();
@@ -601,7 +828,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 int row = gl * R + r;
-                double y = row < N ? m.RY[row] : 0.0;
+                double y = row < N ? m.ry(row) : 0.0;
                 double kv = (y - w.rr[r]) * ig;
 #pragma unroll
                 for (int j = 1; j < 6; ++j)
@@ -637,30 +864,30 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 double h01 = -2.0 * th3 + 3.0 * th2, h11 = th3 - th2;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    m.RY[gl * R + r] = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
+                    m.ry(gl * R + r) = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
                 wsync();
                 if (gl == 0) {
                     Bk so;
                     bk_at(tb, p, k, lo[jo], so);
-                    const double *y = m.RY;
+                    auto y = [&](int r) { return m.ry(r); };
                     double k2 = k * k;
-                    double Hh = so.cH1 * y[L.rETA] +
-                                so.cH2 * (so.rc * y[L.rDC] + so.rb * y[0] + so.rg * y[L.rDG] + so.rur * y[L.bV]);
-                    double Ee = so.cE * (so.rb * y[1] + (4.0 / 3.0) * so.rg * y[2] + (4.0 / 3.0) * so.rur * y[L.bV + 1]);
-                    double tbp = so.cs2 * so.k2H * y[0] + (-1.0 - so.R * so.T) * y[1] + so.R * so.T * y[2];
+                    double Hh = so.cH1 * y(L.rETA) +
+                                so.cH2 * (so.rc * y(L.rDC) + so.rb * y(0) + so.rg * y(L.rDG) + so.rur * y(L.bV));
+                    double Ee = so.cE * (so.rb * y(1) + (4.0 / 3.0) * so.rg * y(2) + (4.0 / 3.0) * so.rur * y(L.bV + 1));
+                    double tbp = so.cs2 * so.k2H * y(0) + (-1.0 - so.R * so.T) * y(1) + so.R * so.T * y(2);
                     double ek = exp(-so.kap);
                     double gv = so.dk * ek;
                     double gp = (so.dkp + so.dk * so.dk * so.invHc) * ek;
                     double Hc = so.Hc;
                     double alpha = Hc * (Hh + 6.0 * Ee) / (2.0 * k2);
-                    double rps = (4.0 / 3.0) * (so.rg * y[3] + so.rur * y[L.bV + 2]);
-                    double alphap = -2.0 * alpha + (y[L.rETA] - 4.5 * so.a * so.a * rps / k2) * so.invHc;
-                    double Pi = 2.0 * y[3] + (L.nG ? y[L.bG] + y[L.bG + 2] : 0.0);
-                    double eta = y[L.rETA];
-                    So[jo] = p.sw * gv * (0.25 * y[L.rDG] + Hc * alphap) +
+                    double rps = (4.0 / 3.0) * (so.rg * y(3) + so.rur * y(L.bV + 2));
+                    double alphap = -2.0 * alpha + (y(L.rETA) - 4.5 * so.a * so.a * rps / k2) * so.invHc;
+                    double Pi = 2.0 * y(3) + (L.nG ? y(L.bG) + y(L.bG + 2) : 0.0);
+                    double eta = y(L.rETA);
+                    So[jo] = p.sw * gv * (0.25 * y(L.rDG) + Hc * alphap) +
                              p.isw * (gv * (eta - Hc * alphap - 2.0 * Hc * alpha) +
                                       2.0 * Hc * ek * (Ee - so.Hcp * alpha - Hc * alphap)) +
-                             p.dop * Hc * (gv * (tbp / k2 + alphap) + gp * (y[1] / k2 + alpha));
+                             p.dop * Hc * (gv * (tbp / k2 + alphap) + gp * (y(1) / k2 + alpha));
                     So[n_tau + jo] = p.isw * ek * k * (Hc * alphap + 2.0 * Hc * alpha - eta);
                     So[2 * n_tau + jo] = gv * Pi * 0.125;
                 }
@@ -673,11 +900,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 w.K[0][r] = w.K[5][r];
             }
             t = tn;
-            double Ef = fmax(E, 1e-10);
-            fac = 0.9 * pow(Ef, -b1) * pow(Ep, -b2) * pow(Epp, -b3);
+            const double lE = log(fmax(E, 1e-10));
+            fac = 0.9 * exp(-(b1 * lE + b2 * lEp + b3 * lEpp));
             fac = fmin(10.0, fmax(0.2, fac));
-            Epp = Ep;
-            Ep = Ef;
+            lEpp = lEp;
+            lEp = lE;
         } else {
             fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -0.25)));
         }
@@ -727,7 +954,7 @@ int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const
     int spw = 64 / G;
     long n_sys = (long)n_cosmo * n_k;
     dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
-    size_t lds = (size_t)spw * (4 * G * R + AXN) * sizeof(double);
+    size_t lds = (size_t)spw * slab_doubles(G * R) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     if (R == 2)
         hipLaunchKernelGGL(perturb2_kernel<2>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,
