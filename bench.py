@@ -13,6 +13,7 @@ resident in HBM).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,11 +29,17 @@ METRIC = "C_ell spectra/s at ell_max=2500 FP64, batched vs plain; p50/p99 solve 
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64: 256 CU x 2.4 GHz x 128 flop/cycle
 
 
-def k1_flops_per_step(N: int) -> float:
-    """Arithmetic of one ESDIRK step of the structured stage solve, counted
-    from the kernel (exp, sqrt, division = 1 flop): 208 per state row plus
-    about 2300 per step for background, coupling system and control."""
-    return 208.0 * N + 2300.0
+def k1_flops_per_step(N: int, n_chains: int = 3) -> float:
+    """Algorithmic arithmetic of one ESDIRK step (five implicit stages) of the
+    structured stage solve, N state rows (exp, sqrt, reciprocal = 1 flop):
+      stage right-hand sides  sum_s 2 s N              = 30 N
+      per stage and row: continuant sweep up 6, pivot reciprocals and
+      downward coefficients 5, downward sweep 2, K = (Y - R)/g 2  = 75 N
+      error estimate and norm                          = 19 N
+      per stage: top rows of each chain ~184, coupling solve ~150,
+      background ~60                                   = 5 (184 n_chains + 210)
+      step control                                     = 10"""
+    return 124.0 * N + 5.0 * (184.0 * n_chains + 210.0) + 10.0
 
 
 K1_FLOPS_PER_OUTPUT = 250.0  # Hermite interpolation of 12 rows + source formulas
@@ -58,11 +65,33 @@ def k2_flops(k: np.ndarray, chi: np.ndarray, ell_max: int) -> float:
     return float(triples * K2_FLOPS_PER_TRIPLE + np.sum(seed) * K2_FLOPS_PER_SEED_STEP)
 
 
+def k1_traffic(batch: int):
+    """HBM bytes per batched K1 launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when that summary was taken on
+    other kernel sources or another batch size."""
+    path = os.path.join(ROOT, "profiles", "perturb2_config1_b32_hbm.md")
+    if batch != 32 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ": " in line and not line.startswith(("|", " ", "#", "-")):
+            k, v = line.strip().split(": ", 1)
+            kv[k] = v
+    try:
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in kv["source_files"].split()))
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def cpu_baseline(wl, every: int = 8):
+def cpu_baseline(wl, every: int = 1):
     """The oracle as it stands on a bounded sample of the same workload:
     every `every`-th mode, all output times and multipoles; scaled to one
     full spectrum."""
@@ -78,8 +107,9 @@ def cpu_baseline(wl, every: int = 8):
     sec_per_spectrum = dt * scale
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / sec_per_spectrum, "unit": "spectra/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(idx)} of {len(wl.k)} modes (every {every}th), all {wl.n_tau} output times, "
-                      f"l<=2500; {dt:.1f} s measured, scaled x{scale:.0f} to one spectrum"}
+            "sample": f"one fiducial spectrum: {len(idx)} of {len(wl.k)} modes, all {wl.n_tau} output times, "
+                      f"l<=2500 (tables, perturbations, projection, quadrature); {dt:.1f} s measured"
+                      + (f", scaled x{scale:.0f}" if every > 1 else "")}
 
 
 def main():
@@ -90,10 +120,12 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--plain-reps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by cosmology "
-              f"with no communication, see DESIGN.md", file=sys.stderr)
+              f"with no communication", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -102,6 +134,15 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     dev = "cuda:0"
+    if args.copy_calibration:
+        n = 1 << 27  # 2^27 doubles = 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}))
+        return
     wl = W.config1()
     B = args.batch
     cosmos = W.perturbed_cosmologies(B, seed=20260215)
@@ -210,7 +251,8 @@ def main():
         "modes_not_ok": int(np.sum(status != 0)),
         "host_table_ms_per_cosmology": t_tables * 1e3,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": k1_traffic(B) if dom == "perturb" else None},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
