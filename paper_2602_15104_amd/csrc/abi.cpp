@@ -287,7 +287,8 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
         const cmbhip::Tables &t = tabs[i]->t;
         const cmb_prec &q = t.prec;
         if ((int)t.k.size() != b.n_k || (int)t.lna_src.size() != b.n_tau || q.ell_gamma != p.ell_gamma ||
-            q.ell_pol != p.ell_pol || q.ell_nu != p.ell_nu || q.n_q != p.n_q || q.max_steps != p.max_steps ||
+            q.ell_pol != p.ell_pol || q.ell_nu != p.ell_nu || t.q.size() != t0.q.size() ||
+            (!t.q.empty() && q.ell_ncdm != p.ell_ncdm) || q.max_steps != p.max_steps ||
             q.pcoeff != p.pcoeff || q.icoeff != p.icoeff || q.dcoeff != p.dcoeff || q.scale_sw != p.scale_sw ||
             q.scale_isw != p.scale_isw || q.scale_dop != p.scale_dop || q.scale_pol != p.scale_pol ||
             q.gravity_scale != p.gravity_scale || q.thomson_scale != p.thomson_scale) {
@@ -299,6 +300,8 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
     b.prec.lp = p.ell_pol;
     b.prec.ln = p.ell_nu;
     b.prec.max_steps = p.max_steps;
+    b.prec.nq = (int)t0.q.size();
+    b.prec.lq = b.prec.nq > 0 ? p.ell_ncdm : 0;
     b.prec.pcoeff = p.pcoeff;
     b.prec.icoeff = p.icoeff;
     b.prec.dcoeff = p.dcoeff;
@@ -316,7 +319,7 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t table_bytes(const cmbhip::Tables &t) {
-    size_t n = t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size();
+    size_t n = t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size() + 2 * t.q.size();
     return align256(n * sizeof(double));
 }
 
@@ -366,6 +369,10 @@ int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s
         x.lna_src = put(t.lna_src);
         x.chi_src = put(t.chi_src);
         x.w_src = put(t.w_src);
+        x.q = put(t.q);
+        x.W = put(t.W);
+        x.pref_ncdm = t.pref_ncdm;
+        x.m_over_T = t.m_over_T;
         x.L0 = t.L0;
         x.inv_dl = 1.0 / t.dl;
         x.n_tab = t.n_tab;
@@ -436,6 +443,10 @@ int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *
     if (rc) return rc;
     const char *variant = std::getenv("CMBHIP_K1");
     bool lane_variant = variant && std::string(variant) == "lane";
+    if (b.prec.nq > 0 && (lane_variant || !cmbhip::perturb2_supported(b.prec))) {
+        set_error("massive neutrinos are built into the cooperative perturbation kernel only");
+        return CMB_E_UNSUPPORTED;
+    }
     if (!lane_variant && cmbhip::perturb2_supported(b.prec)) {
         int32_t *ns2 = d_nsteps;
         if (!ns2) {

@@ -2,12 +2,15 @@
 // launchers of libcmbhip.  Not part of the public interface.
 #pragma once
 
+#include <limits>
 #include <string>
 #include <vector>
 
 #include "../../include/cmbhip.h"
 
 namespace cmbhip {
+
+constexpr int kMaxQ = 16;  // most momentum nodes of the massive-neutrino rule
 
 // Host tables of one cosmology (see tables.cpp).
 struct Tables {
@@ -38,10 +41,12 @@ struct DevTab {
     const double *lna_src;    // [n_tau]
     const double *chi_src;    // [n_tau]
     const double *w_src;      // [n_tau]
+    const double *q, *W;      // [n_q] massive-neutrino momentum rule (n_q = 0: none)
     double L0, inv_dl;
     int n_tab, n_k, n_tau, pad;
     double tau0, R_nu;
     double rt_g0, rt_ur0, rt_c0, rt_b0, rt_L;
+    double pref_ncdm, m_over_T;  // massive nu: rho = pref a^-4 sum W eps, eps = sqrt(q^2 + (a m/T)^2)
     double A_s, n_s, k_pivot;
     double rtol_small, rtol_large, atol_small, atol_large, k_split;
 };
@@ -49,6 +54,7 @@ struct DevTab {
 // Static options shared by one launch.
 struct DevPrec {
     int lg, lp, ln, max_steps;
+    int nq, lq;  // massive-neutrino momentum nodes (0: none) and their hierarchy cut-off
     double pcoeff, icoeff, dcoeff;
     double sw, isw, dop, pol, grav, thom;
 };

@@ -65,7 +65,12 @@ struct Bk {  // background and per-stage constants at one ln a
     double a, Hc, Hcp, rg, rur, rc, rb;
     double dk, dkp, kap, cs2, tau;
     double invHc, kH, k2H, T, R, trunc, cH1, cH2, cE;
+    double am, pn4;  // massive nu: a m/T and pref/a^4 (rho = pn4 sum W eps)
 };
+
+// massive-neutrino node energy and dln f0/dln q for f0 = 1/(e^q + 1)
+__device__ inline double eps_of(double q, double am) { return sqrt(fma(q, q, am * am)); }
+__device__ inline double dlnf0(double q) { return -q / (1.0 + exp(-q)); }
 
 __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, Bk &s) {
     double a = exp(lna);
@@ -77,6 +82,18 @@ __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, 
     s.rb = tb.rt_b0 / a3;
     double rho = s.rg + s.rur + s.rc + s.rb + tb.rt_L;
     double pr = (s.rg + s.rur) * (1.0 / 3.0) - tb.rt_L;
+    s.am = a * tb.m_over_T;
+    s.pn4 = tb.pref_ncdm / a4;
+    if (p.nq > 0) {  // App. C massive neutrinos, eq. mnu_sum
+        double sr = 0.0, sp = 0.0;
+        for (int i = 0; i < p.nq; ++i) {
+            const double q = tb.q[i], e = eps_of(q, s.am);
+            sr += tb.W[i] * e;
+            sp += tb.W[i] * q * q / e;
+        }
+        rho += s.pn4 * sr;
+        pr += s.pn4 * sp * (1.0 / 3.0);
+    }
     s.Hc = a * sqrt(rho);
     s.Hcp = s.Hc * (1.0 - 1.5 * (rho + pr) / rho);
     double u = (lna - tb.L0) * tb.inv_dl;
@@ -103,23 +120,55 @@ __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, 
     s.cE = p.grav * 1.5 * a2 * s.invHc / (k * k);
 }
 
-// Row layout: [F chain | G chain | nu chain | delta_c, eta, delta_g], padded.
+// Row layout: [F chain | G chain | nu chain | one Psi chain per momentum node |
+// delta_c, eta, delta_g], padded.
 struct Lay {
-    int N, nF, nG, nV, bG, bV, rDC, rETA, rDG, nch;
+    int N, nF, nG, nV, nQ, nPs, bG, bV, bM, rDC, rETA, rDG, nch;
 };
 __device__ inline Lay make_lay(const DevPrec &p) {
     Lay L;
     L.nF = p.lg + 2;
     L.nG = p.lp > 0 ? p.lp + 1 : 0;
     L.nV = p.ln + 1;
+    L.nQ = p.nq;
+    L.nPs = p.nq > 0 ? p.lq + 1 : 0;
     L.bG = L.nF;
     L.bV = L.nF + L.nG;
-    L.rDC = L.bV + L.nV;
+    L.bM = L.bV + L.nV;
+    L.rDC = L.bM + L.nQ * L.nPs;
     L.rETA = L.rDC + 1;
     L.rDG = L.rDC + 2;
     L.N = L.rDC + 3;
-    L.nch = L.nG ? 3 : 2;
+    L.nch = (L.nG ? 3 : 2) + L.nQ;
     return L;
+}
+
+// A multipole chain: type (0 photon temperature + baryons, 1 photon
+// polarisation, 2 massless neutrinos, 3 massive neutrinos at node iq), first
+// row and length.
+struct Chain {
+    int ty, cb, cn, iq;
+};
+// chain number ch (0 .. nch-1) in row order
+__device__ inline Chain chain_by_index(int ch, const Lay &L) {
+    const int n0 = L.nG ? 3 : 2;
+    if (ch == 0) return Chain{0, 0, L.nF, 0};
+    if (ch == 1 && L.nG) return Chain{1, L.bG, L.nG, 0};
+    if (ch < n0) return Chain{2, L.bV, L.nV, 0};
+    const int iq = ch - n0;
+    return Chain{3, L.bM + iq * L.nPs, L.nPs, iq};
+}
+// chain of a row (false for the isolated rows and the padding)
+__device__ inline bool chain_of(int row, const Lay &L, Chain &c) {
+    if (row < L.bG) c = Chain{0, 0, L.nF, 0};
+    else if (row < L.bV) c = Chain{1, L.bG, L.nG, 0};
+    else if (row < L.bM) c = Chain{2, L.bV, L.nV, 0};
+    else if (row < L.rDC) {
+        const int iq = (row - L.bM) / L.nPs;
+        c = Chain{3, L.bM + iq * L.nPs, L.nPs, iq};
+    } else
+        return false;
+    return true;
 }
 
 struct RowCo {
@@ -129,25 +178,36 @@ struct RowCo {
 // y'_row = a y_{row-1} + d y_row + c y_{row+1} + uH h' + uE eta' + uP Pi
 // (chain rows; for the isolated rows only the coupling terms are used and
 // the delta_g leaf term of the theta_g row is added by the caller).
-__device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p) {
+__device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p, const DevTab &tb) {
     RowCo r{0, 0, 0, 0, 0, 0};
-    int ch, j, n;
-    if (row < L.bG) {
-        ch = 0;
-        j = row;
-        n = L.nF;
-    } else if (row < L.bV) {
-        ch = 1;
-        j = row - L.bG;
-        n = L.nG;
-    } else if (row < L.rDC) {
-        ch = 2;
-        j = row - L.bV;
-        n = L.nV;
-    } else {
+    Chain cs;
+    if (!chain_of(row, L, cs)) {
         if (row == L.rDC) r.uH = -0.5;
         if (row == L.rETA) r.uE = 1.0;
         if (row == L.rDG) r.uH = -2.0 / 3.0;
+        return r;
+    }
+    const int ch = cs.ty, j = row - cs.cb, n = cs.cn;
+    if (ch == 3) {  // massive neutrinos at node q (App. C), speed v = q k / (eps Hc)
+        const double q = tb.q[cs.iq], v = q * s.kH / eps_of(q, s.am), dl = dlnf0(q);
+        if (j == n - 1) {
+            r.a = v;
+            r.d = -(j + 1.0) * s.trunc;
+        } else if (j == 0) {
+            r.c = -v;
+            r.uH = dl / 6.0;
+        } else if (j == 1) {
+            r.a = v / 3.0;
+            r.c = -2.0 * v / 3.0;
+        } else if (j == 2) {
+            r.a = 0.4 * v;
+            r.c = -0.6 * v;
+            r.uH = -dl / 15.0;
+            r.uE = -0.4 * dl;
+        } else {
+            r.a = j / (2.0 * j + 1.0) * v;
+            r.c = -(j + 1.0) / (2.0 * j + 1.0) * v;
+        }
         return r;
     }
     // generic multipole row: l from the chain, Thomson damping for photons
@@ -227,36 +287,27 @@ struct Slab {
     __device__ double &ry(int row) const { return base[(row + PADR) * STR + F_RY]; }
 };
 
-constexpr int AXN = 64;  // exchange area doubles per mode
+// exchange area per mode: couplings (4) and the 4 x 4 top-row affine maps of
+// every chain, rounded to an even count (16-byte alignment of the next slab)
+__host__ __device__ constexpr int ax_doubles(int nch) { return (4 + 16 * nch + 1) & ~1; }
 // doubles of LDS per mode for NP rows
-__host__ __device__ constexpr int slab_doubles(int NP) { return (NP + 2 * PADR) * STR + AXN; }
+__host__ __device__ constexpr int slab_doubles(int NP, int nch) { return (NP + 2 * PADR) * STR + ax_doubles(nch); }
 
 // Time-independent multipliers of a generic chain row (fifth row of its chain
-// onward): a = CA kH, c = CC kH, d = CD trunc - T (photon chains) or CD trunc,
+// onward): a = CA v, c = CC v, d = CD trunc - T (photon chains) or CD trunc,
+// with the chain's streaming rate v = kH (massive node: q kH / eps),
 // and CP = -CC_j CA_{j+1} >= 0, so that -c_j a_{j+1} = (kH)^2 CP_j.  The first
 // four rows of each chain and the isolated rows get zeros; their entries come
 // from the full row formulas (top_coef).
 __device__ void row_static1(int row, const Lay &L, double &ca, double &cc, double &cd) {
     ca = cc = cd = 0.0;
-    int ch, j, n;
-    if (row < L.bG) {
-        ch = 0;
-        j = row;
-        n = L.nF;
-    } else if (row < L.bV) {
-        ch = 1;
-        j = row - L.bG;
-        n = L.nG;
-    } else if (row < L.rDC) {
-        ch = 2;
-        j = row - L.bV;
-        n = L.nV;
-    } else {
-        return;
-    }
+    Chain cs;
+    if (!chain_of(row, L, cs)) return;
+    const int ch = cs.ty, j = row - cs.cb, n = cs.cn;
     if (j < 4) return;
     const int l = (ch == 0) ? j - 1 : j;
-    const double f2 = (l == 3 && ch != 1) ? 2.0 : 1.0;  // the l = 2 neighbour is stored as sigma = F_2 / 2
+    // the l = 2 neighbour of a photon-temperature or massless-neutrino l = 3 row is sigma = F_2 / 2
+    const double f2 = (l == 3 && (ch == 0 || ch == 2)) ? 2.0 : 1.0;
     if (j == n - 1) {
         ca = f2;
         cd = -(l + 1.0);
@@ -274,10 +325,11 @@ __device__ void row_static(int row, const Lay &L, double &ca, double &cc, double
 }
 
 // Entries of the first four rows (j = 0..3) of chain type ty (0 photon T +
-// baryons, 1 photon polarisation, 2 massless neutrinos), in the form of
-// row_coef, evaluated for every type and selected without branching.
-__device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const DevPrec &p) {
-    RowCo f{0, 0, 0, 0, 0, 0}, gp{0, 0, 0, 0, 0, 0}, v{0, 0, 0, 0, 0, 0};
+// baryons, 1 photon polarisation, 2 massless neutrinos, 3 massive neutrinos at
+// one momentum node), in the form of row_coef, evaluated for every type and
+// selected without branching.
+__device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const DevPrec &p, double vq, double dl) {
+    RowCo f{0, 0, 0, 0, 0, 0}, gp{0, 0, 0, 0, 0, 0}, v{0, 0, 0, 0, 0, 0}, m{0, 0, 0, 0, 0, 0};
     if (j == 0) {
         f.c = -s.invHc;
         f.uH = -0.5;
@@ -318,22 +370,61 @@ __device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const
         gp.d = last ? -s.T - (l + 1.0) * s.trunc : -s.T;
         gp.uP = (j == 0) ? 0.5 * s.T : (j == 2 ? 0.1 * s.T : 0.0);
     }
+    {  // massive neutrinos at one node: rate vq = q kH / eps, dl = dln f0/dln q
+        const bool last = j == L.nPs - 1;
+        if (j == 0) {
+            m.c = -vq;
+            m.uH = dl / 6.0;
+        } else if (j == 1) {
+            m.a = vq / 3.0;
+            m.c = -2.0 * vq / 3.0;
+        } else if (j == 2) {
+            m.a = 0.4 * vq;
+            m.c = -0.6 * vq;
+            m.uH = -dl / 15.0;
+            m.uE = -0.4 * dl;
+        } else {
+            m.a = last ? vq : (3.0 / 7.0) * vq;
+            m.c = last ? 0.0 : -(4.0 / 7.0) * vq;
+            m.d = last ? -4.0 * s.trunc : 0.0;
+        }
+    }
+    auto sel = [&](double a0, double a1, double a2, double a3) {
+        return ty == 0 ? a0 : (ty == 1 ? a1 : (ty == 2 ? a2 : a3));
+    };
     RowCo r;
-    r.a = ty == 0 ? f.a : (ty == 1 ? gp.a : v.a);
-    r.d = ty == 0 ? f.d : (ty == 1 ? gp.d : v.d);
-    r.c = ty == 0 ? f.c : (ty == 1 ? gp.c : v.c);
-    r.uH = ty == 0 ? f.uH : (ty == 1 ? gp.uH : v.uH);
-    r.uE = ty == 0 ? f.uE : (ty == 1 ? gp.uE : v.uE);
-    r.uP = ty == 0 ? f.uP : (ty == 1 ? gp.uP : v.uP);
+    r.a = sel(f.a, gp.a, v.a, m.a);
+    r.d = sel(f.d, gp.d, v.d, m.d);
+    r.c = sel(f.c, gp.c, v.c, m.c);
+    r.uH = sel(f.uH, gp.uH, v.uH, m.uH);
+    r.uE = sel(f.uE, gp.uE, v.uE, m.uE);
+    r.uP = sel(f.uP, gp.uP, v.uP, m.uP);
     return r;
 }
 
-// Couplings (h', eta', Pi) from the state rows held in RY.
-__device__ void aux_from_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, double &H, double &E,
-                              double &P) {
+// Massive-neutrino moments of a state held in the records (App. B.3 eq.
+// mnu_sum): delta rho, (rho + p) theta and (rho + p) sigma, in the units of rt.
+__device__ inline void ncdm_moments(const Slab &m, const Lay &L, const Bk &s, const DevTab &tb, double k,
+                                    double &drho, double &rpt, double &rps) {
+    drho = rpt = rps = 0.0;
+    for (int i = 0; i < L.nQ; ++i) {
+        const double q = tb.q[i], e = eps_of(q, s.am), w = s.pn4 * tb.W[i];
+        const int b = L.bM + i * L.nPs;
+        drho += w * e * m.ry(b);
+        rpt += w * k * q * m.ry(b + 1);
+        rps += w * (2.0 / 3.0) * q * q / e * m.ry(b + 2);
+    }
+}
+
+// Couplings (h', eta', Pi) from the state rows held in RY (App. B.3, eqs.
+// hprime and etaprime).
+__device__ void aux_from_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, const DevTab &tb,
+                              double k, double &H, double &E, double &P) {
     auto y = [&](int r) { return m.ry(r); };
-    H = s.cH1 * y(L.rETA) + s.cH2 * (s.rc * y(L.rDC) + s.rb * y(0) + s.rg * y(L.rDG) + s.rur * y(L.bV));
-    E = s.cE * (s.rb * y(1) + (4.0 / 3.0) * s.rg * y(2) + (4.0 / 3.0) * s.rur * y(L.bV + 1));
+    double drho, rpt, rps;
+    ncdm_moments(m, L, s, tb, k, drho, rpt, rps);
+    H = s.cH1 * y(L.rETA) + s.cH2 * (s.rc * y(L.rDC) + s.rb * y(0) + s.rg * y(L.rDG) + s.rur * y(L.bV) + drho);
+    E = s.cE * (s.rb * y(1) + (4.0 / 3.0) * s.rg * y(2) + (4.0 / 3.0) * s.rur * y(L.bV + 1) + rpt);
     P = (p.lp > 0) ? 2.0 * y(3) + y(L.bG) + y(L.bG + 2) : 0.0;
 }
 
@@ -344,19 +435,19 @@ struct Rows {
 
 // f = A y for this lane's rows; y already in the records (all rows), couplings in AX[0..2].
 template <int R>
-__device__ void rhs_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, int gl, double *f) {
+__device__ void rhs_rows(const Slab &m, const Lay &L, const Bk &s, const DevPrec &p, const DevTab &tb, int gl,
+                         double *f) {
     double H = m.AX[0], E = m.AX[1], P = m.AX[2];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int row = gl * R + r;
         double v = 0.0;
         if (row < L.N) {
-            RowCo c = row_coef(row, L, s, p);
-            if (row < L.rDC) {
-                int n_start = (row < L.bG) ? 0 : (row < L.bV ? L.bG : L.bV);
-                int n_end = (row < L.bG) ? L.bG : (row < L.bV ? L.bV : L.rDC);
-                double ym = row > n_start ? m.ry(row - 1) : 0.0;
-                double yp = row + 1 < n_end ? m.ry(row + 1) : 0.0;
+            RowCo c = row_coef(row, L, s, p, tb);
+            Chain cs;
+            if (chain_of(row, L, cs)) {
+                double ym = row > cs.cb ? m.ry(row - 1) : 0.0;
+                double yp = row + 1 < cs.cb + cs.cn ? m.ry(row + 1) : 0.0;
                 v = c.a * ym + c.d * m.ry(row) + c.c * yp;
                 if (row == 2) v += 0.25 * s.k2H * m.ry(L.rDG);
             } else if (row == L.rDG) {
@@ -389,7 +480,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int NP = G * R;
     Slab m;
     {
-        double *base = lds + (size_t)grp * slab_doubles(NP);
+        double *base = lds + (size_t)grp * slab_doubles(NP, L.nch);
         m.base = base;
         m.AX = base + (NP + 2 * PADR) * STR;
         // every record, pads included, starts from zero; then the multipliers
@@ -422,13 +513,12 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double *lo = tb.lna_src;
     const int ch = gl;  // chain handled by this lane in the sweeps
     const bool sweeper = ch < L.nch;
-    int cb = 0, cn = 0;  // chain start row and length
-    if (sweeper) {
-        cb = ch == 0 ? 0 : (ch == 1 && L.nG ? L.bG : L.bV);
-        cn = ch == 0 ? L.nF : (ch == 1 && L.nG ? L.nG : L.nV);
-    }
-    const int ty = ch == 0 ? 0 : (ch == 1 && L.nG ? 1 : 2);  // chain type swept by this lane
-    const bool photon_chain = ty != 2;
+    const Chain mych = sweeper ? chain_by_index(ch, L) : Chain{2, 0, 0, 0};
+    const int cb = mych.cb, cn = mych.cn, ty = mych.ty;  // chain start row, length, type
+    const bool photon_chain = ty < 2;
+    // massive node of this lane's chain: q and dln f0/dln q
+    const double q_ch = (ty == 3) ? tb.q[mych.iq] : 0.0;
+    const double dl_ch = (ty == 3) ? dlnf0(q_ch) : 0.0;
     const int N = L.N;
 
     Rows<R> w;
@@ -458,6 +548,15 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             if (row == L.rDC) v = 0.75 * dg;
             if (row == L.rDG) v = dg;
             if (row == L.rETA) v = 1.0 - (5.0 + 4.0 * Rn) / (12.0 * (15.0 + 4.0 * Rn)) * x * x;
+            if (row >= L.bM && row < L.rDC) {  // massive nu from the massless moments via dln f0/dln q
+                const int iq = (row - L.bM) / L.nPs, j = row - L.bM - iq * L.nPs;
+                const double q = tb.q[iq], dl = dlnf0(q);
+                const double tn = (23.0 + 4.0 * Rn) / (15.0 + 4.0 * Rn) * tg;
+                const double sn = 2.0 / (3.0 * (15.0 + 4.0 * Rn)) * x * x;
+                if (j == 0) v = -0.25 * dg * dl;
+                if (j == 1) v = -eps_of(q, s.am) / (3.0 * q * k) * tn * dl;
+                if (j == 2) v = -0.5 * sn * dl;
+            }
             w.y[r] = v;
         }
     }
@@ -468,13 +567,13 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         wsync();
         if (gl == 0) {
             double H, E, P;
-            aux_from_rows(m, L, bs, p, H, E, P);
+            aux_from_rows(m, L, bs, p, tb, k, H, E, P);
             m.AX[0] = H;
             m.AX[1] = E;
             m.AX[2] = P;
         }
         wsync();
-        rhs_rows<R>(m, L, bs, p, gl, f);
+        rhs_rows<R>(m, L, bs, p, tb, gl, f);
         wsync();
     };
     full_rhs(w.y, w.K[0], s);
@@ -553,7 +652,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             double hA[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
-            const double gkH = g * s.kH, igkH = rcp(gkH), gT_ph = g * s.T, gtr = g * s.trunc;
+            const double gkH = g * s.kH, gT_ph = g * s.T, gtr = g * s.trunc;
             // (A) stage right-hand sides, row-parallel
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -566,26 +665,29 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             wsync();
             // (B) upward elimination of each chain, one lane per chain
             Aff top[4];
+            double vq = 0.0;  // streaming rate of this lane's massive node
             if (sweeper) {
                 const double gT = photon_chain ? gT_ph : 0.0;
+                if (ty == 3) vq = q_ch * s.kH / eps_of(q_ch, s.am);
+                const double u = ty == 3 ? g * vq : gkH, iu = rcp(u);
                 // Generic rows cn-1 .. 4 in continuant form.  With N_cn = 1,
                 // N_{cn+1} = 0, N_j = b_j N_{j+1} - c_j a_{j+1} N_{j+2} and
                 // T_j = r_j N_{j+1} - c_j T_{j+1}, the eliminated pivot and rhs
                 // are N_j / N_{j+1} and T_j / N_{j+1}.  Kept as M_j = N_j u^(j-cn),
-                // S_j = T_j u^(j+1-cn) with u = g kH, both recurrences take two
-                // operations a row:
+                // S_j = T_j u^(j+1-cn) with u = g v (v the chain's streaming rate),
+                // both recurrences take two operations a row (S_j / u is stored):
                 //   M_j = (b_j / u) M_{j+1} + CP_j M_{j+2},  S_j = r_j M_{j+1} + CC_j S_{j+1}.
                 // Every M_j >= M_{j+1} > 0 (b_j >= 1, CP_j >= 0): no cancellation, no
                 // division on the dependent path; M, S are rescaled by 2^-332 per
                 // block whenever M passes 2^332.  Blocks of four rows always run
                 // whole: rows above the fifth only receive values nobody reads.
                 if (cn >= 5) {
-                    const double bq = (1.0 + gT) * igkH;
+                    const double bq = (1.0 + gT) * iu;
                     double *rl = m.rec(cb + cn - 1);
-                    double M1 = fma(-gtr, rl[F_CD], 1.0 + gT) * igkH, M2 = 1.0, S1 = rl[F_RY];
+                    double M1 = fma(-gtr, rl[F_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
                     rl[F_M] = M1;
                     rl[F_MN] = M2;
-                    rl[F_U] = S1;
+                    rl[F_U] = S1 * iu;
                     // prefetched (RY, CC) and CP of the next block, rows j0 .. j0-3
                     double pr[4], pc[4], pp[4];
                     const double *pb = m.rec(cb + cn - 5);  // row j0 - 3 of the first block
@@ -621,7 +723,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                             double *rq = cbk + (3 - q) * STR;
                             rq[F_M] = M1;
                             rq[F_MN] = M2;
-                            rq[F_U] = S1;
+                            rq[F_U] = S1 * iu;
                         }
                         const double f = M1 > 0x1p332 ? 0x1p-332 : 1.0;
                         M1 *= f;
@@ -634,16 +736,16 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 double ibp = 0.0, rpi = 0.0, alb = 0.0;
                 if (cn >= 5) {
                     const double *r4 = m.rec(cb + 4);
-                    const double iM = rcp(r4[F_M]) * igkH;
-                    ibp = r4[F_MN] * iM;
+                    const double iM = rcp(r4[F_M]);
+                    ibp = r4[F_MN] * iM * iu;
                     rpi = r4[F_U] * iM;
-                    alb = -gkH * r4[F_CA];
+                    alb = -u * r4[F_CA];
                 }
                 double eH = 0.0, eE = 0.0, eP = 0.0;
                 double ib[4], r0[4], rH[4], rE[4], rP[4], al[4];
 #pragma unroll
                 for (int j = 3; j >= 0; --j) {
-                    const RowCo cc = top_coef(ty, j, L, s, p);
+                    const RowCo cc = top_coef(ty, j, L, s, p, vq, dl_ch);
                     double be = 1.0 - g * cc.d, ga = -g * cc.c, rho = m.ry(cb + j);
                     double xH = -g * cc.uH, xE = -g * cc.uE, xP = -g * cc.uP;
                     if (j == 2) {
@@ -700,7 +802,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 const double ca = q[F_CA];
                 if (ca != 0.0) {
                     const double iM = rcp(q[F_M]);
-                    const double u = q[F_U] * iM * igkH;
+                    const double u = q[F_U] * iM;
                     const double v = -ca * q[F_MN] * iM;
                     q[F_U] = u;
                     q[F_V] = v;
@@ -729,6 +831,20 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 eE.vH = s.cE * (s.rb * F1.vH + f43 * s.rg * F2.vH + f43 * s.rur * V1.vH);
                 eE.vE = s.cE * (s.rb * F1.vE + f43 * s.rg * F2.vE + f43 * s.rur * V1.vE);
                 eE.vP = s.cE * (s.rb * F1.vP + f43 * s.rg * F2.vP + f43 * s.rur * V1.vP);
+                // massive neutrinos: delta rho from Psi_0, (rho + p) theta from Psi_1 of every node
+                for (int i = 0; i < L.nQ; ++i) {
+                    const double q = tb.q[i], w = s.pn4 * tb.W[i];
+                    const double wh = s.cH2 * w * eps_of(q, s.am), we = s.cE * w * k * q;
+                    const Aff P0 = T(cv + 1 + i, 0), P1 = T(cv + 1 + i, 1);
+                    eH.v0 = fma(wh, P0.v0, eH.v0);
+                    eH.vH = fma(wh, P0.vH, eH.vH);
+                    eH.vE = fma(wh, P0.vE, eH.vE);
+                    eH.vP = fma(wh, P0.vP, eH.vP);
+                    eE.v0 = fma(we, P1.v0, eE.v0);
+                    eE.vH = fma(we, P1.vH, eE.vH);
+                    eE.vE = fma(we, P1.vE, eE.vE);
+                    eE.vP = fma(we, P1.vP, eE.vP);
+                }
                 double H, E, P;
                 if (L.nG) {
                     Aff G0 = T(1, 0), G2 = T(1, 2);
@@ -871,16 +987,19 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     bk_at(tb, p, k, lo[jo], so);
                     auto y = [&](int r) { return m.ry(r); };
                     double k2 = k * k;
-                    double Hh = so.cH1 * y(L.rETA) +
-                                so.cH2 * (so.rc * y(L.rDC) + so.rb * y(0) + so.rg * y(L.rDG) + so.rur * y(L.bV));
-                    double Ee = so.cE * (so.rb * y(1) + (4.0 / 3.0) * so.rg * y(2) + (4.0 / 3.0) * so.rur * y(L.bV + 1));
+                    double drho, rpt, rpsn;
+                    ncdm_moments(m, L, so, tb, k, drho, rpt, rpsn);
+                    double Hh = so.cH1 * y(L.rETA) + so.cH2 * (so.rc * y(L.rDC) + so.rb * y(0) + so.rg * y(L.rDG) +
+                                                               so.rur * y(L.bV) + drho);
+                    double Ee = so.cE *
+                                (so.rb * y(1) + (4.0 / 3.0) * so.rg * y(2) + (4.0 / 3.0) * so.rur * y(L.bV + 1) + rpt);
                     double tbp = so.cs2 * so.k2H * y(0) + (-1.0 - so.R * so.T) * y(1) + so.R * so.T * y(2);
                     double ek = exp(-so.kap);
                     double gv = so.dk * ek;
                     double gp = (so.dkp + so.dk * so.dk * so.invHc) * ek;
                     double Hc = so.Hc;
                     double alpha = Hc * (Hh + 6.0 * Ee) / (2.0 * k2);
-                    double rps = (4.0 / 3.0) * (so.rg * y(3) + so.rur * y(L.bV + 2));
+                    double rps = (4.0 / 3.0) * (so.rg * y(3) + so.rur * y(L.bV + 2)) + rpsn;
                     double alphap = -2.0 * alpha + (y(L.rETA) - 4.5 * so.a * so.a * rps / k2) * so.invHc;
                     double Pi = 2.0 * y(3) + (L.nG ? y(L.bG) + y(L.bG + 2) : 0.0);
                     double eta = y(L.rETA);
@@ -930,9 +1049,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 // Rows per lane and group size for a hierarchy of N rows: R = 5 and the
 // smallest power-of-two group holding the rows (at most one wavefront).
 static void group_shape(const DevPrec &p, int &R, int &G) {
-    int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + 3;
+    int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + p.nq * (p.nq > 0 ? p.lq + 1 : 0) + 3;
+    const int nch = (p.lp > 0 ? 3 : 2) + p.nq;  // one sweeping lane per chain
     R = (N <= 32) ? 2 : 5;
     int need = (N + R - 1) / R;
+    if (need < nch) need = nch;
     G = 4;
     while (G < need) G <<= 1;
 }
@@ -940,7 +1061,8 @@ static void group_shape(const DevPrec &p, int &R, int &G) {
 bool perturb2_supported(const DevPrec &p) {
     int R, G;
     group_shape(p, R, G);
-    return G <= 64;
+    const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
+    return G <= 64 && (64 / G) * slab_doubles(G * R, nch) * sizeof(double) <= 65536 && p.nq <= kMaxQ;
 }
 
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
@@ -954,7 +1076,8 @@ int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const
     int spw = 64 / G;
     long n_sys = (long)n_cosmo * n_k;
     dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
-    size_t lds = (size_t)spw * slab_doubles(G * R) * sizeof(double);
+    const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
+    size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     if (R == 2)
         hipLaunchKernelGGL(perturb2_kernel<2>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,

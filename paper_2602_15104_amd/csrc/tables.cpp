@@ -92,6 +92,145 @@ struct Model {
 
 static double inv_hbarc3() { return 1.0 / cube(kHbarcEvCm); }
 
+// ---------------------------------------------------------------------------
+// n-node Gauss rule for  int_0^inf dq q^2/(e^q+1) g(q)  (the massive-neutrino
+// momentum integrals of App. B.3, eq. mnu_sum, with more nodes than the paper's
+// rules).  The weight is discretised by composite Gauss-Legendre on [0, 120]
+// (beyond, q^(2n+2) e^-q is below 1e-17 of its peak for n <= 16); the
+// recurrence coefficients of its monic orthogonal polynomials come from the
+// discretised Stieltjes procedure (Gautschi 1982), and nodes and weights from
+// the eigen-decomposition of the Jacobi matrix (Golub & Welsch 1969) by the
+// implicit QL method with Wilkinson shifts.  All in long double.
+// ---------------------------------------------------------------------------
+static void gauss_legendre(int m, std::vector<long double> &x, std::vector<long double> &w) {
+    x.assign(m, 0.0L);
+    w.assign(m, 0.0L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < m; ++i) {
+        long double z = std::cos(pi * (i + 0.75L) / (m + 0.5L)), dp = 0.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1.0L, p1 = z;  // P_0, P_1
+            for (int j = 2; j <= m; ++j) {
+                long double p2 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (z * p1 - p0) / (z * z - 1.0L);  // P_m'
+            long double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-19L) break;
+        }
+        x[i] = z;
+        w[i] = 2.0L / ((1.0L - z * z) * dp * dp);
+    }
+}
+
+// eigenvalues d and first eigenvector components z0 of the symmetric
+// tridiagonal matrix (d on the diagonal, e[i] between i and i+1)
+static bool tridiag_eigen(std::vector<long double> &d, std::vector<long double> e, std::vector<long double> &z0) {
+    const int n = (int)d.size();
+    std::vector<long double> Z((size_t)n * n, 0.0L);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0L;
+    e.resize(n, 0.0L);
+    e[n - 1] = 0.0L;
+    const long double eps = std::numeric_limits<long double>::epsilon();
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+            int mm = l;
+            for (; mm < n - 1; ++mm) {
+                long double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
+                if (std::fabs(e[mm]) <= eps * dd) break;
+            }
+            if (mm == l) break;
+            if (iter > 200) return false;
+            // Wilkinson shift from the leading 2x2 block, then a chase of
+            // plane rotations from the bottom of the unreduced block upwards
+            long double g = (d[l + 1] - d[l]) / (2.0L * e[l]);
+            long double r = std::hypot(g, 1.0L);
+            g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            long double s = 1.0L, c = 1.0L, p = 0.0L;
+            int i = mm - 1;
+            bool deflated = false;
+            for (; i >= l; --i) {
+                long double f = s * e[i], b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0L) {
+                    d[i + 1] -= p;
+                    e[mm] = 0.0L;
+                    deflated = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0L * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                for (int kq = 0; kq < n; ++kq) {
+                    long double t = Z[(size_t)kq * n + i + 1];
+                    Z[(size_t)kq * n + i + 1] = s * Z[(size_t)kq * n + i] + c * t;
+                    Z[(size_t)kq * n + i] = c * Z[(size_t)kq * n + i] - s * t;
+                }
+            }
+            if (deflated) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[mm] = 0.0L;
+        }
+    }
+    z0.assign(n, 0.0L);
+    for (int i = 0; i < n; ++i) z0[i] = Z[i];  // first row of Z: first components of the eigenvectors
+    return true;
+}
+
+static bool fermi_dirac_rule(int n, std::vector<double> &q, std::vector<double> &W) {
+    // discretised weight
+    std::vector<long double> gx, gw, x, w;
+    gauss_legendre(24, gx, gw);
+    const int panels = 120;
+    for (int pnl = 0; pnl < panels; ++pnl)
+        for (int i = 0; i < 24; ++i) {
+            long double t = pnl + 0.5L * (gx[i] + 1.0L);
+            x.push_back(t);
+            w.push_back(0.5L * gw[i] * t * t / (std::exp(t) + 1.0L));
+        }
+    // Stieltjes: p_{j+1} = (x - alpha_j) p_j - beta_j p_{j-1}
+    const size_t M = x.size();
+    std::vector<long double> pm(M, 0.0L), pc(M, 1.0L), alpha(n), beta(n);
+    long double norm_prev = 1.0L;
+    for (int j = 0; j < n; ++j) {
+        long double nrm = 0.0L, xn = 0.0L;
+        for (size_t k = 0; k < M; ++k) {
+            long double v = w[k] * pc[k] * pc[k];
+            nrm += v;
+            xn += v * x[k];
+        }
+        alpha[j] = xn / nrm;
+        beta[j] = (j == 0) ? nrm : nrm / norm_prev;
+        norm_prev = nrm;
+        for (size_t k = 0; k < M; ++k) {
+            long double pn = (x[k] - alpha[j]) * pc[k] - (j == 0 ? 0.0L : beta[j]) * pm[k];
+            pm[k] = pc[k];
+            pc[k] = pn;
+        }
+    }
+    std::vector<long double> d(alpha), e(n, 0.0L), z0;
+    for (int j = 0; j + 1 < n; ++j) e[j] = std::sqrt(beta[j + 1]);
+    if (!tridiag_eigen(d, e, z0)) return false;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
+    q.resize(n);
+    W.resize(n);
+    for (int i = 0; i < n; ++i) {
+        q[i] = (double)d[order[i]];
+        W[i] = (double)(beta[0] * z0[order[i]] * z0[order[i]]);
+    }
+    return true;
+}
+
 // root of x^2 + B x - C = 0 with C >= 0, stable form
 static double pos_root(double B, double C) { return 2.0 * C / (B + std::sqrt(B * B + 4.0 * C)); }
 
@@ -245,7 +384,10 @@ int build_tables(const cmb_cosmo &cin, const cmb_prec &p, const double *k, int n
         return fail(CMB_E_CONFLICT, "tau_reio and z_reio both given");
     if (!std::isfinite(c.tau_reio) && !std::isfinite(c.z_reio))
         return fail(CMB_E_INVALID, "one of tau_reio, z_reio must be given");
-    if (c.N_nu_massive > 0 || p.n_q > 0) return fail(CMB_E_UNSUPPORTED, "massive neutrinos are not built in yet");
+    const bool massive = c.N_nu_massive > 0;
+    if (massive && (!(p.n_q >= 1 && p.n_q <= kMaxQ) || p.ell_ncdm < 3 || !std::isfinite(c.m_nu_massive) ||
+                    c.m_nu_massive < 0 || !finite_pos(c.T_nu_massive)))
+        return fail(CMB_E_INVALID, "massive neutrinos need 1 <= n_q <= 16, ell_ncdm >= 3, m >= 0 and T > 0");
 
     Model m;
     m.c = c;
@@ -273,6 +415,13 @@ int build_tables(const cmb_cosmo &cin, const cmb_prec &p, const double *k, int n
         if (m.N_ml < 0) return fail(CMB_E_INVALID, "N_nu_massless < 0");
     }
     m.Neff = m.N_ml * per_ml + m.N_n * per_m;
+    if (massive) {
+        // rho = (N / pi^2) T^4 a^-4 sum_i W_i eps_i  (two helicity states per species)
+        if (!fermi_dirac_rule(p.n_q, m.q, m.W)) return fail(CMB_E_INVALID, "momentum rule did not converge");
+        const double Tm = c.T_nu_massive * c.TCMB0;
+        m.m_over_T = c.m_nu_massive / Tm;
+        m.pref_n = m.N_n / (kPi * kPi) * Tm * Tm * Tm * Tm * to_rt;
+    }
     double Tml = c.T_nu_massless * c.TCMB0;
     m.rt_ur0 = m.N_ml * 7.0 * kPi * kPi / 120.0 * Tml * Tml * Tml * Tml * to_rt;
     {
@@ -280,8 +429,11 @@ int build_tables(const cmb_cosmo &cin, const cmb_prec &p, const double *k, int n
         m.ncdm(1.0, rn, pn);
         m.rt_L = m.H0 * m.H0 - (m.rt_g0 + m.rt_ur0 + m.rt_m0 + rn);
     }
-    m.rt_rad_early = m.rt_g0 + m.rt_ur0;
-    m.R_nu = m.rt_ur0 / m.rt_rad_early;
+    // early-time radiation, with the massive species still relativistic
+    double ncdm_rel = 0.0;
+    for (size_t i = 0; i < m.q.size(); ++i) ncdm_rel += m.pref_n * m.W[i] * m.q[i];
+    m.rt_rad_early = m.rt_g0 + m.rt_ur0 + ncdm_rel;
+    m.R_nu = (m.rt_ur0 + ncdm_rel) / m.rt_rad_early;
     m.Y = c.YHe;
     m.fHe = c.YHe * kMH / ((1.0 - c.YHe) * kMHe);
     m.nH0 = (1.0 - c.YHe) * c.omega_b * rho_crit_h2 / kMH;

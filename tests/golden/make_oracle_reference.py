@@ -1,11 +1,14 @@
-"""Write the oracle's config-1 spectrum used by the GPU parity test.
+"""Write the oracle spectra used by the GPU parity tests at full size.
 
-    python tests/golden/make_oracle_reference.py
+    python tests/golden/make_oracle_reference.py [config1] [config2]
 
 Calls only the CPU oracle (package ``oracle``) and the seeded workload
-generator; re-run it whenever the oracle's arithmetic changes.  Output:
-tests/golden/oracle_config1_cl.npy, C_ell[3][2501] (TT, TE, EE) for the
-fiducial cosmology of the 400-mode, 2000-output-time, l <= 2500 workload.
+generator; re-run it whenever the oracle's arithmetic changes.  Outputs, for
+the fiducial cosmology of each workload, C_ell[3][2501] (TT, TE, EE):
+  tests/golden/oracle_config1_cl.npy  400 modes, 2000 output times, l <= 2500
+  tests/golden/oracle_config2_cl.npy  the same with one massive neutrino
+                                      (12 momentum nodes, l_ncdm = 17), 600 modes
+plus, for config 2, the per-mode step counts (oracle_config2_nsteps.npy).
 """
 import os
 import sys
@@ -20,14 +23,18 @@ import cmb_workloads as W  # noqa: E402
 import oracle as O  # noqa: E402
 
 
-def main():
-    wl = W.config1()
-    t0 = time.time()
-    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
-    assert np.all(r["status"] == 0)
-    np.save(os.path.join(HERE, "oracle_config1_cl.npy"), r["Cl"])
-    print(f"wrote oracle_config1_cl.npy in {time.time() - t0:.1f} s; mean steps {r['nsteps'].mean():.1f}")
+def main(which):
+    for name in which:
+        wl = getattr(W, name)()
+        t0 = time.time()
+        r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
+        assert np.all(r["status"] == 0)
+        np.save(os.path.join(HERE, f"oracle_{name}_cl.npy"), r["Cl"])
+        if name == "config2":
+            np.save(os.path.join(HERE, f"oracle_{name}_nsteps.npy"), np.asarray(r["nsteps"], dtype=np.int32))
+        print(f"wrote oracle_{name}_cl.npy in {time.time() - t0:.1f} s; mean steps {r['nsteps'].mean():.1f}",
+              flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:] or ["config1", "config2"])

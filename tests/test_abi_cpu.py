@@ -107,7 +107,7 @@ def _pair(wl):
     return to, tp
 
 
-@pytest.mark.parametrize("name", ["config0", "config1", "box"])
+@pytest.mark.parametrize("name", ["config0", "config1", "config2", "box"])
 def test_table_parity_with_oracle(name):
     """Row a1: the library's host tables against the oracle's, built by
     independent code from the same discretisation.  Agreement is at the
@@ -118,6 +118,9 @@ def test_table_parity_with_oracle(name):
     elif name == "config1":
         wl = W.config1()
         wl.k = wl.k[::20].copy()
+    elif name == "config2":
+        wl = W.config2()
+        wl.k = wl.k[::30].copy()
     else:
         wl = W.small_case(n_k=8, k_min=1e-5, k_max=0.5)
         wl.cosmo.update(W.box_cosmologies(1, seed=11)[0])
@@ -140,16 +143,27 @@ def test_table_parity_with_oracle(name):
         assert np.max(np.abs(tp["M_" + col] - to.M[key])) < 1e-13 * scale, col
     assert abs(tp["R_nu"] - to.bg.R_nu) < 1e-14
     assert abs(tp["rt_L"] / to.bg.rt_L - 1) < 1e-13
+    # massive-neutrino momentum rule (App. B.3, eq. mnu_sum): library's
+    # Stieltjes/QL generator against the oracle's Golub-Welsch in 60 digits
+    assert tp["n_q"] == len(to.bg.q)
+    if tp["n_q"]:
+        np.testing.assert_allclose(tp["q"], to.bg.q, rtol=1e-13)
+        np.testing.assert_allclose(tp["W"], to.bg.W, rtol=1e-13)
+        assert abs(tp["pref_ncdm"] / to.bg.pref_ncdm - 1) < 1e-14
+        assert abs(tp["m_over_T"] / to.bg.m_over_T - 1) < 1e-14
 
 
-def test_massive_neutrinos_reported_unsupported(lib):
+def test_massive_neutrinos_need_nodes(lib):
+    """A massive species without momentum nodes (or with more than the
+    library holds) is rejected, not silently dropped."""
     wl = W.small_case()
     c = dict(wl.cosmo)
     c["N_nu_massless"] = float("nan")
     c["Neff"] = 3.044
     c["N_nu_massive"] = 1.0
-    p = dict(wl.prec)
-    p["n_q"] = 12
-    with pytest.raises(lib.CmbError) as e:
-        lib.Tables(c, p, wl.k, wl.n_tau)
-    assert e.value.name == "CMB_E_UNSUPPORTED"
+    for nq in (0, 17):
+        p = dict(wl.prec)
+        p["n_q"] = nq
+        with pytest.raises(lib.CmbError) as e:
+            lib.Tables(c, p, wl.k, wl.n_tau)
+        assert e.value.name == "CMB_E_INVALID"

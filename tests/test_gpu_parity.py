@@ -270,6 +270,96 @@ def test_config1_full_size(ctx):
         assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
 
 
+def _massive(wl, m_nu, n_q, ell_ncdm):
+    c = wl.cosmo
+    c["N_nu_massless"] = float("nan")
+    c["Neff"] = 3.044
+    c["N_nu_massive"] = 1.0
+    c["m_nu_massive"] = m_nu
+    wl.prec.update(n_q=n_q, ell_ncdm=ell_ncdm)
+    return wl
+
+
+@pytest.mark.parametrize("m_nu", [0.06, 0.6])
+def test_massive_nu_small_parity(ctx, m_nu):
+    """One massive neutrino species (App. C massive neutrinos, App. B.3 eq.
+    mnu_sum) on a small hierarchy: 3 momentum nodes with l <= 6, photon and
+    massless cut-offs 8, 10 modes up to k = 0.2 (a ragged set of groups), 100
+    output times, l <= 100.  At 0.6 eV the massive terms are large."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = _massive(W.small_case(n_k=10, n_tau=100, ell_max=100, k_max=0.2), m_nu, 3, 6)
+    _say("case massive small m =", m_nu)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
+    assert np.all(g["status"] == 0) and np.all(r["status"] == 0)
+    assert np.all(np.abs(g["nsteps"][0] - r["nsteps"]) <= 2), (g["nsteps"][0], r["nsteps"])
+    e = src_err(g["S"][0], r["S"])
+    tt, te, ee = cl_err(g["Cl"][0], r["Cl"])
+    _say("source err", e, "cl err", tt, te, ee)
+    assert e <= 1e-8
+    assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+
+
+def test_massive_nu_batch_invariance(ctx):
+    """Two massive-neutrino cosmologies (0.06 and 0.6 eV) in one launch give
+    bitwise the results of separate launches."""
+    import paper_2602_15104_amd as L
+    tabs = []
+    for m_nu in (0.06, 0.6):
+        wl = _massive(W.small_case(n_k=7, n_tau=60, ell_max=40, k_max=0.1), m_nu, 3, 5)
+        tabs.append(L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau))
+    both = run_gpu(ctx, tabs, 40)
+    for i in range(2):
+        one = run_gpu(ctx, [tabs[i]], 40)
+        assert np.array_equal(both["S"][i], one["S"][0])
+        assert np.array_equal(both["Cl"][i], one["Cl"][0])
+
+
+def test_massive_nu_lane_variant_refused(ctx):
+    """The lane-per-mode kernel carries no massive-neutrino chains: asking for
+    it with a massive species is an error, not a silent massless solve."""
+    import paper_2602_15104_amd as L
+    wl = _massive(W.small_case(n_k=3, n_tau=40, ell_max=20), 0.06, 3, 5)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    os.environ["CMBHIP_K1"] = "lane"
+    try:
+        with pytest.raises(L.CmbError) as e:
+            run_gpu(ctx, [tab], 20)
+        assert e.value.name == "CMB_E_UNSUPPORTED"
+    finally:
+        del os.environ["CMBHIP_K1"]
+
+
+def test_config2_full_size(ctx):
+    """Config 2 (config 1 + one 0.06 eV neutrino, 12 momentum nodes x l <= 17,
+    N = 295 rows, 600 modes) at full size: sampled modes' sources against the
+    oracle computed live, the full C_ell and the per-mode step counts against
+    the stored oracle run (tests/golden/make_oracle_reference.py)."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.config2()
+    _say("case", wl.name)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    assert np.all(g["status"] == 0), np.bincount(g["status"].ravel())
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    idx = np.array([0, 40, 200, 599])
+    S, st, ns, na = O.perturb(t_or, idx)
+    e = src_err(g["S"][0][idx], S)
+    _say("sampled source err", e, "steps", g["nsteps"][0][idx], ns)
+    assert e <= 1e-8
+    ref = os.path.join(GOLD, "oracle_config2_cl.npy")
+    if os.path.exists(ref):
+        Co = np.load(ref)
+        tt, te, ee = cl_err(g["Cl"][0], Co)
+        nso = np.load(os.path.join(GOLD, "oracle_config2_nsteps.npy"))
+        _say("cl err", tt, te, ee, "max step-count difference", np.max(np.abs(g["nsteps"][0] - nso)))
+        assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+        assert np.max(np.abs(g["nsteps"][0] - nso)) <= 2
+
+
 def test_lane_per_mode_variant_parity(ctx):
     """The lane-per-mode perturbation kernel (CMBHIP_K1=lane) gives the same
     sources as the oracle and as the default cooperative kernel."""
