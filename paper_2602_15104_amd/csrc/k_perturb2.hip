@@ -72,30 +72,34 @@ struct Bk {  // background and per-stage constants at one ln a
 __device__ inline double eps_of(double q, double am) { return sqrt(fma(q, q, am * am)); }
 __device__ inline double dlnf0(double q) { return -q / (1.0 + exp(-q)); }
 
+// MNU: the hierarchy has massive-neutrino chains (compiled separately, so the
+// massless kernel carries none of their code)
+template <bool MNU>
 __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, Bk &s) {
     double a = exp(lna);
     s.a = a;
-    double a2 = a * a, a3 = a2 * a, a4 = a2 * a2;
-    s.rg = tb.rt_g0 / a4;
-    s.rur = tb.rt_ur0 / a4;
-    s.rc = tb.rt_c0 / a3;
-    s.rb = tb.rt_b0 / a3;
+    const double ia = rcp(a), ia3 = ia * ia * ia, ia4 = ia3 * ia;
+    double a2 = a * a;
+    s.rg = tb.rt_g0 * ia4;
+    s.rur = tb.rt_ur0 * ia4;
+    s.rc = tb.rt_c0 * ia3;
+    s.rb = tb.rt_b0 * ia3;
     double rho = s.rg + s.rur + s.rc + s.rb + tb.rt_L;
     double pr = (s.rg + s.rur) * (1.0 / 3.0) - tb.rt_L;
     s.am = a * tb.m_over_T;
-    s.pn4 = tb.pref_ncdm / a4;
-    if (p.nq > 0) {  // App. C massive neutrinos, eq. mnu_sum
+    s.pn4 = tb.pref_ncdm * ia4;
+    if (MNU && p.nq > 0) {  // App. C massive neutrinos, eq. mnu_sum
         double sr = 0.0, sp = 0.0;
         for (int i = 0; i < p.nq; ++i) {
             const double q = tb.q[i], e = eps_of(q, s.am);
             sr += tb.W[i] * e;
-            sp += tb.W[i] * q * q / e;
+            sp += tb.W[i] * q * q * rcp(e);
         }
         rho += s.pn4 * sr;
         pr += s.pn4 * sp * (1.0 / 3.0);
     }
     s.Hc = a * sqrt(rho);
-    s.Hcp = s.Hc * (1.0 - 1.5 * (rho + pr) / rho);
+    s.Hcp = s.Hc * (1.0 - 1.5 * (rho + pr) * rcp(rho));
     double u = (lna - tb.L0) * tb.inv_dl;
     int j = (int)floor(u);
     j = j < 0 ? 0 : (j > tb.n_tab - 1 ? tb.n_tab - 1 : j);
@@ -108,16 +112,16 @@ __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, 
     s.kap = ((o[7] * t + o[6]) * t + o[5]) * t + o[4];
     s.cs2 = exp(((o[11] * t + o[10]) * t + o[9]) * t + o[8]);
     s.tau = exp(((o[15] * t + o[14]) * t + o[13]) * t + o[12]);
-    s.invHc = 1.0 / s.Hc;
+    s.invHc = rcp(s.Hc);
     s.kH = k * s.invHc;
     s.k2H = k * s.kH;
     s.T = p.thom * s.dk * s.invHc;
-    s.R = (4.0 / 3.0) * s.rg / s.rb;
-    s.trunc = s.invHc / s.tau;
+    s.R = (4.0 / 3.0) * s.rg * rcp(s.rb);
+    s.trunc = s.invHc * rcp(s.tau);
     double ih2 = s.invHc * s.invHc;
     s.cH1 = p.grav * 2.0 * k * k * ih2;
     s.cH2 = p.grav * 3.0 * a2 * ih2;
-    s.cE = p.grav * 1.5 * a2 * s.invHc / (k * k);
+    s.cE = p.grav * 1.5 * a2 * s.invHc * rcp(k * k);
 }
 
 // Row layout: [F chain | G chain | nu chain | one Psi chain per momentum node |
@@ -328,6 +332,7 @@ __device__ void row_static(int row, const Lay &L, double &ca, double &cc, double
 // baryons, 1 photon polarisation, 2 massless neutrinos, 3 massive neutrinos at
 // one momentum node), in the form of row_coef, evaluated for every type and
 // selected without branching.
+template <bool MNU>
 __device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const DevPrec &p, double vq, double dl) {
     RowCo f{0, 0, 0, 0, 0, 0}, gp{0, 0, 0, 0, 0, 0}, v{0, 0, 0, 0, 0, 0}, m{0, 0, 0, 0, 0, 0};
     if (j == 0) {
@@ -370,18 +375,18 @@ __device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const
         gp.d = last ? -s.T - (l + 1.0) * s.trunc : -s.T;
         gp.uP = (j == 0) ? 0.5 * s.T : (j == 2 ? 0.1 * s.T : 0.0);
     }
-    {  // massive neutrinos at one node: rate vq = q kH / eps, dl = dln f0/dln q
+    if (MNU) {  // massive neutrinos at one node: rate vq = q kH / eps, dl = dln f0/dln q
         const bool last = j == L.nPs - 1;
         if (j == 0) {
             m.c = -vq;
-            m.uH = dl / 6.0;
+            m.uH = dl * (1.0 / 6.0);
         } else if (j == 1) {
-            m.a = vq / 3.0;
-            m.c = -2.0 * vq / 3.0;
+            m.a = vq * (1.0 / 3.0);
+            m.c = vq * (-2.0 / 3.0);
         } else if (j == 2) {
             m.a = 0.4 * vq;
             m.c = -0.6 * vq;
-            m.uH = -dl / 15.0;
+            m.uH = dl * (-1.0 / 15.0);
             m.uE = -0.4 * dl;
         } else {
             m.a = last ? vq : (3.0 / 7.0) * vq;
@@ -390,7 +395,7 @@ __device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const
         }
     }
     auto sel = [&](double a0, double a1, double a2, double a3) {
-        return ty == 0 ? a0 : (ty == 1 ? a1 : (ty == 2 ? a2 : a3));
+        return ty == 0 ? a0 : (ty == 1 ? a1 : ((!MNU || ty == 2) ? a2 : a3));
     };
     RowCo r;
     r.a = sel(f.a, gp.a, v.a, m.a);
@@ -465,7 +470,7 @@ struct Aff {
 
 __device__ inline double aff(const Aff &a, double H, double E, double P) { return a.v0 + a.vH * H + a.vE * E + a.vP * P; }
 
-template <int R>
+template <int R, bool MNU>
 __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
                                                       DevPrec p, int G, double *__restrict__ Sout,
                                                       int *__restrict__ status, int *__restrict__ nsteps) {
@@ -517,8 +522,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int cb = mych.cb, cn = mych.cn, ty = mych.ty;  // chain start row, length, type
     const bool photon_chain = ty < 2;
     // massive node of this lane's chain: q and dln f0/dln q
-    const double q_ch = (ty == 3) ? tb.q[mych.iq] : 0.0;
-    const double dl_ch = (ty == 3) ? dlnf0(q_ch) : 0.0;
+    const double q_ch = (MNU && ty == 3) ? tb.q[mych.iq] : 0.0;
+    const double dl_ch = (MNU && ty == 3) ? dlnf0(q_ch) : 0.0;
     const int N = L.N;
 
     Rows<R> w;
@@ -531,7 +536,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         for (int j = 0; j < 6; ++j) w.K[j][r] = 0.0;
     }
     Bk s;
-    bk_at(tb, p, k, t0, s);
+    bk_at<MNU>(tb, p, k, t0, s);
     // initial conditions (Ma & Bertschinger 1995 growing mode, eta -> 1)
     {
         double x = k * s.tau, Rn = tb.R_nu;
@@ -589,7 +594,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             if (gl * R + r < N) {
                 double yy = fabs(y1[r]);
                 if (y2) yy = fmax(yy, fabs(y2[r]));
-                double q = v[r] / (atol + rtol * yy);
+                double q = v[r] * rcp(fma(rtol, yy, atol));
                 acc += q * q;
             }
         }
@@ -618,7 +623,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
         for (int r = 0; r < R; ++r) y1[r] = w.y[r] + h0 * w.K[0][r];
         Bk s1;
-        bk_at(tb, p, k, t + h0, s1);
+        bk_at<MNU>(tb, p, k, t + h0, s1);
         full_rhs(y1, f1, s1);
 #pragma unroll
         for (int r = 0; r < R; ++r) f1[r] -= w.K[0][r];
@@ -646,7 +651,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         const double g = h * GAMMA;
         for (int si = 1; si < 6; ++si) {
             double ts = (si == 5) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
-            bk_at(tb, p, k, ts, s);
+            bk_at<MNU>(tb, p, k, ts, s);
             // stage weights h a_sj for j < s (zero otherwise): fixed-length sums keep
             // every register index static
             double hA[5];
@@ -668,8 +673,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             double vq = 0.0;  // streaming rate of this lane's massive node
             if (sweeper) {
                 const double gT = photon_chain ? gT_ph : 0.0;
-                if (ty == 3) vq = q_ch * s.kH / eps_of(q_ch, s.am);
-                const double u = ty == 3 ? g * vq : gkH, iu = rcp(u);
+                if (MNU && ty == 3) vq = q_ch * s.kH * rcp(eps_of(q_ch, s.am));
+                const double u = (MNU && ty == 3) ? g * vq : gkH, iu = rcp(u);
                 // Generic rows cn-1 .. 4 in continuant form.  With N_cn = 1,
                 // N_{cn+1} = 0, N_j = b_j N_{j+1} - c_j a_{j+1} N_{j+2} and
                 // T_j = r_j N_{j+1} - c_j T_{j+1}, the eliminated pivot and rhs
@@ -745,7 +750,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 double ib[4], r0[4], rH[4], rE[4], rP[4], al[4];
 #pragma unroll
                 for (int j = 3; j >= 0; --j) {
-                    const RowCo cc = top_coef(ty, j, L, s, p, vq, dl_ch);
+                    const RowCo cc = top_coef<MNU>(ty, j, L, s, p, vq, dl_ch);
                     double be = 1.0 - g * cc.d, ga = -g * cc.c, rho = m.ry(cb + j);
                     double xH = -g * cc.uH, xE = -g * cc.uE, xP = -g * cc.uP;
                     if (j == 2) {
@@ -832,7 +837,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 eE.vE = s.cE * (s.rb * F1.vE + f43 * s.rg * F2.vE + f43 * s.rur * V1.vE);
                 eE.vP = s.cE * (s.rb * F1.vP + f43 * s.rg * F2.vP + f43 * s.rur * V1.vP);
                 // massive neutrinos: delta rho from Psi_0, (rho + p) theta from Psi_1 of every node
-                for (int i = 0; i < L.nQ; ++i) {
+                for (int i = 0; i < (MNU ? L.nQ : 0); ++i) {
                     const double q = tb.q[i], w = s.pn4 * tb.W[i];
                     const double wh = s.cH2 * w * eps_of(q, s.am), we = s.cE * w * k * q;
                     const Aff P0 = T(cv + 1 + i, 0), P1 = T(cv + 1 + i, 1);
@@ -984,11 +989,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 wsync();
                 if (gl == 0) {
                     Bk so;
-                    bk_at(tb, p, k, lo[jo], so);
+                    bk_at<MNU>(tb, p, k, lo[jo], so);
                     auto y = [&](int r) { return m.ry(r); };
                     double k2 = k * k;
-                    double drho, rpt, rpsn;
-                    ncdm_moments(m, L, so, tb, k, drho, rpt, rpsn);
+                    double drho = 0.0, rpt = 0.0, rpsn = 0.0;
+                    if (MNU) ncdm_moments(m, L, so, tb, k, drho, rpt, rpsn);
                     double Hh = so.cH1 * y(L.rETA) + so.cH2 * (so.rc * y(L.rDC) + so.rb * y(0) + so.rg * y(L.rDG) +
                                                                so.rur * y(L.bV) + drho);
                     double Ee = so.cE *
@@ -1079,12 +1084,19 @@ int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const
     const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
     size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
-    if (R == 2)
-        hipLaunchKernelGGL(perturb2_kernel<2>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,
-                           d_nsteps);
+    const bool mnu = p.nq > 0;
+    if (R == 2 && !mnu)
+        hipLaunchKernelGGL((perturb2_kernel<2, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
+                           d_status, d_nsteps);
+    else if (R == 2)
+        hipLaunchKernelGGL((perturb2_kernel<2, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
+                           d_status, d_nsteps);
+    else if (!mnu)
+        hipLaunchKernelGGL((perturb2_kernel<5, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
+                           d_status, d_nsteps);
     else
-        hipLaunchKernelGGL(perturb2_kernel<5>, grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, d_status,
-                           d_nsteps);
+        hipLaunchKernelGGL((perturb2_kernel<5, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
+                           d_status, d_nsteps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
