@@ -165,6 +165,64 @@ int cmb_cl(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max
 int cmb_solve(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_S, double *d_Delta,
               double *d_Cl, int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
 
+/* ---------------------------------------------------------------- serving */
+/*
+ * Continuous-batching runtime for independent spectrum requests (each one
+ * cosmology with its own k grid, output-time count and ell_max; the whole
+ * path of App. B.1-B.4 per request).  Requests are submitted from any host
+ * thread; host tables are built on a pool of worker threads; a scheduler
+ * thread admits ready requests while their device footprint (tables,
+ * sources, transfer functions, spectra) fits the server's HBM arena, launches
+ * them as one perturbation launch over the work list of all their modes
+ * (longest first), then each request's projection and k quadrature, on up to
+ * n_streams HIP streams so that consecutive batches overlap on the device.
+ * All requests of one server must share the hierarchy options of cmb_prec
+ * (ell_gamma, ell_pol, ell_nu, n_q, ell_ncdm, max_steps, controller and
+ * switch options) and have n_tau <= 4096.
+ */
+typedef struct cmb_server cmb_server;
+typedef struct cmb_server_opts {
+    int n_workers;            /* host table-builder threads (0 = 4) */
+    int n_streams;            /* batches in flight on the device (0 = 2, at most 4) */
+    int max_batch;            /* requests per batch (0 = 64; 1 = one request at a time) */
+    size_t hbm_budget_bytes;  /* device arena (0 = 8 GiB) */
+} cmb_server_opts;
+
+/* Timing of one request, seconds on the server's monotonic clock
+ * (submit = 0 at cmb_server_create). */
+typedef struct cmb_request_times {
+    double submit, tables_ready, launched, done;
+    int batch_size; /* requests in the batch it ran in */
+} cmb_request_times;
+
+/* Create a server on HIP device `device` (opts may be NULL for defaults).
+ * Errors: CMB_E_INVALID, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_server_create(int device, const cmb_server_opts *opts, cmb_server **out);
+
+/* Queue one request; k[n_k] is copied.  *ticket identifies it in
+ * cmb_server_wait.  Returns at once; table-build errors are reported by
+ * cmb_server_wait.  Errors now: CMB_E_INVALID (NULL, sizes, options that
+ * differ from the server's first request). */
+int cmb_server_submit(cmb_server *s, const cmb_cosmo *c, const cmb_prec *p, const double *k, int n_k, int n_tau,
+                      int ell_max, uint64_t *ticket);
+
+/* Wait up to timeout_s seconds (< 0: forever) for a request.  On completion
+ * copies its spectra to host Cl[3][ell_max+1] (TT, TE, EE), and optionally
+ * status[n_k] (CMB_K_* per mode) and *times, then forgets the ticket.
+ * Returns CMB_OK, the request's table-build or device error code,
+ * CMB_E_NOMEM if it can never fit the arena, or -1 on timeout (the ticket
+ * stays valid). */
+int cmb_server_wait(cmb_server *s, uint64_t ticket, double timeout_s, double *Cl, int32_t *status,
+                    cmb_request_times *times);
+
+/* Drain: waits for every request in flight, then releases the server. */
+void cmb_server_destroy(cmb_server *s);
+
+/* Host self-test of the server's device-arena allocator (no GPU used):
+ * random allocation/release sequences checked for overlap, bounds and full
+ * coalescing.  Returns 0 on success. */
+int cmb_server_selftest_arena(unsigned seed, int n_ops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,7 +41,8 @@ MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
 # exported symbols (kept in step with include/cmbhip.h; a CPU test checks this)
 EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
-           "cmb_los", "cmb_cl", "cmb_solve"]
+           "cmb_los", "cmb_cl", "cmb_solve", "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
+           "cmb_server_destroy", "cmb_server_selftest_arena"]
 
 
 class CmbError(RuntimeError):
@@ -85,6 +86,16 @@ class CTableView(ctypes.Structure):
 _vp = ctypes.c_void_p
 
 
+class CServerOpts(ctypes.Structure):
+    _fields_ = [("n_workers", ctypes.c_int), ("n_streams", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class CRequestTimes(ctypes.Structure):
+    _fields_ = [("submit", ctypes.c_double), ("tables_ready", ctypes.c_double), ("launched", ctypes.c_double),
+                ("done", ctypes.c_double), ("batch_size", ctypes.c_int)]
+
+
 def _declare(lib):
     lib.cmb_defaults.argtypes = [ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec)]
     lib.cmb_last_error.restype = ctypes.c_char_p
@@ -102,6 +113,14 @@ def _declare(lib):
     lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.cmb_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(CServerOpts), ctypes.POINTER(_vp)]
+    lib.cmb_server_submit.argtypes = [_vp, ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec), _dp, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+    lib.cmb_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(CRequestTimes)]
+    lib.cmb_server_destroy.argtypes = [_vp]
+    lib.cmb_server_destroy.restype = None
+    lib.cmb_server_selftest_arena.argtypes = [ctypes.c_uint, ctypes.c_int]
 
 
 if not isinstance(_lib, _MissingLibrary):
@@ -187,8 +206,9 @@ class Tables:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.cmb_tables_destroy(h)
+        lib = globals().get("_lib")  # None while the interpreter shuts down
+        if h is not None and h.value and lib is not None:
+            lib.cmb_tables_destroy(h)
             self._h = None
 
 
@@ -222,8 +242,9 @@ class Context:
         self.device = device
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.cmb_ctx_destroy(self._h)
+        lib = globals().get("_lib")  # None while the interpreter shuts down
+        if getattr(self, "_h", None) is not None and self._h.value and lib is not None:
+            lib.cmb_ctx_destroy(self._h)
         self._h = None
 
     def __del__(self):
@@ -274,3 +295,56 @@ def solve_batch(ctx: Context, tabs, ell_max: int, keep_S: bool = True, keep_Delt
     ctx.solve(tabs, ell_max, out["Cl"], out["status"], S=out["S"], Delta=out["Delta"], nsteps=out["nsteps"],
               stream=stream)
     return out
+
+
+class Server:
+    """Continuous-batching runtime (cmb_server_*): submit spectrum requests
+    from the host, wait for their C_ell.  All requests share the hierarchy
+    options of their prec dicts."""
+
+    def __init__(self, device: int = 0, n_workers: int = 0, n_streams: int = 0, max_batch: int = 0,
+                 hbm_budget_bytes: int = 0):
+        o = CServerOpts(int(n_workers), int(n_streams), int(max_batch), int(hbm_budget_bytes))
+        h = _vp()
+        _check(_lib.cmb_server_create(int(device), ctypes.byref(o), ctypes.byref(h)), "cmb_server_create")
+        self._h = h
+        self._shape = {}
+
+    def submit(self, cosmo: dict, prec: dict, k, n_tau: int, ell_max: int) -> int:
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        cs, ps = _cosmo_struct(cosmo), _prec_struct(prec)
+        t = ctypes.c_uint64()
+        _check(_lib.cmb_server_submit(self._h, ctypes.byref(cs), ctypes.byref(ps), k.ctypes.data_as(_dp), len(k),
+                                      int(n_tau), int(ell_max), ctypes.byref(t)), "cmb_server_submit")
+        self._shape[t.value] = (len(k), int(ell_max))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        """(C_ell[3][ell_max+1], status[n_k], times dict); raises CmbError on a
+        failed request, TimeoutError on timeout."""
+        n_k, ell_max = self._shape[ticket]
+        Cl = np.zeros((3, ell_max + 1))
+        st = np.zeros(n_k, dtype=np.int32)
+        tm = CRequestTimes()
+        rc = _lib.cmb_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s), Cl.ctypes.data_as(_dp),
+                                  st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(tm))
+        if rc == -1:
+            raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+        del self._shape[ticket]
+        _check(rc, "cmb_server_wait")
+        times = {n: getattr(tm, n) for n, _ in CRequestTimes._fields_}
+        return Cl, st, times
+
+    def close(self):
+        lib = globals().get("_lib")  # None while the interpreter shuts down
+        if getattr(self, "_h", None) is not None and self._h.value and lib is not None:
+            lib.cmb_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def server_selftest_arena(seed: int = 1, n_ops: int = 20000) -> int:
+    """Host self-test of the server's device-arena allocator (no GPU)."""
+    return int(_lib.cmb_server_selftest_arena(int(seed), int(n_ops)))

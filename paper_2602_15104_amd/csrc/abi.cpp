@@ -17,6 +17,75 @@ struct cmb_tables {
     cmbhip::Tables t;
 };
 
+namespace cmbhip {
+
+size_t table_doubles(const Tables &t) {
+    return t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size() + 2 * t.q.size();
+}
+
+void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x) {
+    size_t o = 0;
+    auto put = [&](const std::vector<double> &v) {
+        std::memcpy(hp + o, v.data(), v.size() * sizeof(double));
+        const double *r = dp + o;
+        o += v.size();
+        return r;
+    };
+    std::memset(&x, 0, sizeof(x));
+    x.poly = put(t.poly);
+    x.k = put(t.k);
+    x.lna_start = put(t.lna_start);
+    x.lna_src = put(t.lna_src);
+    x.chi_src = put(t.chi_src);
+    x.w_src = put(t.w_src);
+    x.q = put(t.q);
+    x.W = put(t.W);
+    x.pref_ncdm = t.pref_ncdm;
+    x.m_over_T = t.m_over_T;
+    x.L0 = t.L0;
+    x.inv_dl = 1.0 / t.dl;
+    x.n_tab = t.n_tab;
+    x.n_k = (int)t.k.size();
+    x.n_tau = (int)t.lna_src.size();
+    x.tau0 = t.tau0;
+    x.R_nu = t.R_nu;
+    x.rt_g0 = t.rt_g0;
+    x.rt_ur0 = t.rt_ur0;
+    x.rt_c0 = t.rt_c0;
+    x.rt_b0 = t.rt_b0;
+    x.rt_L = t.rt_L;
+    x.A_s = t.cosmo.A_s;
+    x.n_s = t.cosmo.n_s;
+    x.k_pivot = t.prec.k_pivot;
+    x.rtol_small = t.prec.rtol_small;
+    x.rtol_large = t.prec.rtol_large;
+    x.atol_small = t.prec.atol_small;
+    x.atol_large = t.prec.atol_large;
+    x.k_split = t.prec.k_split;
+}
+
+DevPrec dev_prec(const cmb_prec &p, int nq) {
+    DevPrec d{};
+    d.lg = p.ell_gamma;
+    d.lp = p.ell_pol;
+    d.ln = p.ell_nu;
+    d.max_steps = p.max_steps;
+    d.nq = nq;
+    d.lq = nq > 0 ? p.ell_ncdm : 0;
+    d.pcoeff = p.pcoeff;
+    d.icoeff = p.icoeff;
+    d.dcoeff = p.dcoeff;
+    d.sw = p.scale_sw;
+    d.isw = p.scale_isw;
+    d.dop = p.scale_dop;
+    d.pol = p.scale_pol;
+    d.grav = p.gravity_scale;
+    d.thom = p.thomson_scale;
+    return d;
+}
+
+}  // namespace cmbhip
+
 struct cmb_ctx {
     int device = 0;
     size_t budget = 0;
@@ -296,21 +365,7 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
             return CMB_E_INVALID;
         }
     }
-    b.prec.lg = p.ell_gamma;
-    b.prec.lp = p.ell_pol;
-    b.prec.ln = p.ell_nu;
-    b.prec.max_steps = p.max_steps;
-    b.prec.nq = (int)t0.q.size();
-    b.prec.lq = b.prec.nq > 0 ? p.ell_ncdm : 0;
-    b.prec.pcoeff = p.pcoeff;
-    b.prec.icoeff = p.icoeff;
-    b.prec.dcoeff = p.dcoeff;
-    b.prec.sw = p.scale_sw;
-    b.prec.isw = p.scale_isw;
-    b.prec.dop = p.scale_dop;
-    b.prec.pol = p.scale_pol;
-    b.prec.grav = p.gravity_scale;
-    b.prec.thom = p.thomson_scale;
+    b.prec = cmbhip::dev_prec(p, (int)t0.q.size());
     b.polar = p.ell_pol > 0;
     b.s_pol = p.scale_pol;
     return CMB_OK;
@@ -318,10 +373,7 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t table_bytes(const cmbhip::Tables &t) {
-    size_t n = t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size() + 2 * t.q.size();
-    return align256(n * sizeof(double));
-}
+size_t table_bytes(const cmbhip::Tables &t) { return align256(cmbhip::table_doubles(t) * sizeof(double)); }
 
 // Upload the batch's tables (skipped when the same tables are resident).
 int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s) {
@@ -352,47 +404,7 @@ int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s
     cmbhip::DevTab *dt = (cmbhip::DevTab *)h;
     for (int i = 0; i < n_cosmo; ++i) {
         const cmbhip::Tables &t = tabs[i]->t;
-        double *hp = (double *)(h + off);
-        const double *dp = (const double *)(d + off);
-        size_t o = 0;
-        auto put = [&](const std::vector<double> &v) {
-            std::memcpy(hp + o, v.data(), v.size() * sizeof(double));
-            const double *r = dp + o;
-            o += v.size();
-            return r;
-        };
-        cmbhip::DevTab &x = dt[i];
-        std::memset(&x, 0, sizeof(x));
-        x.poly = put(t.poly);
-        x.k = put(t.k);
-        x.lna_start = put(t.lna_start);
-        x.lna_src = put(t.lna_src);
-        x.chi_src = put(t.chi_src);
-        x.w_src = put(t.w_src);
-        x.q = put(t.q);
-        x.W = put(t.W);
-        x.pref_ncdm = t.pref_ncdm;
-        x.m_over_T = t.m_over_T;
-        x.L0 = t.L0;
-        x.inv_dl = 1.0 / t.dl;
-        x.n_tab = t.n_tab;
-        x.n_k = (int)t.k.size();
-        x.n_tau = (int)t.lna_src.size();
-        x.tau0 = t.tau0;
-        x.R_nu = t.R_nu;
-        x.rt_g0 = t.rt_g0;
-        x.rt_ur0 = t.rt_ur0;
-        x.rt_c0 = t.rt_c0;
-        x.rt_b0 = t.rt_b0;
-        x.rt_L = t.rt_L;
-        x.A_s = t.cosmo.A_s;
-        x.n_s = t.cosmo.n_s;
-        x.k_pivot = t.prec.k_pivot;
-        x.rtol_small = t.prec.rtol_small;
-        x.rtol_large = t.prec.rtol_large;
-        x.atol_small = t.prec.atol_small;
-        x.atol_large = t.prec.atol_large;
-        x.k_split = t.prec.k_split;
+        cmbhip::pack_table(t, (double *)(h + off), (const double *)(d + off), dt[i]);
         off += table_bytes(t);
     }
     hipError_t e = hipMemcpyAsync(c->tab_buf, c->h_stage, bytes, hipMemcpyHostToDevice, s);

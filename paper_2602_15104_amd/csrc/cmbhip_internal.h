@@ -42,6 +42,8 @@ struct DevTab {
     const double *chi_src;    // [n_tau]
     const double *w_src;      // [n_tau]
     const double *q, *W;      // [n_q] massive-neutrino momentum rule (n_q = 0: none)
+    double *S;                // work-list launches only: this cosmology's [n_k][3][n_tau] sources
+    int *status, *nsteps;     //   and [n_k] status / step counts
     double L0, inv_dl;
     int n_tab, n_k, n_tau, pad;
     double tau0, R_nu;
@@ -59,6 +61,13 @@ struct DevPrec {
     double sw, isw, dop, pol, grav, thom;
 };
 
+// table arrays of one cosmology packed for the device: count, and packing
+// into host staging hp whose device copy will sit at dp (fills the DevTab)
+size_t table_doubles(const Tables &t);
+void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x);
+// launch options of a hierarchy (nq: momentum nodes actually present)
+DevPrec dev_prec(const cmb_prec &p, int nq);
+
 // kernel launchers (hipStream_t passed as void*)
 int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_ws,
                    double *d_S, int *d_status, int *d_nsteps, void *stream);
@@ -66,6 +75,11 @@ size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
                     int *d_status, int *d_nsteps, void *stream);
 bool perturb2_supported(const DevPrec &p);
+// work list of (cosmology, mode) pairs; outputs through each DevTab's S/status/nsteps
+struct WorkItem {
+    int c, ik;
+};
+int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_items, const DevPrec &p, void *stream);
 int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E, double s_pol,
                const double *d_S, double *d_Delta, void *stream);
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,

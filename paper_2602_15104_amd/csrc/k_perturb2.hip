@@ -470,16 +470,21 @@ struct Aff {
 
 __device__ inline double aff(const Aff &a, double H, double E, double P) { return a.v0 + a.vH * H + a.vE * E + a.vP * P; }
 
+// Modes: either the whole [n_cosmo][n_k] batch (items == nullptr; outputs in
+// Sout/status/nsteps, largest k first) or the work list items[n_items] of
+// (cosmology, mode) pairs, each cosmology with its own grids and its own
+// output arrays in its DevTab (ragged batches of the serving runtime).
 template <int R, bool MNU>
-__global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
-                                                      DevPrec p, int G, double *__restrict__ Sout,
-                                                      int *__restrict__ status, int *__restrict__ nsteps) {
+__global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                      int n_tau_all, DevPrec p, int G, double *__restrict__ Sout,
+                                                      int *__restrict__ status, int *__restrict__ nsteps,
+                                                      const int2 *__restrict__ items, int n_items) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int gl = lane % G;
     const int grp = lane / G;
     const int spw = 64 / G;
-    const int n_sys = n_cosmo * n_k;
+    const int n_sys = items ? n_items : n_cosmo * n_k;
     const int lin = blockIdx.x * spw + grp;
     const Lay L = make_lay(p);
     const int NP = G * R;
@@ -505,16 +510,23 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         wsync();
     }
     if (lin >= n_sys) return;  // whole group idle (no cross-group dependence)
-    const int sys = n_sys - 1 - lin;  // largest k first, cosmology fastest
-    const int c = sys % n_cosmo;
-    const int ik = sys / n_cosmo;
+    int c, ik;
+    if (items) {
+        c = items[lin].x;
+        ik = items[lin].y;
+    } else {
+        const int sys = n_sys - 1 - lin;  // largest k first, cosmology fastest
+        c = sys % n_cosmo;
+        ik = sys / n_cosmo;
+    }
     const DevTab &tb = tabs[c];
+    const int n_tau = items ? tb.n_tau : n_tau_all;
     const double k = tb.k[ik];
     const double t0 = tb.lna_start[ik];
     const bool small = k < tb.k_split;
     const double rtol = small ? tb.rtol_small : tb.rtol_large;
     const double atol = small ? tb.atol_small : tb.atol_large;
-    double *So = Sout + ((size_t)c * n_k + ik) * 3 * n_tau;
+    double *So = items ? tb.S + (size_t)ik * 3 * n_tau : Sout + ((size_t)c * n_k + ik) * 3 * n_tau;
     const double *lo = tb.lna_src;
     const int ch = gl;  // chain handled by this lane in the sweeps
     const bool sweeper = ch < L.nch;
@@ -1044,8 +1056,13 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             So[n_tau + jo] = 0.0;
             So[2 * n_tau + jo] = 0.0;
         }
-        status[(size_t)c * n_k + ik] = st;
-        nsteps[(size_t)c * n_k + ik] = ns;
+        if (items) {
+            tb.status[ik] = st;
+            tb.nsteps[ik] = ns;
+        } else {
+            status[(size_t)c * n_k + ik] = st;
+            nsteps[(size_t)c * n_k + ik] = ns;
+        }
     }
 }
 
@@ -1070,8 +1087,8 @@ bool perturb2_supported(const DevPrec &p) {
     return G <= 64 && (64 / G) * slab_doubles(G * R, nch) * sizeof(double) <= 65536 && p.nq <= kMaxQ;
 }
 
-int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, void *stream) {
+static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
+                               int *d_status, int *d_nsteps, const int2 *d_items, int n_items, void *stream) {
     int R, G;
     group_shape(p, R, G);
     if (G > 64) {
@@ -1079,7 +1096,8 @@ int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const
         return CMB_E_UNSUPPORTED;
     }
     int spw = 64 / G;
-    long n_sys = (long)n_cosmo * n_k;
+    long n_sys = d_items ? (long)n_items : (long)n_cosmo * n_k;
+    if (n_sys <= 0) return CMB_OK;
     dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
     const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
     size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
@@ -1087,22 +1105,33 @@ int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const
     const bool mnu = p.nq > 0;
     if (R == 2 && !mnu)
         hipLaunchKernelGGL((perturb2_kernel<2, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps);
+                           d_status, d_nsteps, d_items, n_items);
     else if (R == 2)
         hipLaunchKernelGGL((perturb2_kernel<2, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps);
+                           d_status, d_nsteps, d_items, n_items);
     else if (!mnu)
         hipLaunchKernelGGL((perturb2_kernel<5, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps);
+                           d_status, d_nsteps, d_items, n_items);
     else
         hipLaunchKernelGGL((perturb2_kernel<5, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps);
+                           d_status, d_nsteps, d_items, n_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
         return CMB_E_DEVICE;
     }
     return CMB_OK;
+}
+
+int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
+                    int *d_status, int *d_nsteps, void *stream) {
+    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, stream);
+}
+
+int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_items, const DevPrec &p, void *stream) {
+    static_assert(sizeof(WorkItem) == sizeof(int2), "work item layout");
+    return launch_perturb2_any(d_tabs, 0, 0, 0, p, nullptr, nullptr, nullptr, reinterpret_cast<const int2 *>(d_items),
+                               n_items, stream);
 }
 
 }  // namespace cmbhip

@@ -167,3 +167,10 @@ def test_massive_neutrinos_need_nodes(lib):
         with pytest.raises(lib.CmbError) as e:
             lib.Tables(c, p, wl.k, wl.n_tau)
         assert e.value.name == "CMB_E_INVALID"
+
+def test_server_arena_allocator(lib):
+    """The serving runtime's device-arena allocator (host logic only): random
+    allocate/release sequences never overlap, stay in bounds and 256-byte
+    aligned, account every byte, and coalesce back to one block."""
+    for seed in range(8):
+        assert lib.server_selftest_arena(seed, 20000) == 0
