@@ -87,6 +87,35 @@ def k1_traffic(batch: int):
         return None
 
 
+def serve(reqs, prec, n_tau, max_batch, n_streams, n_workers=8):
+    """Replay the requests' arrival times against a serving runtime; returns
+    per-request latency (arrival to spectra on the host) and its parts."""
+    import paper_2602_15104_amd as L
+    srv = L.Server(0, n_workers=n_workers, n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=16 << 30)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            dt = r["arrival_s"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(r["cosmo"], prec, r["k"], n_tau, r["ell_max"]))
+        res = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    tm = [x[2] for x in res]
+    lat = np.array([t["done"] - t["submit"] for t in tm]) * 1e3
+    span = max(t["done"] for t in tm) - min(t["submit"] for t in tm)
+    bad = sum(int(np.any(x[1] != 0)) for x in res)
+    return {"requests": len(reqs), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()),
+            "max_ms": float(lat.max()), "throughput_per_s": len(reqs) / span,
+            "mean_tables_ms": 1e3 * float(np.mean([t["tables_ready"] - t["submit"] for t in tm])),
+            "mean_queue_ms": 1e3 * float(np.mean([t["launched"] - t["tables_ready"] for t in tm])),
+            "mean_device_ms": 1e3 * float(np.mean([t["done"] - t["launched"] for t in tm])),
+            "mean_batch": float(np.mean([t["batch_size"] for t in tm])), "modes_not_ok_requests": bad,
+            "max_batch": max_batch, "streams": n_streams}
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
@@ -120,6 +149,10 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--plain-reps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="Poisson serving workload: requests replayed (0 = skip)")
+    ap.add_argument("--serving-plain-requests", type=int, default=128,
+                    help="the same arrivals served one request at a time (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -254,6 +287,20 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": k1_traffic(B) if dom == "perturb" else None},
     }
+    if args.serving_requests > 0:
+        reqs = W.serving_requests(args.serving_requests, rate_hz=50.0, seed=20260215)
+        print(f"[bench] serving {len(reqs)} Poisson requests (50/s)", file=sys.stderr, flush=True)
+        out["serving"] = serve(reqs, wl.prec, wl.n_tau, max_batch=64, n_streams=2)
+        out["serving"]["workload"] = ("512 requests, Poisson 50/s, 5% Gaussian cosmologies, l_max in {500, 1000, "
+                                      "2500} with 100/250/400 modes on [1e-5, 0.5 l_max/2500], 2000 output times, "
+                                      "config-1 hierarchy; latency = arrival to spectra on the host, incl. host tables")
+        print(f"[bench] serving p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+        if args.serving_plain_requests > 0:
+            sub = reqs[:args.serving_plain_requests]
+            out["serving_plain"] = serve(sub, wl.prec, wl.n_tau, max_batch=1, n_streams=1)
+            print(f"[bench] serving one-at-a-time p50 {out['serving_plain']['p50_ms']:.1f} ms", file=sys.stderr,
+                  flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
