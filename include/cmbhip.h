@@ -138,6 +138,17 @@ size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo);
 int cmb_perturb(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
                 int32_t *d_nsteps, void *hip_stream);
 
+/* As cmb_perturb, plus the linear matter power spectrum today (App. B.4,
+ * eq. PK): P(k, z=0) = 2 pi^2/k^3 A_s (k/k_pivot)^(n_s-1) [sum_i rho_i delta_i
+ * / sum_i rho_i]^2 in Mpc^3, the sums over the non-relativistic species (CDM,
+ * baryons and massive neutrinos), from each mode's state at a = 1.
+ *   d_Pk: device, [n_cosmo][n_k] doubles, caller-owned (0 for a mode whose
+ *         status is not CMB_K_OK).
+ * Errors as cmb_perturb; CMB_E_UNSUPPORTED for a hierarchy the cooperative
+ * perturbation kernel cannot hold. */
+int cmb_perturb_pk(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                   int32_t *d_nsteps, double *d_Pk, void *hip_stream);
+
 /*
  * Line-of-sight projection (App. B.4, transfer integrals; trapezoid in ln a):
  * from sources d_S (layout above, any values) to

@@ -100,6 +100,9 @@ def lib():
                                               dp, dp, ctypes.c_int, dp, dp, ip, ip, ip]
             L.oracle_state_size.restype = ctypes.c_int
             L.oracle_state_size.argtypes = [ctypes.POINTER(_OPrec)]
+            L.oracle_matter_pk.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, dp,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double]
+            L.oracle_matter_pk.restype = ctypes.c_double
             L.oracle_bessel.restype = None
             L.oracle_bessel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_longdouble)]
             L.oracle_los.restype = None
@@ -219,6 +222,29 @@ def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None
         out["y"] = Y
     if acc_cap:
         out["accepted_lna"] = acc[: min(na.value, acc_cap)]
+    return out
+
+
+def matter_pk(t, idx=None):
+    """Linear matter power spectrum today (App. B.4, eq. PK) [Mpc^3] for the
+    modes idx (default all): each mode integrated to a = 1 by the oracle's
+    ESDIRK (one output time, ln a = 0), then 2 pi^2/k^3 P_R(k) delta_m^2 with
+    delta_m over CDM, baryons and massive neutrinos.  NaN where a mode did not
+    finish."""
+    idx = np.arange(len(t.k)) if idx is None else np.asarray(idx)
+    out = np.full(len(idx), np.nan)
+    prec = dict(t.prec)
+    c = t.cosmo
+    for n, i in enumerate(idx):
+        r = perturb_one(t, float(t.k[i]), float(t.lna_i[i]), [0.0], want_y=True)
+        if r["status"] != 0:
+            continue
+        rt, at = tolerances(prec, np.array([t.k[i]]))
+        p = make_prec(prec, len(t.bg.q), float(rt[0]), float(at[0]))
+        b = _Bound(t)
+        y = np.ascontiguousarray(r["y"][-1])
+        out[n] = lib().oracle_matter_pk(ctypes.byref(b.tab), ctypes.byref(p), float(t.k[i]), _dp(y), float(c["A_s"]),
+                                        float(c["n_s"]), float(prec["k_pivot"]))
     return out
 
 

@@ -83,6 +83,28 @@ static void make_layout(const oprec_t *p, olayout_t *L) {
     L->N = L->eta + 1;
 }
 
+/* Linear matter power spectrum today (App. B.4, eq. PK) from the state y at
+   a = 1: P = 2 pi^2/k^3 * A_s (k/k_pivot)^(n_s - 1) * [sum_i rho_i delta_i /
+   sum_i rho_i]^2, the sums over the non-relativistic species -- CDM, baryons
+   and the massive neutrinos (their density contrast from Psi_0 through the
+   momentum rule, eq. mnu_sum).  Units Mpc^3. */
+double oracle_matter_pk(const otab_t *t, const oprec_t *p, double k, const double *y, double A_s, double n_s,
+                        double k_pivot) {
+    olayout_t L;
+    make_layout(p, &L);
+    double num = t->rt_c0 * y[L.dc] + t->rt_b0 * y[L.db];
+    double den = t->rt_c0 + t->rt_b0;
+    for (int i = 0; i < p->nq; ++i) {
+        double e = sqrt(t->q[i] * t->q[i] + t->m_over_T * t->m_over_T); /* a = 1 */
+        num += t->pref_ncdm * t->W[i] * e * y[L.m0 + i * (p->lq + 1)];
+        den += t->pref_ncdm * t->W[i] * e;
+    }
+    double dm = num / den;
+    double prim = A_s * pow(k / k_pivot, n_s - 1.0);
+    const double pi = 3.14159265358979323846;
+    return 2.0 * pi * pi / (k * k * k) * prim * dm * dm;
+}
+
 int oracle_state_size(const oprec_t *p) {
     olayout_t L;
     make_layout(p, &L);

@@ -24,14 +24,15 @@ LIB_PATH = os.environ.get("CMBHIP_LIBRARY") or os.path.join(_HERE, "libcmbhip.so
 
 
 class _MissingLibrary:
-    """Stands in for the library until it is built; every use raises."""
+    """Stands in for the library until it is built (or rebuilt, when the file
+    on disk lacks a symbol of this binding); every use raises."""
+
+    def __init__(self, why: str = "not found"):
+        self.why = why
 
     def __getattr__(self, name):
-        raise RuntimeError(f"libcmbhip.so not found at {LIB_PATH}: build it with "
+        raise RuntimeError(f"libcmbhip.so {self.why} at {LIB_PATH}: build it with "
                            f"`python -m paper_2602_15104_amd.build` (no CPU fallback exists)")
-
-
-_lib = ctypes.CDLL(LIB_PATH) if os.path.exists(LIB_PATH) else _MissingLibrary()
 
 CMB_OK = 0
 ERRORS = {1: "CMB_E_INVALID", 2: "CMB_E_CONFLICT", 3: "CMB_E_NEG_NMASSLESS", 4: "CMB_E_ROOT", 5: "CMB_E_DEVICE",
@@ -41,7 +42,7 @@ MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
 # exported symbols (kept in step with include/cmbhip.h; a CPU test checks this)
 EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
-           "cmb_los", "cmb_cl", "cmb_solve", "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
+           "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
 
@@ -110,6 +111,7 @@ def _declare(lib):
     lib.cmb_solve_workspace_bytes.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
     lib.cmb_solve_workspace_bytes.restype = ctypes.c_size_t
     lib.cmb_perturb.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.cmb_perturb_pk.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
     lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -123,8 +125,18 @@ def _declare(lib):
     lib.cmb_server_selftest_arena.argtypes = [ctypes.c_uint, ctypes.c_int]
 
 
-if not isinstance(_lib, _MissingLibrary):
-    _declare(_lib)
+def _load():
+    if not os.path.exists(LIB_PATH):
+        return _MissingLibrary()
+    lib = ctypes.CDLL(LIB_PATH)
+    missing = [f for f in EXPORTS if not hasattr(lib, f)]
+    if missing:
+        return _MissingLibrary(f"out of date (lacks {', '.join(missing)})")
+    _declare(lib)
+    return lib
+
+
+_lib = _load()
 
 
 def _check(rc: int, where: str):
@@ -254,6 +266,12 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_perturb(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _stream(stream)),
                "cmb_perturb")
+
+    def perturb_pk(self, tabs, S, status, Pk, nsteps=None, stream=None):
+        """cmb_perturb plus the matter power spectrum today into Pk[n_cosmo][n_k]."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_pk(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _ptr(Pk),
+                                   _stream(stream)), "cmb_perturb_pk")
 
     def los(self, tabs, ell_max, S, Delta, stream=None):
         hs = _handles(tabs)

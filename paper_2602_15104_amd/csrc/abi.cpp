@@ -438,12 +438,12 @@ size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo) {
     return bytes;
 }
 
-int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
-                int32_t *d_nsteps, void *stream) {
-    if (!c || !d_S || !d_status) {
-        set_error("cmb_perturb: NULL argument");
-        return CMB_E_INVALID;
-    }
+}  // extern "C"
+
+namespace {
+
+int perturb_impl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                 int32_t *d_nsteps, double *d_Pk, void *stream) {
     Batch b;
     int rc = check_batch(tabs, n_cosmo, b);
     if (rc) return rc;
@@ -454,9 +454,13 @@ int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
     const char *variant = std::getenv("CMBHIP_K1");
-    bool lane_variant = variant && std::string(variant) == "lane";
+    bool lane_variant = variant && std::string(variant) == "lane" && !d_Pk;
     if (b.prec.nq > 0 && (lane_variant || !cmbhip::perturb2_supported(b.prec))) {
         set_error("massive neutrinos are built into the cooperative perturbation kernel only");
+        return CMB_E_UNSUPPORTED;
+    }
+    if (d_Pk && !cmbhip::perturb2_supported(b.prec)) {
+        set_error("the matter power spectrum is built into the cooperative perturbation kernel only");
         return CMB_E_UNSUPPORTED;
     }
     if (!lane_variant && cmbhip::perturb2_supported(b.prec)) {
@@ -466,7 +470,7 @@ int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *
             if (rc) return rc;
             ns2 = (int32_t *)c->st_buf;
         }
-        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, stream);
+        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, d_Pk, stream);
         if (rc == CMB_OK) set_error("");
         return rc;
     }
@@ -483,6 +487,28 @@ int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *
                                 stream);
     if (rc == CMB_OK) set_error("");
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cmb_perturb(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                int32_t *d_nsteps, void *stream) {
+    if (!c || !d_S || !d_status) {
+        set_error("cmb_perturb: NULL argument");
+        return CMB_E_INVALID;
+    }
+    return perturb_impl(c, tabs, n_cosmo, d_S, d_status, d_nsteps, nullptr, stream);
+}
+
+int cmb_perturb_pk(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                   int32_t *d_nsteps, double *d_Pk, void *stream) {
+    if (!c || !d_S || !d_status || !d_Pk) {
+        set_error("cmb_perturb_pk: NULL argument");
+        return CMB_E_INVALID;
+    }
+    return perturb_impl(c, tabs, n_cosmo, d_S, d_status, d_nsteps, d_Pk, stream);
 }
 
 int cmb_los(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S, double *d_Delta,

@@ -478,7 +478,8 @@ template <int R, bool MNU>
 __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
                                                       int n_tau_all, DevPrec p, int G, double *__restrict__ Sout,
                                                       int *__restrict__ status, int *__restrict__ nsteps,
-                                                      const int2 *__restrict__ items, int n_items) {
+                                                      const int2 *__restrict__ items, int n_items,
+                                                      double *__restrict__ Pk) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int gl = lane % G;
@@ -1050,6 +1051,29 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             break;
         }
     }
+    // matter power spectrum today (App. B.4, eq. PK) from the state at a = 1:
+    // 2 pi^2/k^3 P_R(k) [sum rho_i delta_i / sum rho_i]^2 over CDM, baryons and
+    // the massive neutrinos (0 for a mode that did not finish)
+    if (Pk) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) m.ry(gl * R + r) = w.y[r];
+        wsync();
+        if (gl == 0) {
+            double val = 0.0;
+            if (st == CMB_K_OK) {
+                double num = tb.rt_c0 * m.ry(L.rDC) + tb.rt_b0 * m.ry(0), den = tb.rt_c0 + tb.rt_b0;
+                if (MNU)
+                    for (int i = 0; i < L.nQ; ++i) {
+                        const double w1 = tb.pref_ncdm * tb.W[i] * eps_of(tb.q[i], tb.m_over_T);
+                        num = fma(w1, m.ry(L.bM + i * L.nPs), num);
+                        den += w1;
+                    }
+                const double dm = num * rcp(den);
+                val = 2.0 * M_PI * M_PI * rcp(k * k * k) * tb.A_s * pow(k / tb.k_pivot, tb.n_s - 1.0) * dm * dm;
+            }
+            Pk[(size_t)c * n_k + ik] = val;
+        }
+    }
     if (gl == 0) {
         for (; jo < n_tau; ++jo) {
             So[jo] = 0.0;
@@ -1088,7 +1112,8 @@ bool perturb2_supported(const DevPrec &p) {
 }
 
 static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                               int *d_status, int *d_nsteps, const int2 *d_items, int n_items, void *stream) {
+                               int *d_status, int *d_nsteps, const int2 *d_items, int n_items, double *d_Pk,
+                               void *stream) {
     int R, G;
     group_shape(p, R, G);
     if (G > 64) {
@@ -1105,16 +1130,16 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
     const bool mnu = p.nq > 0;
     if (R == 2 && !mnu)
         hipLaunchKernelGGL((perturb2_kernel<2, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items);
+                           d_status, d_nsteps, d_items, n_items, d_Pk);
     else if (R == 2)
         hipLaunchKernelGGL((perturb2_kernel<2, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items);
+                           d_status, d_nsteps, d_items, n_items, d_Pk);
     else if (!mnu)
         hipLaunchKernelGGL((perturb2_kernel<5, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items);
+                           d_status, d_nsteps, d_items, n_items, d_Pk);
     else
         hipLaunchKernelGGL((perturb2_kernel<5, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items);
+                           d_status, d_nsteps, d_items, n_items, d_Pk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
@@ -1124,14 +1149,14 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
 }
 
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, void *stream) {
-    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, stream);
+                    int *d_status, int *d_nsteps, double *d_Pk, void *stream) {
+    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, d_Pk, stream);
 }
 
 int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_items, const DevPrec &p, void *stream) {
     static_assert(sizeof(WorkItem) == sizeof(int2), "work item layout");
     return launch_perturb2_any(d_tabs, 0, 0, 0, p, nullptr, nullptr, nullptr, reinterpret_cast<const int2 *>(d_items),
-                               n_items, stream);
+                               n_items, nullptr, stream);
 }
 
 }  // namespace cmbhip

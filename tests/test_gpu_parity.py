@@ -392,3 +392,43 @@ def test_config1_repeat_bitwise(ctx):
     b = run_gpu(ctx, tabs, wl.ell_max)
     assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
     assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["Cl"], b["Cl"])
+
+
+def _gpu_pk(ctx, tab):
+    import torch
+    n_k, n_tau = len(tab.k), tab.n_tau
+    S = torch.empty((1, n_k, 3, n_tau), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((1, n_k), dtype=torch.int32, device="cuda:0")
+    Pk = torch.empty((1, n_k), dtype=torch.float64, device="cuda:0")
+    ctx.perturb_pk([tab], S, st, Pk)
+    torch.cuda.synchronize()
+    return Pk[0].cpu().numpy(), st[0].cpu().numpy(), S[0].cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["small", "small_massive", "config1", "config2"])
+def test_matter_pk_parity(ctx, case):
+    """Matter power spectrum today (App. B.4, eq. PK) from cmb_perturb_pk
+    against the oracle (each mode integrated to a = 1), relative per mode
+    <= 1e-8; the sources of the same call equal cmb_perturb's bitwise."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    if case == "small":
+        wl, idx = W.small_case(n_k=12, n_tau=60, ell_max=40, k_max=0.1), None
+    elif case == "small_massive":
+        wl, idx = _massive(W.small_case(n_k=8, n_tau=60, ell_max=40, k_max=0.1), 0.6, 3, 6), None
+    elif case == "config1":
+        wl, idx = W.config1(), np.array([0, 150, 399])
+    else:
+        wl, idx = W.config2(), np.array([0, 200])
+    _say("case pk", case)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    Pg, st, Sg = _gpu_pk(ctx, tab)
+    assert np.all(st == 0) and np.all(Pg > 0)
+    ref = run_gpu(ctx, [tab], 2)
+    assert np.array_equal(Sg, ref["S"][0])
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    Po = O.matter_pk(t_or, idx)
+    Pg_s = Pg if idx is None else Pg[idx]
+    e = np.max(np.abs(Pg_s / Po - 1))
+    _say("pk err", e)
+    assert e <= 1e-8

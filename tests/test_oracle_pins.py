@@ -454,3 +454,52 @@ def test_physical_spectrum_shape():
     assert 190 < lp < 250 and 5000 < D[0, lp] < 6500
     assert D[1, 300] > 50
     assert D[2, 2] > D[2, 8]
+
+
+def test_matter_pk_large_scale_limit():
+    """Matter power spectrum today (App. B.4, eq. PK) on scales that entered
+    the horizon well after equality: the comoving-gauge Poisson equation with
+    Phi = (3/5) R in matter domination and the dust + Lambda growth factor give
+    P = 2 pi^2/k^3 P_R(k) [(2/5) (k/H0)^2 D(1) / Omega_m]^2, R = 1 (the eta -> 1
+    normalisation).  The oracle must agree to 0.5% at k <= 1e-4 (the radiation
+    era and the transfer function move it by ~0.2% there), and fall below it
+    as k grows (transfer function < 1)."""
+    from scipy.integrate import quad
+    wl = W.small_case(n_k=4, k_min=5e-5, k_max=4e-4, n_tau=20)
+    k = np.array([5e-5, 1e-4, 2e-4, 4e-4])
+    t = O.build_tables(wl.cosmo, wl.prec, k, 20)
+    P = O.matter_pk(t)
+    c = wl.cosmo
+    H0 = c["h"] / 2997.92458
+    Om = (c["omega_b"] + c["omega_cdm"]) / c["h"] ** 2
+
+    def E(a):
+        return np.sqrt(Om / a ** 3 + 1.0 - Om)
+
+    D1 = 2.5 * Om * E(1.0) * quad(lambda a: 1.0 / (a * E(a)) ** 3, 1e-10, 1.0, epsabs=0, epsrel=1e-12)[0]
+    Pa = 2 * np.pi ** 2 / k ** 3 * c["A_s"] * (k / 0.05) ** (c["n_s"] - 1) * (0.4 * (k / H0) ** 2 * D1 / Om) ** 2
+    r = P / Pa
+    assert np.all(np.abs(r[:2] - 1) < 5e-3), r
+    assert np.all(np.diff(r) < 0) and r[-1] < 1.0, r
+
+
+def test_matter_pk_massive_neutrinos_large_scales():
+    """With one massive neutrino, counted in Omega_m today, the large-scale
+    P(k) stays within 1.5% of the same limit (the neutrinos were relativistic
+    early on and lag the growth slightly)."""
+    from scipy.integrate import quad
+    wl = W.config2()
+    wl.prec.update(ell_gamma=10, ell_pol=10, ell_nu=10, n_q=5, ell_ncdm=8)
+    k = np.array([5e-5, 1e-4])
+    t = O.build_tables(wl.cosmo, wl.prec, k, 20)
+    P = O.matter_pk(t)
+    c = wl.cosmo
+    H0 = c["h"] / 2997.92458
+    Om = (c["omega_b"] + c["omega_cdm"] + t.bg.rho_ncdm(1.0)[0] / (100.0 / 2997.92458) ** 2) / c["h"] ** 2
+
+    def E(a):
+        return np.sqrt(Om / a ** 3 + 1.0 - Om)
+
+    D1 = 2.5 * Om * E(1.0) * quad(lambda a: 1.0 / (a * E(a)) ** 3, 1e-10, 1.0, epsabs=0, epsrel=1e-12)[0]
+    Pa = 2 * np.pi ** 2 / k ** 3 * c["A_s"] * (k / 0.05) ** (c["n_s"] - 1) * (0.4 * (k / H0) ** 2 * D1 / Om) ** 2
+    assert np.all(np.abs(P / Pa - 1) < 1.5e-2), P / Pa
