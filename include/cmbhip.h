@@ -176,6 +176,32 @@ int cmb_cl(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max
 int cmb_solve(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_S, double *d_Delta,
               double *d_Cl, int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
 
+/* ------------------------------------------------------- transfer k-grid */
+/* Transfer k-grid of App. A.2 (eq. k_transfer_spacing):
+ *   k_{n+1} = k_n + k_period linstep k_n / (k_n + linstep/logstep),
+ *   k_period = 2 pi / (tau0_fid - tau_rec_fid),
+ * from max(k_min_tau0 / tau0_fid, k_lo) to min(k_max_tau0_over_l_max ell_max
+ * / tau0_fid, k_hi), the last point being that upper end, with the paper's
+ * default constants (k_min_tau0 0.1, k_max_tau0_over_l_max 1.8, tau0_fid
+ * 14186.68 Mpc, tau_rec_fid 281.040565 Mpc, linstep 0.45, logstep 170).
+ * Writes at most cap points to k_out (may be NULL when cap = 0) and returns
+ * the number of points of the grid (call once with cap = 0 to size it), or
+ * -CMB_E_INVALID. */
+int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int cap);
+
+/* Spectra on a transfer k-grid: the sources d_S [n_cosmo][n_k][3][n_tau] of
+ * the perturbation grid (all cosmologies sharing it) are interpolated in k
+ * by natural cubic splines at every output time onto kt, then projected
+ * (App. B.4 transfer integrals) and integrated over kt (eq. Cl) as cmb_los
+ * and cmb_cl do on the perturbation grid.
+ *   kt:      host [n_kt], strictly increasing inside [k_0, k_{n_k-1}]
+ *   d_St:    device [n_cosmo][n_kt][3][n_tau], the interpolated sources
+ *   d_Delta: device [n_cosmo][2][ell_max-1][n_kt];  d_Cl: device [n_cosmo][3][ell_max+1]
+ * Caller-owned buffers, asynchronous on hip_stream.  Errors: CMB_E_INVALID,
+ * CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_spectra_on_grid(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
+                        const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 /*
  * Continuous-batching runtime for independent spectrum requests (each one

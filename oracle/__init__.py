@@ -313,6 +313,43 @@ def cl(k, DT, DE, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: floa
     return Cl
 
 
+def transfer_kgrid(ell_max: int, k_lo: float, k_hi: float) -> np.ndarray:
+    """Transfer k-grid (App. A.2, eq. k_transfer_spacing, with eq. defkperiod
+    and the k_min / k_max_cmb rules): steps k -> k + k_period linstep k /
+    (k + linstep/logstep) from max(k_min_tau0/tau0_fid, k_lo) while below
+    min(k_max_tau0_over_l_max ell_max/tau0_fid, k_hi), then that upper end.
+    Constants are the App. A.2 defaults."""
+    tau0_fid, tau_rec_fid = 1.418668e4, 281.040565
+    linstep, logstep = 0.45, 170.0
+    kmin = max(0.1 / tau0_fid, k_lo)
+    kmax = min(1.8 * ell_max / tau0_fid, k_hi)
+    kperiod = 2.0 * math.pi / (tau0_fid - tau_rec_fid)
+    out = []
+    k = kmin
+    while k < kmax:
+        out.append(k)
+        k = k + kperiod * linstep * k / (k + linstep / logstep)
+    out.append(kmax)
+    return np.array(out)
+
+
+def interp_sources(k, S: np.ndarray, kt) -> np.ndarray:
+    """Sources S[k][3][n_tau] interpolated onto kt by natural cubic splines in k
+    at every (type, output time) (scipy's CubicSpline with natural ends)."""
+    from scipy.interpolate import CubicSpline
+    sp = CubicSpline(np.asarray(k, dtype=np.float64), S, axis=0, bc_type="natural")
+    return sp(np.asarray(kt, dtype=np.float64))
+
+
+def spectra_on_grid(t, S: np.ndarray, kt, ell_max: int, pol: bool):
+    """C_ell on the transfer grid kt: interpolated sources, projection and k
+    quadrature there."""
+    St = interp_sources(t.k, S, kt)
+    DT, DE = los(t, St, ell_max, pol, k=kt)
+    C = cl(kt, DT, DE, ell_max, pol, t.cosmo["A_s"], t.cosmo["n_s"], t.prec["k_pivot"])
+    return {"St": St, "DT": DT, "DE": DE, "Cl": C}
+
+
 def solve(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, tables=None):
     """The whole path for one cosmology: tables, sources, transfers, C_ell."""
     t = build_tables(cosmo, prec, np.asarray(k, dtype=np.float64), n_tau) if tables is None else tables

@@ -42,7 +42,8 @@ MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
 # exported symbols (kept in step with include/cmbhip.h; a CPU test checks this)
 EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
-           "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
+           "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
+           "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
 
@@ -112,6 +113,9 @@ def _declare(lib):
     lib.cmb_solve_workspace_bytes.restype = ctypes.c_size_t
     lib.cmb_perturb.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp]
     lib.cmb_perturb_pk.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+    lib.cmb_transfer_kgrid.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int]
+    lib.cmb_spectra_on_grid.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _dp, ctypes.c_int,
+                                        _vp, _vp, _vp, _vp]
     lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -273,6 +277,15 @@ class Context:
         _check(_lib.cmb_perturb_pk(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _ptr(Pk),
                                    _stream(stream)), "cmb_perturb_pk")
 
+    def spectra_on_grid(self, tabs, ell_max, S, kt, St, Delta, Cl, stream=None):
+        """Sources interpolated onto the transfer grid kt, then projection and
+        k quadrature there (cmb_spectra_on_grid)."""
+        hs = _handles(tabs)
+        kt = np.ascontiguousarray(kt, dtype=np.float64)
+        _check(_lib.cmb_spectra_on_grid(self._h, hs, len(tabs), int(ell_max), _ptr(S), kt.ctypes.data_as(_dp),
+                                        len(kt), _ptr(St), _ptr(Delta), _ptr(Cl), _stream(stream)),
+               "cmb_spectra_on_grid")
+
     def los(self, tabs, ell_max, S, Delta, stream=None):
         hs = _handles(tabs)
         _check(_lib.cmb_los(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _stream(stream)), "cmb_los")
@@ -366,3 +379,13 @@ class Server:
 def server_selftest_arena(seed: int = 1, n_ops: int = 20000) -> int:
     """Host self-test of the server's device-arena allocator (no GPU)."""
     return int(_lib.cmb_server_selftest_arena(int(seed), int(n_ops)))
+
+
+def transfer_kgrid(ell_max: int, k_lo: float, k_hi: float) -> np.ndarray:
+    """The transfer k-grid of cmb_transfer_kgrid."""
+    n = _lib.cmb_transfer_kgrid(int(ell_max), float(k_lo), float(k_hi), None, 0)
+    if n < 0:
+        raise CmbError(-n, "cmb_transfer_kgrid")
+    out = np.zeros(n)
+    _lib.cmb_transfer_kgrid(int(ell_max), float(k_lo), float(k_hi), out.ctypes.data_as(_dp), n)
+    return out

@@ -103,9 +103,15 @@ struct cmb_ctx {
     // host staging for uploads (pinned)
     void *h_stage = nullptr;
     size_t h_cap = 0;
-    // cache key of the resident tables
+    // transfer-grid interpolation: small device arrays and their pinned staging
+    void *kt_buf = nullptr;
+    size_t kt_cap = 0;
+    void *kt_stage = nullptr;
+    size_t kt_stage_cap = 0;
+    // cache key of the resident tables, their device descriptors and a host copy
     std::vector<unsigned long long> resident;
     cmbhip::DevTab *d_tabs = nullptr;
+    std::vector<cmbhip::DevTab> h_tabs;
     std::mutex mu;
 };
 
@@ -292,8 +298,9 @@ void cmb_ctx_destroy(cmb_ctx *c) {
     hipGetDevice(&prev);
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf}) hipFree(p);
+    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf, c->kt_buf}) hipFree(p);
     if (c->h_stage) hipHostFree(c->h_stage);
+    if (c->kt_stage) hipHostFree(c->kt_stage);
     hipSetDevice(prev);
     delete c;
 }
@@ -302,7 +309,9 @@ void cmb_ctx_destroy(cmb_ctx *c) {
 
 namespace {
 
-size_t total_bytes(const cmb_ctx *c) { return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap; }
+size_t total_bytes(const cmb_ctx *c) {
+    return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap + c->kt_cap;
+}
 
 int grow(cmb_ctx *c, void **buf, size_t *cap, size_t need, hipStream_t s) {
     if (need <= *cap) return CMB_OK;
@@ -411,6 +420,7 @@ int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s
     if (e != hipSuccess) return herr(e, "hipMemcpyAsync (tables)");
     c->d_tabs = (cmbhip::DevTab *)c->tab_buf;
     c->resident = key;
+    c->h_tabs.assign(dt, dt + n_cosmo);
     return CMB_OK;
 }
 
@@ -594,6 +604,147 @@ int cmb_solve(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_ma
     rc = cmb_los(c, tabs, n_cosmo, ell_max, d_S, d_Delta, stream);
     if (rc) return rc;
     return cmb_cl(c, tabs, n_cosmo, ell_max, d_Delta, d_Cl, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Transfer k-grid constants: the fiducial values of App. A.2 (k_min_tau0,
+// k_max_tau0_over_l_max, tau0_fid, tau_rec_fid, k_transfer_linstep,
+// k_transfer_logstep).
+constexpr double kMinTau0 = 0.1, kMaxTau0PerL = 1.8, kTau0Fid = 1.418668e4, kTauRecFid = 281.040565;
+constexpr double kLinStep = 0.45, kLogStep = 170.0;
+
+}  // namespace
+
+extern "C" {
+
+int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int cap) {
+    if (ell_max < 2 || !(k_lo > 0) || !(k_hi > k_lo) || cap < 0 || (cap > 0 && !k_out)) {
+        set_error("cmb_transfer_kgrid: ell_max >= 2, 0 < k_lo < k_hi, cap >= 0");
+        return -CMB_E_INVALID;
+    }
+    const double kmin = std::max(kMinTau0 / kTau0Fid, k_lo);
+    const double kmax = std::min(kMaxTau0PerL * ell_max / kTau0Fid, k_hi);
+    if (!(kmax > kmin)) {
+        set_error("cmb_transfer_kgrid: empty range");
+        return -CMB_E_INVALID;
+    }
+    const double kperiod = 2.0 * M_PI / (kTau0Fid - kTauRecFid);
+    int n = 0;
+    double k = kmin;
+    while (k < kmax) {
+        if (n < cap) k_out[n] = k;
+        ++n;
+        k += kperiod * kLinStep * k / (k + kLinStep / kLogStep);
+    }
+    if (n < cap) k_out[n] = kmax;
+    ++n;
+    set_error("");
+    return n;
+}
+
+int cmb_spectra_on_grid(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
+                        const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *stream) {
+    if (!c || !d_S || !kt || !d_St || !d_Delta || !d_Cl || n_kt < 2) {
+        set_error("cmb_spectra_on_grid: NULL argument or n_kt < 2");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    const std::vector<double> &kg = tabs[0]->t.k;
+    const int nk = b.n_k;
+    for (int i = 1; i < n_cosmo; ++i)
+        if (tabs[i]->t.k != kg) {
+            set_error("cmb_spectra_on_grid: the cosmologies of one call must share the perturbation k grid");
+            return CMB_E_INVALID;
+        }
+    if (nk < 2 || b.n_tau > cmbhip::los_max_tau()) {
+        set_error("cmb_spectra_on_grid: need n_k >= 2 and n_tau within the projection kernel's limit");
+        return CMB_E_INVALID;
+    }
+    for (int q = 0; q < n_kt; ++q)
+        if (!(kt[q] >= kg.front() && kt[q] <= kg.back()) || (q > 0 && !(kt[q] > kt[q - 1]))) {
+            set_error("cmb_spectra_on_grid: kt must increase strictly inside the perturbation k range");
+            return CMB_E_INVALID;
+        }
+    // spline factors of the k grid (interior rows 1..nk-2) and the interval of every kt
+    std::vector<double> lo(nk, 0.0), dinv(nk, 0.0);
+    for (int i = 1; i < nk - 1; ++i) {
+        const double hm = kg[i] - kg[i - 1], hp = kg[i + 1] - kg[i];
+        double piv = 2.0 * (hm + hp);
+        if (i > 1) {
+            lo[i] = hm * dinv[i - 1];
+            piv -= lo[i] * hm;  // sub_i = h_{i-1}, sup_{i-1} = h_{i-1}
+        }
+        dinv[i] = 1.0 / piv;
+    }
+    std::vector<int> seg(n_kt);
+    for (int q = 0, i = 0; q < n_kt; ++q) {
+        while (i < nk - 2 && kt[q] > kg[i + 1]) ++i;
+        seg[q] = i;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    // small arrays: DevTab copies on kt | kg | lo | dinv | kt | seg
+    const size_t o_tabs = 0;
+    const size_t o_kg = align256(sizeof(cmbhip::DevTab) * n_cosmo);
+    const size_t o_lo = o_kg + align256(sizeof(double) * nk);
+    const size_t o_di = o_lo + align256(sizeof(double) * nk);
+    const size_t o_kt = o_di + align256(sizeof(double) * nk);
+    const size_t o_seg = o_kt + align256(sizeof(double) * n_kt);
+    const size_t small = o_seg + align256(sizeof(int) * n_kt);
+    rc = grow(c, &c->kt_buf, &c->kt_cap, small, s);
+    if (rc) return rc;
+    const size_t need_m = sizeof(double) * (size_t)n_cosmo * nk * 3 * b.n_tau;
+    rc = grow(c, &c->ws_buf, &c->ws_cap, need_m, s);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);  // the staging may still be read by a previous call
+    if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    if (small > c->kt_stage_cap) {
+        if (c->kt_stage) hipHostFree(c->kt_stage);
+        c->kt_stage = nullptr;
+        c->kt_stage_cap = 0;
+        e = hipHostMalloc(&c->kt_stage, small, hipHostMallocDefault);
+        if (e != hipSuccess) return herr(e, "hipHostMalloc");
+        c->kt_stage_cap = small;
+    }
+    char *h = (char *)c->kt_stage;
+    char *d = (char *)c->kt_buf;
+    cmbhip::DevTab *ht = (cmbhip::DevTab *)(h + o_tabs);
+    for (int i = 0; i < n_cosmo; ++i) {
+        ht[i] = c->h_tabs[i];
+        ht[i].k = (const double *)(d + o_kt);
+        ht[i].n_k = n_kt;
+    }
+    std::memcpy(h + o_kg, kg.data(), sizeof(double) * nk);
+    std::memcpy(h + o_lo, lo.data(), sizeof(double) * nk);
+    std::memcpy(h + o_di, dinv.data(), sizeof(double) * nk);
+    std::memcpy(h + o_kt, kt, sizeof(double) * n_kt);
+    std::memcpy(h + o_seg, seg.data(), sizeof(int) * n_kt);
+    e = hipMemcpyAsync(d, h, small, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return herr(e, "hipMemcpyAsync (transfer grid)");
+    rc = cmbhip::launch_spline_sources(d_S, (double *)c->ws_buf, (const double *)(d + o_kg),
+                                       (const double *)(d + o_lo), (const double *)(d + o_di),
+                                       (const int *)(d + o_seg), (const double *)(d + o_kt), d_St, n_cosmo, nk,
+                                       b.n_tau, n_kt, stream);
+    if (rc) return rc;
+    const cmbhip::DevTab *dt = (const cmbhip::DevTab *)(d + o_tabs);
+    rc = cmbhip::launch_los(dt, n_cosmo, n_kt, b.n_tau, ell_max, b.polar, b.s_pol, d_St, d_Delta, stream);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl(dt, n_cosmo, n_kt, ell_max, d_Delta, d_Cl, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
 }
 
 }  // extern "C"

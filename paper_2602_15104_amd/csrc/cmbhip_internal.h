@@ -85,6 +85,12 @@ int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_ma
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
               void *stream);
 int los_max_tau();
+// sources of the perturbation grid interpolated in k onto kt (natural cubic
+// splines; elimination factors lo/dinv and intervals seg from the host); M is
+// workspace of the size of S
+int launch_spline_sources(const double *d_S, double *d_M, const double *d_kg, const double *d_lo,
+                          const double *d_dinv, const int *d_seg, const double *d_kt, double *d_St, int n_cosmo,
+                          int n_k, int n_tau, int n_kt, void *stream);
 int ell_cut(double x);  // host copy of the Bessel cut rule (tests)
 
 }  // namespace cmbhip

@@ -174,3 +174,23 @@ def test_server_arena_allocator(lib):
     aligned, account every byte, and coalesce back to one block."""
     for seed in range(8):
         assert lib.server_selftest_arena(seed, 20000) == 0
+
+
+@pytest.mark.parametrize("ell_max,k_lo,k_hi", [(2500, 1e-5, 0.5), (3000, 1e-4, 0.05), (20, 1e-7, 10.0), (2, 1e-6, 1.0)])
+def test_transfer_kgrid_matches_oracle(lib, ell_max, k_lo, k_hi):
+    """cmb_transfer_kgrid (host code) against the oracle's own step-law grid
+    (App. A.2 eq. k_transfer_spacing): same length, same points."""
+    import oracle as O
+    a = lib.transfer_kgrid(ell_max, k_lo, k_hi)
+    b = O.transfer_kgrid(ell_max, k_lo, k_hi)
+    assert len(a) == len(b) >= 2
+    np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)
+    assert lib._lib.cmb_transfer_kgrid(ell_max, k_lo, k_hi, None, 0) == len(a)
+
+
+@pytest.mark.parametrize("args", [(1, 1e-5, 0.5), (2500, 0.0, 0.5), (2500, 0.5, 0.1), (2500, 1.0, 2.0)])
+def test_transfer_kgrid_errors(lib, args):
+    """Rejected: ell_max < 2, k_lo <= 0, k_hi <= k_lo, and a range that the
+    k_max_cmb rule leaves empty."""
+    with pytest.raises(lib.CmbError):
+        lib.transfer_kgrid(*args)

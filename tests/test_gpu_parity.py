@@ -432,3 +432,108 @@ def test_matter_pk_parity(ctx, case):
     e = np.max(np.abs(Pg_s / Po - 1))
     _say("pk err", e)
     assert e <= 1e-8
+
+
+# ---------------------------------------------------------------- transfer k-grid
+def _gpu_on_grid(ctx, tabs, ell_max, S, kt):
+    import torch
+    B, n_tau = len(tabs), tabs[0].n_tau
+    dS = S if isinstance(S, torch.Tensor) else torch.tensor(S, device="cuda:0")
+    St = torch.empty((B, len(kt), 3, n_tau), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((B, 2, ell_max - 1, len(kt)), dtype=torch.float64, device="cuda:0")
+    C = torch.empty((B, 3, ell_max + 1), dtype=torch.float64, device="cuda:0")
+    ctx.spectra_on_grid(tabs, ell_max, dS, kt, St, D, C)
+    torch.cuda.synchronize()
+    return St.cpu().numpy(), D.cpu().numpy(), C.cpu().numpy()
+
+
+def test_transfer_grid_interp_same_sources(ctx):
+    """Spline stage alone: seeded random sources on a 50-mode grid, onto a
+    transfer grid with ragged spacing, against the oracle's natural splines
+    (relative to each (k~, type) row's largest value, <= 1e-12); C_ell of the
+    interpolated sources against the oracle's projection of the same."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=50, n_tau=90, ell_max=50, k_max=0.1)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    kt = L.transfer_kgrid(1500, wl.k[0], wl.k[-1])
+    assert kt[0] == wl.k[0] and kt[-1] == wl.k[-1]
+    rng = np.random.Generator(np.random.PCG64(11))
+    S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
+    _say("case interp", len(kt), "points")
+    St, D, C = _gpu_on_grid(ctx, [tab], wl.ell_max, S, kt)
+    So = O.interp_sources(wl.k, S[0], kt)
+    e = src_err(St[0], So)
+    _say("interp err", e)
+    assert e <= 1e-12
+    DT, DE = O.los(t_or, St[0], wl.ell_max, True, k=kt)
+    for plane, ref in ((0, DT), (1, DE)):
+        assert np.max(np.abs(D[0, plane] - ref)) <= 1e-9 * np.max(np.abs(ref))
+    Co = O.cl(kt, D[0, 0], D[0, 1], wl.ell_max, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
+    np.testing.assert_allclose(C[0][:, 2:], Co[:, 2:], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("pol", [True, False])
+def test_transfer_grid_full_parity(ctx, pol):
+    """Whole path onto the transfer grid: each side integrates its own modes,
+    interpolates its own sources onto k~ and projects there."""
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=24, n_tau=120, ell_max=120, k_max=0.05, polarization=pol)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    kt = L.transfer_kgrid(wl.ell_max * 3, wl.k[0], wl.k[-1])
+    _say("case transfer small", pol, len(kt))
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    St, D, C = _gpu_on_grid(ctx, [tab], wl.ell_max, g["S"], kt)
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, pol)
+    ro = O.spectra_on_grid(r["tables"], r["S"], kt, wl.ell_max, pol)
+    e = src_err(St[0], ro["St"])
+    tt, te, ee = cl_err(C[0], ro["Cl"])
+    _say("source err", e, "cl err", tt, te, ee)
+    assert e <= 1e-8 and tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+
+
+def test_transfer_grid_batch_and_errors(ctx):
+    """Two cosmologies on one k grid: each result equals its solo call bit for
+    bit.  Rejected: k~ outside the mode grid, not increasing, fewer than two
+    points, and batches whose k grids differ."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=16, n_tau=60, ell_max=30, k_max=0.05)
+    cosmos = W.perturbed_cosmologies(2, seed=5)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    g = run_gpu(ctx, tabs, wl.ell_max)
+    kt = L.transfer_kgrid(2500, wl.k[0], wl.k[-1])
+    Sb, Db, Cb = _gpu_on_grid(ctx, tabs, wl.ell_max, g["S"], kt)
+    S1, D1, C1 = _gpu_on_grid(ctx, [tabs[1]], wl.ell_max, g["S"][1:], kt)
+    assert np.array_equal(Sb[1], S1[0]) and np.array_equal(Cb[1], C1[0])
+    dS = torch.tensor(g["S"][:1], device="cuda:0")
+    for bad in (np.array([wl.k[0] * 0.5, wl.k[-1]]), kt[::-1].copy(), kt[:1].copy(),
+                np.array([wl.k[0], wl.k[-1] * 1.01])):
+        with pytest.raises(L.CmbError):
+            _gpu_on_grid(ctx, tabs[:1], wl.ell_max, dS, bad)
+    other = L.Tables(cosmos[0], wl.prec, wl.k * 1.001, wl.n_tau)
+    with pytest.raises(L.CmbError):
+        _gpu_on_grid(ctx, [tabs[0], other], wl.ell_max, torch.tensor(g["S"], device="cuda:0"), kt)
+
+
+def test_config1_transfer_grid(ctx):
+    """Config 1 (400 modes, 2000 times, l <= 2500) on the App. A.2 transfer
+    grid for l_max = 2500 (1699 points): C_ell against the stored oracle
+    spectrum on the same grid (tests/golden/make_oracle_reference.py)."""
+    import paper_2602_15104_amd as L
+    ref = os.path.join(GOLD, "oracle_config1_transfer_cl.npy")
+    if not os.path.exists(ref):
+        pytest.skip("stored oracle spectrum absent")
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    kt = L.transfer_kgrid(wl.ell_max, wl.k[0], wl.k[-1])
+    _say("case config1 transfer", len(kt))
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    St, D, C = _gpu_on_grid(ctx, [tab], wl.ell_max, g["S"], kt)
+    tt, te, ee = cl_err(C[0], np.load(ref))
+    _say("cl err", tt, te, ee)
+    assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6

@@ -503,3 +503,78 @@ def test_matter_pk_massive_neutrinos_large_scales():
     D1 = 2.5 * Om * E(1.0) * quad(lambda a: 1.0 / (a * E(a)) ** 3, 1e-10, 1.0, epsabs=0, epsrel=1e-12)[0]
     Pa = 2 * np.pi ** 2 / k ** 3 * c["A_s"] * (k / 0.05) ** (c["n_s"] - 1) * (0.4 * (k / H0) ** 2 * D1 / Om) ** 2
     assert np.all(np.abs(P / Pa - 1) < 1.5e-2), P / Pa
+
+
+# ---------------------------------------------------------------- P14 transfer k-grid
+def test_transfer_kgrid_step_law():
+    """App. A.2 eq. k_transfer_spacing with eq. defkperiod: the step is
+    logarithmic (d ln k -> k_period logstep) at small k and linear
+    (dk -> k_period linstep) at large k; the grid runs from k_min = 0.1/tau0_fid
+    to k_max_cmb = 1.8 ell_max/tau0_fid (or the caller's bounds inside them)."""
+    fid = GOLD["fiducials"]
+    tau0, taur = fid["tau0_fid_Mpc"], fid["tau_rec_fid_Mpc"]
+    kper = 2 * math.pi / (tau0 - taur)
+    kt = O.transfer_kgrid(20000, 1e-7, 10.0)
+    assert kt[0] == 0.1 / tau0 and kt[-1] == 1.8 * 20000 / tau0
+    d = np.diff(kt)
+    assert np.all(d > 0)
+    assert abs(d[0] / kt[0] / (kper * 170.0) - 1) < 3e-3  # k_0 logstep/linstep ~ 3e-3
+    assert abs(d[-2] / (kper * 0.45) - 1) < 2e-3  # linstep/(logstep k) ~ 1e-3
+    # every step lies between its two limits, and the caller's bounds clip
+    assert np.all(d[:-1] < kper * 0.45) and np.all(d[:-1] < kper * 170.0 * kt[:-2])
+    kc = O.transfer_kgrid(2500, 1e-3, 0.2)
+    assert kc[0] == 1e-3 and kc[-1] == 0.2 and np.all(np.diff(kc) > 0)
+    # the last step may be short but never longer than the law
+    assert kc[-1] - kc[-2] <= kper * 0.45 * kc[-2] / (kc[-2] + 0.45 / 170.0) * (1 + 1e-14)
+
+
+def test_interp_sources_spline_properties():
+    """Natural cubic splines in k: knots reproduced, linear functions exact,
+    zero second derivative at both ends, O(h^4) error on a smooth function."""
+    from scipy.interpolate import CubicSpline
+    k = np.cumsum(np.linspace(0.01, 0.03, 40))
+    kt = np.linspace(k[0], k[-1], 333)
+    S = np.empty((len(k), 3, 5))
+    for ty in range(3):
+        for j in range(5):
+            S[:, ty, j] = (ty - 1.5) * k + j
+    St = O.interp_sources(k, S, kt)
+    for ty in range(3):
+        for j in range(5):
+            assert np.allclose(St[:, ty, j], (ty - 1.5) * kt + j, rtol=0, atol=1e-13)
+    R = np.random.default_rng(3).standard_normal(S.shape)
+    assert np.allclose(O.interp_sources(k, R, k), R, rtol=0, atol=1e-14)
+    S2 = np.sin(3 * k)[:, None, None] * np.ones((1, 3, 5))
+    sp = CubicSpline(k, S2, axis=0, bc_type="natural")
+    assert np.max(np.abs(sp(k[[0, -1]], 2))) < 1e-12
+    St2 = O.interp_sources(k, S2, kt)
+    # interior bound 5/384 h^4 max|f''''| ~ 9e-7; the end error decays ~3.7x a knot
+    mid = (kt > k[8]) & (kt < k[-9])
+    assert np.max(np.abs(St2[mid, 0, 0] - np.sin(3 * kt[mid]))) < 2e-6
+
+
+def test_spectra_on_grid_invariants(tab12):
+    """On the perturbation grid itself the transfer-grid path is the plain
+    path (the spline passes through its knots); a source constant in k gives
+    the spike closed form (C_l = 2 pi A_s/(l(l+1)) for n_s = 1) on a dense
+    transfer grid."""
+    t = tab12
+    rng = np.random.default_rng(7)
+    S = rng.standard_normal((len(t.k), 3, len(t.chi_src)))
+    r = O.spectra_on_grid(t, S, t.k, 20, True)
+    DT, DE = O.los(t, S, 20, True)
+    C = O.cl(t.k, DT, DE, 20, True, t.cosmo["A_s"], t.cosmo["n_s"], t.prec["k_pivot"])
+    assert np.allclose(r["Cl"], C, rtol=1e-12, atol=0)
+    j = 30
+    chis = t.chi_src[j]
+    S = np.zeros((len(t.k), 3, len(t.chi_src)))
+    S[:, 0, j] = 1.0 / t.w_src[j]
+    kt = np.linspace(t.k[0], t.k[-1], 4000)
+    tt = O.build_tables(dict(t.cosmo, n_s=1.0), t.prec, t.k, len(t.chi_src))
+    r = O.spectra_on_grid(tt, S, kt, 20, False)
+    L = np.arange(21)
+    ex = 2 * math.pi * tt.cosmo["A_s"] / (L[2:] * (L[2:] + 1.0))
+    xmin, xmax = kt[0] * chis, kt[-1] * chis  # keep l well inside the k range
+    ok = (L[2:] > 3 * xmin) & (L[2:] < xmax / 3)
+    assert ok.sum() >= 5
+    assert np.max(np.abs(r["Cl"][0, 2:][ok] / ex[ok] - 1)) < 1e-3
