@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--plain-reps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", type=int, default=1, help="time the spectrum-side variants (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="Poisson serving workload: requests replayed (0 = skip)")
     ap.add_argument("--serving-plain-requests", type=int, default=128,
@@ -247,6 +248,55 @@ def main():
             plain_ms.append((time.perf_counter() - ts) * 1e3)
     print(f"[bench] plain p50 {pct(plain_ms, 50):.1f} ms", file=sys.stderr, flush=True)
 
+    # spectrum-side variants on the same batch (outside `value`): the transfer
+    # k-grid (spline interpolation + projection + quadrature on 1699 points) and
+    # the perturbation launch with the matter power spectrum today
+    variants = {}
+    if args.variants:
+        ktg = L.transfer_kgrid(lmax, float(wl.k[0]), float(wl.k[-1]))
+        St = torch.empty((B, len(ktg), 3, n_tau), dtype=torch.float64, device=dev)
+        Dt = torch.empty((B, 2, lmax - 1, len(ktg)), dtype=torch.float64, device=dev)
+        Ct = torch.empty((B, 3, lmax + 1), dtype=torch.float64, device=dev)
+        Pk = torch.empty((B, n_k), dtype=torch.float64, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tg, tp = [], []
+        for r in range(3):
+            e0.record()
+            ctx.spectra_on_grid(tabs, lmax, S, ktg, St, Dt, Ct)
+            e1.record()
+            torch.cuda.synchronize()
+            tg.append(e0.elapsed_time(e1))
+            e0.record()
+            ctx.perturb_pk(tabs, S, st, Pk, ns)
+            e1.record()
+            torch.cuda.synchronize()
+            tp.append(e0.elapsed_time(e1))
+        variants["transfer_grid"] = {"n_kt": len(ktg), "ms_per_batch": float(np.median(tg[1:])),
+                                     "batch": B, "what": "natural-spline sources onto the App. A.2 transfer grid, "
+                                                         "projection and k quadrature there"}
+        variants["perturb_pk"] = {"ms_per_batch": float(np.median(tp[1:])), "batch": B,
+                                  "perturb_ms": float(np.mean(kt["perturb"]))}
+        del St, Dt, Ct, Pk
+        # three-region Bessel scheme in the projection (table built outside the timing)
+        D3 = torch.empty_like(D)
+        t0b = time.perf_counter()
+        ctx.los_bessel3(tabs[:1], lmax, S[:1], D3[:1])
+        torch.cuda.synchronize()
+        t_b3 = time.perf_counter() - t0b
+        t3 = []
+        for r in range(3):
+            e0.record()
+            ctx.los_bessel3(tabs, lmax, S, D3)
+            e1.record()
+            torch.cuda.synchronize()
+            t3.append(e0.elapsed_time(e1))
+        variants["los_bessel3"] = {"ms_per_batch": float(np.median(t3[1:])), "los_ms": float(np.mean(kt["los"])),
+                                   "first_call_s_incl_table": t_b3, "batch": B}
+        del D3
+        print(f"[bench] variants: transfer grid {variants['transfer_grid']['ms_per_batch']:.1f} ms, "
+              f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
+              f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms", file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel (algorithmic flops / measured duration)
     exs = [t.export() for t in tabs]
     f_k1 = float(np.sum(nsteps)) * k1_flops_per_step(N) + B * n_k * n_tau * K1_FLOPS_PER_OUTPUT
@@ -283,6 +333,7 @@ def main():
         "mean_steps_per_mode": float(np.mean(nsteps)),
         "modes_not_ok": int(np.sum(status != 0)),
         "host_table_ms_per_cosmology": t_tables * 1e3,
+        "variants": variants,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": k1_traffic(B) if dom == "perturb" else None},

@@ -202,6 +202,30 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
 int cmb_spectra_on_grid(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
                         const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *hip_stream);
 
+/* ------------------------------------------- three-region Bessel variant */
+/* The paper's three-region spherical Bessel scheme (App. B.4, below the
+ * transfer integrals): for each l >= 1, j_l = 0 up to x_start(l) (the first x
+ * where j_l reaches 1e-10), linear interpolation on 5000 equally spaced exact
+ * samples over [x_start(l), x_5(l)] (x_5 the fifth local maximum of j_l), and
+ * the leading Debye-type asymptotic form above x_5.
+ *
+ * cmb_bessel3_table: the context's table for 1 <= l <= ell_max, built on the
+ * device at the first call that needs it (and rebuilt whole for a larger
+ * ell_max), copied to host arrays: h_xs[ell_max] = x_start, h_x5[ell_max] =
+ * x_5, h_tab[ell_max][5000] = j_l at x_start + i (x_5 - x_start)/4999 (index
+ * l - 1; any pointer may be NULL).  Synchronous.  Errors: CMB_E_INVALID,
+ * CMB_E_DEVICE (also when a root search fails), CMB_E_NOMEM (the table takes
+ * 8 (5002 ell_max) bytes of the context's budget). */
+int cmb_bessel3_table(cmb_ctx *ctx, int ell_max, double *h_xs, double *h_x5, double *h_tab);
+
+/* cmb_los with the three-region scheme in place of the exact recurrence:
+ * the same arguments, layouts and errors; j_l' = j_{l-1} - (l+1) j_l / x and
+ * j_l'' from Bessel's equation, both from the scheme's values.  A speed and
+ * accuracy variant of the projection; the first call for a larger ell_max
+ * builds the table and synchronises hip_stream. */
+int cmb_los_bessel3(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
+                    double *d_Delta, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 /*
  * Continuous-batching runtime for independent spectrum requests (each one

@@ -43,6 +43,7 @@ MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
 EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
+           "cmb_bessel3_table", "cmb_los_bessel3",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -117,6 +118,8 @@ def _declare(lib):
     lib.cmb_spectra_on_grid.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _dp, ctypes.c_int,
                                         _vp, _vp, _vp, _vp]
     lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.cmb_bessel3_table.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp]
+    lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.cmb_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(CServerOpts), ctypes.POINTER(_vp)]
@@ -289,6 +292,21 @@ class Context:
     def los(self, tabs, ell_max, S, Delta, stream=None):
         hs = _handles(tabs)
         _check(_lib.cmb_los(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _stream(stream)), "cmb_los")
+
+    def los_bessel3(self, tabs, ell_max, S, Delta, stream=None):
+        """cmb_los with the three-region Bessel scheme (cmb_los_bessel3)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_los_bessel3(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _stream(stream)),
+               "cmb_los_bessel3")
+
+    def bessel3_table(self, ell_max, samples=True):
+        """The context's three-region Bessel table for 1 <= l <= ell_max:
+        (x_start, x_5, samples[l-1][5000] or None)."""
+        xs, x5 = np.zeros(ell_max), np.zeros(ell_max)
+        tab = np.zeros((ell_max, 5000)) if samples else None
+        _check(_lib.cmb_bessel3_table(self._h, int(ell_max), xs.ctypes.data_as(_dp), x5.ctypes.data_as(_dp),
+                                      tab.ctypes.data_as(_dp) if samples else None), "cmb_bessel3_table")
+        return xs, x5, tab
 
     def cl(self, tabs, ell_max, Delta, Cl, stream=None):
         hs = _handles(tabs)

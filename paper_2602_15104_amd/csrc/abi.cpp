@@ -108,6 +108,10 @@ struct cmb_ctx {
     size_t kt_cap = 0;
     void *kt_stage = nullptr;
     size_t kt_stage_cap = 0;
+    // three-region Bessel table: x_start[L] | x_5[L] | samples[L][B3_PTS], built for l <= b3_lmax
+    void *b3_buf = nullptr;
+    size_t b3_cap = 0;
+    int b3_lmax = 0;
     // cache key of the resident tables, their device descriptors and a host copy
     std::vector<unsigned long long> resident;
     cmbhip::DevTab *d_tabs = nullptr;
@@ -298,7 +302,7 @@ void cmb_ctx_destroy(cmb_ctx *c) {
     hipGetDevice(&prev);
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf, c->kt_buf}) hipFree(p);
+    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf, c->kt_buf, c->b3_buf}) hipFree(p);
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->kt_stage) hipHostFree(c->kt_stage);
     hipSetDevice(prev);
@@ -310,7 +314,7 @@ void cmb_ctx_destroy(cmb_ctx *c) {
 namespace {
 
 size_t total_bytes(const cmb_ctx *c) {
-    return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap + c->kt_cap;
+    return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap + c->kt_cap + c->b3_cap;
 }
 
 int grow(cmb_ctx *c, void **buf, size_t *cap, size_t need, hipStream_t s) {
@@ -643,6 +647,90 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
     ++n;
     set_error("");
     return n;
+}
+
+}  // extern "C"
+
+// the context's three-region Bessel table covering l <= ell_max (rebuilt
+// whole, on the caller's stream, when a larger l_max is asked for)
+static int ensure_bessel3(cmb_ctx *c, int ell_max, hipStream_t s) {
+    if (c->b3_lmax >= ell_max) return CMB_OK;
+    const size_t need = sizeof(double) * (size_t)ell_max * (2 + cmbhip::B3_PTS);
+    c->b3_lmax = 0;
+    int rc = grow(c, &c->b3_buf, &c->b3_cap, need, s);
+    if (rc) return rc;
+    double *xs = (double *)c->b3_buf, *x5 = xs + ell_max, *tab = x5 + ell_max;
+    rc = cmbhip::launch_bessel3_build(1, ell_max, xs, x5, tab, s);
+    if (rc) return rc;
+    std::vector<double> h(2 * (size_t)ell_max);
+    hipError_t e = hipMemcpyAsync(h.data(), xs, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return herr(e, "bessel table build");
+    for (int l = 1; l <= ell_max; ++l)
+        if (!(h[ell_max + l - 1] > h[l - 1]) || (l > 1 && !(h[l - 1] >= h[l - 2]))) {
+            set_error("bessel table build: x_start / x_5 search failed at l = " + std::to_string(l));
+            return CMB_E_DEVICE;
+        }
+    c->b3_lmax = ell_max;
+    return CMB_OK;
+}
+
+extern "C" {
+
+int cmb_bessel3_table(cmb_ctx *c, int ell_max, double *h_xs, double *h_x5, double *h_tab) {
+    if (!c || ell_max < 1 || ell_max > 10000) {
+        set_error("cmb_bessel3_table: NULL context or ell_max outside [1, 10000]");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = nullptr;
+    int rc = ensure_bessel3(c, ell_max, s);
+    if (rc) return rc;
+    const int L = c->b3_lmax;
+    const double *xs = (const double *)c->b3_buf, *x5 = xs + L, *tab = x5 + L;
+    hipError_t e = hipSuccess;
+    if (h_xs) e = hipMemcpy(h_xs, xs, sizeof(double) * ell_max, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_x5) e = hipMemcpy(h_x5, x5, sizeof(double) * ell_max, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_tab)
+        e = hipMemcpy(h_tab, tab, sizeof(double) * (size_t)ell_max * cmbhip::B3_PTS, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return herr(e, "hipMemcpy (bessel table)");
+    set_error("");
+    return CMB_OK;
+}
+
+int cmb_los_bessel3(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
+                    double *d_Delta, void *stream) {
+    if (!c || !d_S || !d_Delta) {
+        set_error("cmb_los_bessel3: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    if (b.n_tau > cmbhip::los_max_tau()) {
+        set_error("n_tau above the line-of-sight kernel's limit");
+        return CMB_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = ensure_bessel3(c, ell_max, s);
+    if (rc) return rc;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    const int L = c->b3_lmax;
+    const double *xs = (const double *)c->b3_buf, *x5 = xs + L, *tab = x5 + L;
+    rc = cmbhip::launch_los3(c->d_tabs, n_cosmo, b.n_k, b.n_tau, ell_max, b.polar, b.s_pol, d_S, xs, x5, tab, d_Delta,
+                             stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
 }
 
 int cmb_spectra_on_grid(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,

@@ -92,5 +92,13 @@ int launch_spline_sources(const double *d_S, double *d_M, const double *d_kg, co
                           const double *d_dinv, const int *d_seg, const double *d_kt, double *d_St, int n_cosmo,
                           int n_k, int n_tau, int n_kt, void *stream);
 int ell_cut(double x);  // host copy of the Bessel cut rule (tests)
+// three-region Bessel scheme: samples per multipole, table build for
+// l_lo..l_hi (x_start[l-1], x_5[l-1] (NaN if not found), tab[l-1][B3_PTS]) and
+// the projection with it
+constexpr int B3_PTS = 5000;
+int launch_bessel3_build(int l_lo, int l_hi, double *d_xs, double *d_x5, double *d_tab, void *stream);
+int launch_los3(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E, double s_pol,
+                const double *d_S, const double *d_xs, const double *d_x5, const double *d_tab, double *d_Delta,
+                void *stream);
 
 }  // namespace cmbhip

@@ -27,14 +27,14 @@ def lib():
 def header_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(cmb_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(cmb_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_exports_match_header(lib):
     declared = header_functions()
     assert len(declared) >= 13
     out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (cmb_[a-z_]+)\b", out))
+    exported = set(re.findall(r"\bT (cmb_[a-z0-9_]+)\b", out))
     missing = [f for f in declared if f not in exported]
     assert not missing, missing
     assert sorted(lib.EXPORTS) == declared

@@ -537,3 +537,85 @@ def test_config1_transfer_grid(ctx):
     tt, te, ee = cl_err(C[0], np.load(ref))
     _say("cl err", tt, te, ee)
     assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+
+
+# ---------------------------------------------------------------- three-region Bessel variant
+def test_bessel3_table_parity(ctx):
+    """The device-built table (Miller recurrence and root searches on the GPU)
+    against the oracle's (scipy samples, its own searches), every l <= 300:
+    x_start and x_5 to 1e-12 relative, samples to 1e-12 of each row's peak."""
+    from oracle import bessel3 as B3
+    xs, x5, tab = ctx.bessel3_table(300)
+    T = B3.Table(300)
+    e_s, e_5 = np.max(np.abs(xs / T.xs - 1)), np.max(np.abs(x5 / T.x5 - 1))
+    err = np.max(np.abs(tab - T.tab), axis=1) / np.max(np.abs(T.tab), axis=1)
+    _say("bessel3 table l<=300: x_start", e_s, "x_5", e_5, "samples", np.max(err))
+    assert e_s < 1e-12 and e_5 < 1e-12 and np.max(err) < 1e-12
+
+
+def test_bessel3_table_full_size_sampled(ctx):
+    """l_max = 2500: every x_start and x_5, and the samples of a few rows."""
+    from scipy.special import spherical_jn
+    from oracle import bessel3 as B3
+    xs, x5, tab = ctx.bessel3_table(2500)
+    ells = np.arange(1, 2501)
+    oxs, ox5 = B3.x_start(ells), B3.x_fifth_max(ells)
+    assert np.max(np.abs(xs / oxs - 1)) < 1e-12 and np.max(np.abs(x5 / ox5 - 1)) < 1e-12
+    for l in (1, 2, 777, 2499, 2500):
+        dx = (ox5[l - 1] - oxs[l - 1]) / 4999
+        ref = spherical_jn(l, oxs[l - 1] + dx * np.arange(5000))
+        assert np.max(np.abs(tab[l - 1] - ref)) < 1e-12 * np.max(np.abs(ref)), l
+
+
+def test_los_bessel3_same_sources(ctx):
+    """The variant projection alone: seeded random sources, 30 modes up to
+    k = 0.1 (x up to ~1400, all three regions), 300 output times (two per
+    lane, ragged), l <= 150, against the oracle's scheme: Delta per k to 1e-9
+    of its largest value, C_ell of the same Delta to 1e-12."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    from oracle import bessel3 as B3
+    wl = W.small_case(n_k=30, n_tau=300, ell_max=150, k_max=0.1)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    rng = np.random.Generator(np.random.PCG64(17))
+    S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
+    dS = torch.tensor(S, device="cuda:0")
+    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
+    ctx.los_bessel3([tab], wl.ell_max, dS, D)
+    ctx.cl([tab], wl.ell_max, D, C)
+    torch.cuda.synchronize()
+    DT, DE = B3.los3(t_or, S[0], wl.ell_max, True, T=B3.Table(wl.ell_max))
+    Dg = D.cpu().numpy()[0]
+    worst = 0.0
+    for ik in range(len(wl.k)):
+        for plane, ref in ((0, DT), (1, DE)):
+            den = np.max(np.abs(ref[:, ik]))
+            worst = max(worst, np.max(np.abs(Dg[plane][:, ik] - ref[:, ik])) / den)
+    _say("los3 same sources: Delta err", worst)
+    assert worst <= 1e-9
+    Co = O.cl(t_or.k, Dg[0], Dg[1], wl.ell_max, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
+    np.testing.assert_allclose(C.cpu().numpy()[0][:, 2:], Co[:, 2:], rtol=1e-12, atol=0)
+
+
+def test_los_bessel3_config1_error(ctx):
+    """Measured accuracy of the scheme at config 1 (400 modes, 2000 times,
+    l <= 2500): its C_ell against the exact recurrence's from the same GPU
+    sources.  A measurement, bounded loosely (the scheme's Debye form carries
+    a 1/(8x) phase error)."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    dS = torch.tensor(g["S"], device="cuda:0")
+    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
+    ctx.los_bessel3([tab], wl.ell_max, dS, D)
+    ctx.cl([tab], wl.ell_max, D, C)
+    torch.cuda.synchronize()
+    tt, te, ee = cl_err(C.cpu().numpy()[0], g["Cl"][0])
+    _say("config1 three-region vs exact: TT", tt, "TE", te, "EE", ee)
+    assert tt < 5e-2 and te < 5e-2 and ee < 5e-2

@@ -578,3 +578,92 @@ def test_spectra_on_grid_invariants(tab12):
     ok = (L[2:] > 3 * xmin) & (L[2:] < xmax / 3)
     assert ok.sum() >= 5
     assert np.max(np.abs(r["Cl"][0, 2:][ok] / ex[ok] - 1)) < 1e-3
+
+
+# ---------------------------------------------------------------- P15 three-region Bessel scheme
+@pytest.fixture(scope="module")
+def b3tab():
+    from oracle import bessel3 as B3
+    return B3.Table(80)
+
+
+def _mp_j(l, x, d=0):
+    import mpmath as mp
+    f = lambda z: mp.sqrt(mp.pi / (2 * z)) * mp.besselj(l + 0.5, z)  # noqa: E731
+    return float(mp.diff(f, mp.mpf(x), d)) if d else float(f(mp.mpf(x)))
+
+
+@pytest.mark.parametrize("l", [1, 7, 60, 80])
+def test_bessel3_edges_vs_mpmath(b3tab, l):
+    """x_start: j_l = 1e-10 there; x_5: a zero of j_l' with j_l'' < 0 and
+    exactly four positive peaks of j_l before it (mpmath, independent of the
+    scipy samples the scheme stores)."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    xs, x5 = b3tab.xs[l - 1], b3tab.x5[l - 1]
+    assert abs(_mp_j(l, xs) / 1e-10 - 1) < 1e-9
+    amp = abs(_mp_j(l, x5))
+    assert abs(_mp_j(l, x5, 1)) < 1e-12 * amp and _mp_j(l, x5, 2) < 0
+    grid = np.linspace(xs, x5 - 0.05, 400)
+    d = np.array([_mp_j(l, g, 1) for g in grid])
+    assert int(np.sum((d[:-1] > 0) & (d[1:] <= 0))) == 4
+
+
+def test_bessel3_debye_limit():
+    """The Debye-type form tends to j_l far above the turning point: its phase
+    expands as x - nu pi/2 - pi/4 + nu^2/(2x) + ..., the exact one as
+    x - (l+1) pi/2 + l(l+1)/(2x) + ..., and nu^2 - l(l+1) = 1/4, so x |error|
+    stays below 1/(8x) (plus higher orders) and reaches it at the zeros."""
+    from oracle import bessel3 as B3
+    for l in (2, 30):
+        for x0 in (400.0, 4000.0):
+            xx = x0 + np.linspace(0, 2 * math.pi, 25)
+            e = np.array([abs(B3.debye(l, v) - _mp_j(l, v)) * v for v in xx])
+            assert np.max(e) <= 1.05 / (8 * x0) and np.max(e) >= 0.8 / (8 * (x0 + 7))
+
+
+@pytest.mark.parametrize("l", [3, 45, 80])
+def test_bessel3_regions(b3tab, l):
+    """Zero below x_start; inside [x_start, x_5] linear interpolation within
+    its bound dx^2/8 max|j''| (|j''| <= 1) of the exact value; the Debye form
+    above x_5."""
+    from oracle import bessel3 as B3
+    xs, x5, dx = b3tab.xs[l - 1], b3tab.x5[l - 1], b3tab.dx[l - 1]
+    rng = np.random.default_rng(l)
+    below = rng.uniform(0, xs, 20)
+    assert np.all(B3.j3(b3tab, l, below) == 0)
+    inside = rng.uniform(xs, x5, 40)
+    ex = np.array([_mp_j(l, v) for v in inside])
+    assert np.max(np.abs(B3.j3(b3tab, l, inside) - ex)) <= dx * dx / 8 + 1e-14
+    above = rng.uniform(x5 * 1.001, 3 * x5, 10)
+    assert np.array_equal(B3.j3(b3tab, l, above), B3.debye(l, above))
+
+
+def test_los3_assembly_with_exact_bessel(tab12):
+    """The scheme's projection with the exact j_l in place of the scheme
+    equals the oracle's recurrence-based projection (same sources): checks
+    j' from j_{l-1}, j'' from Bessel's equation, the weights and the E
+    factor."""
+    from scipy.special import spherical_jn
+    from oracle import bessel3 as B3
+    t = tab12
+    rng = np.random.default_rng(5)
+    S = rng.standard_normal((len(t.k), 3, len(t.chi_src)))
+    DT, DE = B3.los3(t, S, 20, True, jfun=lambda l, x: spherical_jn(l, x))
+    RT, RE = O.los(t, S, 20, True)
+    for a, b in ((DT, RT), (DE, RE)):
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+
+
+def test_los3_scheme_error_small(b3tab):
+    """The scheme itself against the exact projection on physical sources
+    (small hierarchy, l <= 80): the spectra differ at the level of the
+    scheme's approximations (measured ~1e-4), far below the spectra."""
+    from oracle import bessel3 as B3
+    wl = W.small_case(n_k=40, n_tau=150, ell_max=80, k_max=0.05)
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
+    t = r["tables"]
+    DT, DE = B3.los3(t, r["S"], 80, True, T=b3tab)
+    C = O.cl(t.k, DT, DE, 80, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
+    e = np.max(np.abs(C[0, 2:] / r["Cl"][0, 2:] - 1))
+    assert 0 < e < 1e-2
