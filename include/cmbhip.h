@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-#define CMB_ABI_VERSION 1
+#define CMB_ABI_VERSION 2
 
 /* call-level return codes */
 enum {
@@ -109,6 +109,14 @@ typedef struct cmb_table_view {
     const double *M_ln_dk, *M_kappa, *M_ln_cs2, *M_ln_tau; /* [n_tab+1] second derivatives */
     const double *q, *W;                              /* [n_q] momentum rule */
     double rt_g0, rt_ur0, rt_c0, rt_b0, rt_L, pref_ncdm, m_over_T, H0;
+    /* lensing (App. B.5): conformal time of the visibility peak (parabola
+     * through the three table knots around the largest kappa' e^-kappa),
+     * chi_* = tau0 - tau_star, and the Limber weights per output time
+     * w_j / chi_j (3/2 a_j^2 rho_m(a_j))^2 ((chi_* - chi_j)/chi_*)^2 for
+     * 0 < chi_j < chi_* (else 0), rho_m over CDM, baryons and massive nu in
+     * units where H^2 = sum rho (Mpc^-2) */
+    double tau_star, chi_star;
+    const double *lens_w; /* [n_tau] */
 } cmb_table_view;
 int cmb_tables_export(const cmb_tables *t, cmb_table_view *out);
 
@@ -201,6 +209,34 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
  * CMB_E_DEVICE, CMB_E_NOMEM. */
 int cmb_spectra_on_grid(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
                         const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *hip_stream);
+
+/* ---------------------------------------------------------------- lensing */
+/* cmb_perturb plus the matter outputs (App. B.4 eq. PK, App. B.5): either
+ * pointer may be NULL, not both.
+ *   d_Pk: device [n_cosmo][n_k], P(k, z = 0) in Mpc^3 as cmb_perturb_pk;
+ *   d_Dm: device [n_cosmo][n_k][n_tau], the matter density contrast
+ *         delta_m = sum rho_i delta_i / sum rho_i over CDM, baryons and
+ *         massive neutrinos at every output time (synchronous gauge; zero
+ *         before the mode's start time and after a failed integration).
+ * Errors as cmb_perturb; CMB_E_UNSUPPORTED for hierarchies the cooperative
+ * kernel does not hold. */
+int cmb_perturb_matter(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                       int32_t *d_nsteps, double *d_Pk, double *d_Dm, void *hip_stream);
+
+/* Lensing-potential spectrum by Limber's approximation (App. B.5):
+ *   C_l^psipsi = 8 pi^2/(l+1/2)^3 sum_j W_j P_R(k_j) delta_m(k_j, tau_j)^2 / k_j^4,
+ *   k_j = (l+1/2)/chi_j,
+ * W_j the tables' Limber weights (cmb_table_view.lens_w: time quadrature,
+ * 1/chi, (3/2 a^2 rho_m)^2 and ((chi_* - chi)/chi_*)^2), delta_m(k, tau_j) the
+ * natural cubic spline in k of d_Dm at output time j, zero outside
+ * [k_0, k_{n_k-1}].
+ *   d_Dm:   device [n_cosmo][n_k][n_tau] from cmb_perturb_matter;
+ *   d_Clpp: device [n_cosmo][ell_max+1], zero for l < 2.
+ * All cosmologies of one call share the perturbation k grid.  Asynchronous
+ * on hip_stream (synchronises it once before staging the spline factors).
+ * Errors: CMB_E_INVALID, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_lensing_potential(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Dm,
+                          double *d_Clpp, void *hip_stream);
 
 /* ------------------------------------------- three-region Bessel variant */
 /* The paper's three-region spherical Bessel scheme (App. B.4, below the

@@ -98,6 +98,11 @@ def lib():
             L.oracle_perturb_many.restype = ctypes.c_int
             L.oracle_perturb_many.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_int, dp, dp,
                                               dp, dp, ctypes.c_int, dp, dp, ip, ip, ip]
+            L.oracle_perturb_many_dm.restype = ctypes.c_int
+            L.oracle_perturb_many_dm.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_int, dp, dp,
+                                                 dp, dp, ctypes.c_int, dp, dp, dp, ip, ip, ip]
+            L.oracle_delta_m.restype = ctypes.c_double
+            L.oracle_delta_m.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, dp]
             L.oracle_state_size.restype = ctypes.c_int
             L.oracle_state_size.argtypes = [ctypes.POINTER(_OPrec)]
             L.oracle_matter_pk.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, dp,
@@ -187,6 +192,36 @@ def perturb(t, idx=None, prec_over: dict | None = None):
     lib().oracle_perturb_many(ctypes.byref(b.tab), ctypes.byref(p), len(k), _dp(k), _dp(lna0), _dp(rtol), _dp(atol),
                               n_out, _dp(lna_out), _dp(S), _ip(st), _ip(ns), _ip(na))
     return S, st, ns, na
+
+
+def perturb_dm(t, idx=None):
+    """As perturb, plus the matter density contrast delta_m[n][n_tau] at the
+    output times (App. B.4 eq. PK's species sum; zero before a mode's start).
+    Returns (S, Dm, status, nsteps)."""
+    idx = np.arange(len(t.k)) if idx is None else np.asarray(idx, dtype=np.int64)
+    k = np.ascontiguousarray(t.k[idx], dtype=np.float64)
+    lna0 = np.ascontiguousarray(t.lna_i[idx], dtype=np.float64)
+    rtol, atol = tolerances(t.prec, k)
+    n_out = len(t.lna_src)
+    S = np.zeros((len(k), 3, n_out))
+    Dm = np.zeros((len(k), n_out))
+    st = np.zeros(len(k), dtype=np.int32)
+    ns = np.zeros(len(k), dtype=np.int32)
+    na = np.zeros(len(k), dtype=np.int32)
+    b = _Bound(t)
+    p = make_prec(t.prec, len(t.bg.q))
+    lna_out = np.ascontiguousarray(t.lna_src, dtype=np.float64)
+    lib().oracle_perturb_many_dm(ctypes.byref(b.tab), ctypes.byref(p), len(k), _dp(k), _dp(lna0), _dp(rtol),
+                                 _dp(atol), n_out, _dp(lna_out), _dp(S), _dp(Dm), _ip(st), _ip(ns), _ip(na))
+    return S, Dm, st, ns
+
+
+def delta_m_of_state(t, lna: float, y) -> float:
+    """delta_m of one state vector at ln a (tests)."""
+    b = _Bound(t)
+    p = make_prec(t.prec, len(t.bg.q))
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().oracle_delta_m(ctypes.byref(b.tab), ctypes.byref(p), float(lna), _dp(y))
 
 
 def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None, y0=None, want_y: bool = False,

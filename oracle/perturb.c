@@ -105,6 +105,24 @@ double oracle_matter_pk(const otab_t *t, const oprec_t *p, double k, const doubl
     return 2.0 * pi * pi / (k * k * k) * prim * dm * dm;
 }
 
+/* Matter density contrast at ln a (App. B.4 eq. PK, App. B.5): sum rho_i
+   delta_i / sum rho_i over CDM, baryons and massive neutrinos, with rho_c,b
+   proportional to a^-3 and the massive species' rho to a^-4 sum W eps. */
+double oracle_delta_m(const otab_t *t, const oprec_t *p, double lna, const double *y) {
+    olayout_t L;
+    make_layout(p, &L);
+    double a = exp(lna);
+    double num = t->rt_c0 / (a * a * a) * y[L.dc] + t->rt_b0 / (a * a * a) * y[L.db];
+    double den = (t->rt_c0 + t->rt_b0) / (a * a * a);
+    for (int i = 0; i < p->nq; ++i) {
+        double x = a * t->m_over_T;
+        double rho_i = t->pref_ncdm * t->W[i] * sqrt(t->q[i] * t->q[i] + x * x) / (a * a * a * a);
+        num += rho_i * y[L.m0 + i * (p->lq + 1)];
+        den += rho_i;
+    }
+    return num / den;
+}
+
 int oracle_state_size(const oprec_t *p) {
     olayout_t L;
     make_layout(p, &L);
@@ -589,6 +607,33 @@ int oracle_perturb_many(const otab_t *tb, const oprec_t *p0, int nk, const doubl
         p.atol = atol[i];
         status[i] = oracle_perturb(tb, &p, k[i], lna0[i], n_out, lna_out, S + (size_t)i * 3 * n_out, NULL, NULL,
                                    &nsteps[i], &naccept[i], NULL, 0, NULL);
+    }
+    return 0;
+}
+
+/* As oracle_perturb_many, plus the matter density contrast Dm[nk][n_out] at
+   every output time (zero where S is zero: before the start, after an abort). */
+int oracle_perturb_many_dm(const otab_t *tb, const oprec_t *p0, int nk, const double *k, const double *lna0,
+                           const double *rtol, const double *atol, int n_out, const double *lna_out, double *S,
+                           double *Dm, int *status, int *nsteps, int *naccept) {
+    int N = oracle_state_size(p0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = nk - 1; i >= 0; --i) {
+        oprec_t p = *p0;
+        p.rtol = rtol[i];
+        p.atol = atol[i];
+        double *Y = (double *)calloc((size_t)n_out * N, sizeof(double));
+        status[i] = oracle_perturb(tb, &p, k[i], lna0[i], n_out, lna_out, S + (size_t)i * 3 * n_out, Y, NULL,
+                                   &nsteps[i], &naccept[i], NULL, 0, NULL);
+        for (int j = 0; j < n_out; ++j) {
+            /* a state row that the integration never produced is still all zero */
+            const double *y = Y + (size_t)j * N;
+            int produced = 0;
+            for (int r = 0; r < N; ++r)
+                if (y[r] != 0.0) produced = 1;
+            Dm[(size_t)i * n_out + j] = produced ? oracle_delta_m(tb, &p, lna_out[j], y) : 0.0;
+        }
+        free(Y);
     }
     return 0;
 }

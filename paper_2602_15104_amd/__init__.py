@@ -43,7 +43,7 @@ MODE_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "NONFINITE", 3: "STEP_UNDERFLOW"}
 EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_build", "cmb_tables_destroy",
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
-           "cmb_bessel3_table", "cmb_los_bessel3",
+           "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -83,7 +83,8 @@ class CTableView(ctypes.Structure):
                                     "kappa", "ln_cs2", "ln_tau", "M_ln_dk", "M_kappa", "M_ln_cs2", "M_ln_tau", "q",
                                     "W")] +
                 [(n, ctypes.c_double) for n in ("rt_g0", "rt_ur0", "rt_c0", "rt_b0", "rt_L", "pref_ncdm", "m_over_T",
-                                                "H0")])
+                                                "H0", "tau_star", "chi_star")] +
+                [("lens_w", _dp)])
 
 
 _vp = ctypes.c_void_p
@@ -119,6 +120,8 @@ def _declare(lib):
                                         _vp, _vp, _vp, _vp]
     lib.cmb_los.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_bessel3_table.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp]
+    lib.cmb_perturb_matter.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.cmb_lensing_potential.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -212,10 +215,10 @@ class Tables:
 
         out = {f: getattr(v, f) for f in ("n_k", "n_tau", "n_tab", "n_q", "L0", "dlna", "tau0", "z_reio", "lna_tc",
                                           "N_massless", "Neff", "R_nu", "rt_g0", "rt_ur0", "rt_c0", "rt_b0", "rt_L",
-                                          "pref_ncdm", "m_over_T", "H0")}
+                                          "pref_ncdm", "m_over_T", "H0", "tau_star", "chi_star")}
         for f in ("k", "lna_start"):
             out[f] = arr(getattr(v, f), v.n_k)
-        for f in ("lna_src", "tau_src", "chi_src", "w_src"):
+        for f in ("lna_src", "tau_src", "chi_src", "w_src", "lens_w"):
             out[f] = arr(getattr(v, f), v.n_tau)
         for f in ("xe", "tm", "ln_dk", "kappa", "ln_cs2", "ln_tau", "M_ln_dk", "M_kappa", "M_ln_cs2", "M_ln_tau"):
             out[f] = arr(getattr(v, f), n1)
@@ -292,6 +295,18 @@ class Context:
     def los(self, tabs, ell_max, S, Delta, stream=None):
         hs = _handles(tabs)
         _check(_lib.cmb_los(self._h, hs, len(tabs), int(ell_max), _ptr(S), _ptr(Delta), _stream(stream)), "cmb_los")
+
+    def perturb_matter(self, tabs, S, status, Pk=None, Dm=None, nsteps=None, stream=None):
+        """cmb_perturb plus P(k) today and/or delta_m at the output times."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_matter(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _ptr(Pk),
+                                       _ptr(Dm), _stream(stream)), "cmb_perturb_matter")
+
+    def lensing_potential(self, tabs, ell_max, Dm, Clpp, stream=None):
+        """Limber C_l^psipsi from delta_m (cmb_lensing_potential)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_lensing_potential(self._h, hs, len(tabs), int(ell_max), _ptr(Dm), _ptr(Clpp),
+                                          _stream(stream)), "cmb_lensing_potential")
 
     def los_bessel3(self, tabs, ell_max, S, Delta, stream=None):
         """cmb_los with the three-region Bessel scheme (cmb_los_bessel3)."""

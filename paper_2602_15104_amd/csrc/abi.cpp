@@ -20,7 +20,7 @@ struct cmb_tables {
 namespace cmbhip {
 
 size_t table_doubles(const Tables &t) {
-    return t.poly.size() + 2 * t.k.size() + 3 * t.lna_src.size() + 2 * t.q.size();
+    return t.poly.size() + 2 * t.k.size() + 4 * t.lna_src.size() + 2 * t.q.size();
 }
 
 void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x) {
@@ -40,6 +40,8 @@ void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x) {
     x.w_src = put(t.w_src);
     x.q = put(t.q);
     x.W = put(t.W);
+    x.lens_w = put(t.lens_w);
+    x.chi_star = t.chi_star;
     x.pref_ncdm = t.pref_ncdm;
     x.m_over_T = t.m_over_T;
     x.L0 = t.L0;
@@ -248,6 +250,9 @@ int cmb_tables_export(const cmb_tables *tt, cmb_table_view *v) {
     v->tau_src = t.tau_src.data();
     v->chi_src = t.chi_src.data();
     v->w_src = t.w_src.data();
+    v->tau_star = t.tau_star;
+    v->chi_star = t.chi_star;
+    v->lens_w = t.lens_w.data();
     v->xe = t.xe.data();
     v->tm = t.tm.data();
     v->ln_dk = t.col[0].data();
@@ -457,7 +462,7 @@ size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo) {
 namespace {
 
 int perturb_impl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
-                 int32_t *d_nsteps, double *d_Pk, void *stream) {
+                 int32_t *d_nsteps, double *d_Pk, void *stream, double *d_Dm = nullptr) {
     Batch b;
     int rc = check_batch(tabs, n_cosmo, b);
     if (rc) return rc;
@@ -468,12 +473,12 @@ int perturb_impl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double 
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
     const char *variant = std::getenv("CMBHIP_K1");
-    bool lane_variant = variant && std::string(variant) == "lane" && !d_Pk;
+    bool lane_variant = variant && std::string(variant) == "lane" && !d_Pk && !d_Dm;
     if (b.prec.nq > 0 && (lane_variant || !cmbhip::perturb2_supported(b.prec))) {
         set_error("massive neutrinos are built into the cooperative perturbation kernel only");
         return CMB_E_UNSUPPORTED;
     }
-    if (d_Pk && !cmbhip::perturb2_supported(b.prec)) {
+    if ((d_Pk || d_Dm) && !cmbhip::perturb2_supported(b.prec)) {
         set_error("the matter power spectrum is built into the cooperative perturbation kernel only");
         return CMB_E_UNSUPPORTED;
     }
@@ -484,7 +489,8 @@ int perturb_impl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double 
             if (rc) return rc;
             ns2 = (int32_t *)c->st_buf;
         }
-        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, d_Pk, stream);
+        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, d_Pk, d_Dm,
+                                     stream);
         if (rc == CMB_OK) set_error("");
         return rc;
     }
@@ -523,6 +529,15 @@ int cmb_perturb_pk(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, doubl
         return CMB_E_INVALID;
     }
     return perturb_impl(c, tabs, n_cosmo, d_S, d_status, d_nsteps, d_Pk, stream);
+}
+
+int cmb_perturb_matter(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                       int32_t *d_nsteps, double *d_Pk, double *d_Dm, void *stream) {
+    if (!c || !d_S || !d_status || (!d_Pk && !d_Dm)) {
+        set_error("cmb_perturb_matter: NULL argument");
+        return CMB_E_INVALID;
+    }
+    return perturb_impl(c, tabs, n_cosmo, d_S, d_status, d_nsteps, d_Pk, stream, d_Dm);
 }
 
 int cmb_los(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S, double *d_Delta,
@@ -651,6 +666,23 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
 
 }  // extern "C"
 
+// Thomas factors of the natural-spline system on the grid kg (interior rows
+// 1..n-2): dinv[i] = 1/pivot_i, lo[i] = sub_i / pivot_{i-1}
+static void spline_factors(const std::vector<double> &kg, std::vector<double> &lo, std::vector<double> &dinv) {
+    const int nk = (int)kg.size();
+    lo.assign(nk, 0.0);
+    dinv.assign(nk, 0.0);
+    for (int i = 1; i < nk - 1; ++i) {
+        const double hm = kg[i] - kg[i - 1], hp = kg[i + 1] - kg[i];
+        double piv = 2.0 * (hm + hp);
+        if (i > 1) {
+            lo[i] = hm * dinv[i - 1];
+            piv -= lo[i] * hm;  // sub_i = h_{i-1}, sup_{i-1} = h_{i-1}
+        }
+        dinv[i] = 1.0 / piv;
+    }
+}
+
 // the context's three-region Bessel table covering l <= ell_max (rebuilt
 // whole, on the caller's stream, when a larger l_max is asked for)
 static int ensure_bessel3(cmb_ctx *c, int ell_max, hipStream_t s) {
@@ -733,6 +765,70 @@ int cmb_los_bessel3(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int 
     return rc;
 }
 
+int cmb_lensing_potential(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Dm,
+                          double *d_Clpp, void *stream) {
+    if (!c || !d_Dm || !d_Clpp) {
+        set_error("cmb_lensing_potential: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 20000) {
+        set_error("ell_max must be in [2, 20000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    const std::vector<double> &kg = tabs[0]->t.k;
+    const int nk = b.n_k;
+    for (int i = 1; i < n_cosmo; ++i)
+        if (tabs[i]->t.k != kg) {
+            set_error("cmb_lensing_potential: the cosmologies of one call must share the perturbation k grid");
+            return CMB_E_INVALID;
+        }
+    if (nk < 2) {
+        set_error("cmb_lensing_potential: need n_k >= 2");
+        return CMB_E_INVALID;
+    }
+    std::vector<double> lo, dinv;
+    spline_factors(kg, lo, dinv);
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    const size_t o_kg = 0, o_lo = align256(sizeof(double) * nk), o_di = o_lo + align256(sizeof(double) * nk);
+    const size_t small = o_di + align256(sizeof(double) * nk);
+    rc = grow(c, &c->kt_buf, &c->kt_cap, small, s);
+    if (rc) return rc;
+    rc = grow(c, &c->ws_buf, &c->ws_cap, sizeof(double) * (size_t)n_cosmo * nk * b.n_tau, s);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);  // the staging may still be read by a previous call
+    if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    if (small > c->kt_stage_cap) {
+        if (c->kt_stage) hipHostFree(c->kt_stage);
+        c->kt_stage = nullptr;
+        c->kt_stage_cap = 0;
+        e = hipHostMalloc(&c->kt_stage, small, hipHostMallocDefault);
+        if (e != hipSuccess) return herr(e, "hipHostMalloc");
+        c->kt_stage_cap = small;
+    }
+    char *h = (char *)c->kt_stage;
+    char *d = (char *)c->kt_buf;
+    std::memcpy(h + o_kg, kg.data(), sizeof(double) * nk);
+    std::memcpy(h + o_lo, lo.data(), sizeof(double) * nk);
+    std::memcpy(h + o_di, dinv.data(), sizeof(double) * nk);
+    e = hipMemcpyAsync(d, h, small, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return herr(e, "hipMemcpyAsync (spline factors)");
+    double *M = (double *)c->ws_buf;
+    rc = cmbhip::launch_spline_m(d_Dm, M, (const double *)(d + o_kg), (const double *)(d + o_lo),
+                                 (const double *)(d + o_di), n_cosmo, nk, 1, b.n_tau, stream);
+    if (rc) return rc;
+    rc = cmbhip::launch_limber(c->d_tabs, n_cosmo, nk, b.n_tau, ell_max, d_Dm, M, d_Clpp, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
 int cmb_spectra_on_grid(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
                         const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *stream) {
     if (!c || !d_S || !kt || !d_St || !d_Delta || !d_Cl || n_kt < 2) {
@@ -763,16 +859,8 @@ int cmb_spectra_on_grid(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, 
             return CMB_E_INVALID;
         }
     // spline factors of the k grid (interior rows 1..nk-2) and the interval of every kt
-    std::vector<double> lo(nk, 0.0), dinv(nk, 0.0);
-    for (int i = 1; i < nk - 1; ++i) {
-        const double hm = kg[i] - kg[i - 1], hp = kg[i + 1] - kg[i];
-        double piv = 2.0 * (hm + hp);
-        if (i > 1) {
-            lo[i] = hm * dinv[i - 1];
-            piv -= lo[i] * hm;  // sub_i = h_{i-1}, sup_{i-1} = h_{i-1}
-        }
-        dinv[i] = 1.0 / piv;
-    }
+    std::vector<double> lo, dinv;
+    spline_factors(kg, lo, dinv);
     std::vector<int> seg(n_kt);
     for (int q = 0, i = 0; q < n_kt; ++q) {
         while (i < nk - 2 && kt[q] > kg[i + 1]) ++i;

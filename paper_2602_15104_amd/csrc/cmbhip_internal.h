@@ -25,6 +25,8 @@ struct Tables {
     std::vector<double> col[4], M[4];  // ln dk, kappa, ln cs2, ln tau: knot values, second derivatives
     std::vector<double> poly;          // [n_tab][4 columns][4 coefficients]
     std::vector<double> lna_src, tau_src, chi_src, w_src;
+    double lna_star = 0, tau_star = 0, chi_star = 0;  // visibility peak
+    std::vector<double> lens_w;                        // [n_tau] Limber weights
     unsigned long long uid = 0;
     double eval(int column, double lna) const;
 };
@@ -42,6 +44,7 @@ struct DevTab {
     const double *chi_src;    // [n_tau]
     const double *w_src;      // [n_tau]
     const double *q, *W;      // [n_q] massive-neutrino momentum rule (n_q = 0: none)
+    const double *lens_w;     // [n_tau] Limber weights of the lensing potential
     double *S;                // work-list launches only: this cosmology's [n_k][3][n_tau] sources
     int *status, *nsteps;     //   and [n_k] status / step counts
     double L0, inv_dl;
@@ -50,6 +53,7 @@ struct DevTab {
     double rt_g0, rt_ur0, rt_c0, rt_b0, rt_L;
     double pref_ncdm, m_over_T;  // massive nu: rho = pref a^-4 sum W eps, eps = sqrt(q^2 + (a m/T)^2)
     double A_s, n_s, k_pivot;
+    double chi_star;
     double rtol_small, rtol_large, atol_small, atol_large, k_split;
 };
 
@@ -73,7 +77,7 @@ int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const 
                    double *d_S, int *d_status, int *d_nsteps, void *stream);
 size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, double *d_Pk, void *stream);
+                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream);
 bool perturb2_supported(const DevPrec &p);
 // work list of (cosmology, mode) pairs; outputs through each DevTab's S/status/nsteps
 struct WorkItem {
@@ -92,6 +96,14 @@ int launch_spline_sources(const double *d_S, double *d_M, const double *d_kg, co
                           const double *d_dinv, const int *d_seg, const double *d_kt, double *d_St, int n_cosmo,
                           int n_k, int n_tau, int n_kt, void *stream);
 int ell_cut(double x);  // host copy of the Bessel cut rule (tests)
+// spline second derivatives in k of F[n_cosmo][n_k][nty][n_tau] (one system
+// per (cosmology, type, time)) into M of the same layout
+int launch_spline_m(const double *d_F, double *d_M, const double *d_kg, const double *d_lo, const double *d_dinv,
+                    int n_cosmo, int n_k, int nty, int n_tau, void *stream);
+// lensing potential by Limber's approximation (App. B.5): Clpp[c][0..ell_max]
+// from the matter density contrast Dm[c][n_k][n_tau] and its spline M in k
+int launch_limber(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, const double *d_Dm,
+                  const double *d_M, double *d_Clpp, void *stream);
 // three-region Bessel scheme: samples per multipole, table build for
 // l_lo..l_hi (x_start[l-1], x_5[l-1] (NaN if not found), tab[l-1][B3_PTS]) and
 // the projection with it

@@ -12,7 +12,9 @@
 //
 // One thread per (cosmology, type, time): consecutive lanes take consecutive
 // times, so every load and store of S, M and the result is coalesced (times
-// are the fastest index of all three arrays).
+// are the fastest index of all three arrays).  The second-derivative kernel
+// takes any number of types per mode (3 for the sources, 1 for the matter
+// density contrast of the lensing potential).
 #include <hip/hip_runtime.h>
 
 #include "cmbhip_internal.h"
@@ -28,14 +30,14 @@ constexpr int BLOCK = 256;
 __global__ void __launch_bounds__(BLOCK) spline_m_kernel(const double *__restrict__ S, double *__restrict__ M,
                                                         const double *__restrict__ kg, const double *__restrict__ lo,
                                                         const double *__restrict__ dinv, int n_cosmo, int n_k,
-                                                        int n_tau) {
+                                                        int nty, int n_tau) {
     const long sys = (long)blockIdx.x * BLOCK + threadIdx.x;
-    const long n_sys = (long)n_cosmo * 3 * n_tau;
+    const long n_sys = (long)n_cosmo * nty * n_tau;
     if (sys >= n_sys) return;
     const int j = (int)(sys % n_tau);
-    const int ty = (int)((sys / n_tau) % 3);
-    const int c = (int)(sys / (3L * n_tau));
-    const size_t st = (size_t)3 * n_tau;  // stride between consecutive k
+    const int ty = (int)((sys / n_tau) % nty);
+    const int c = (int)(sys / ((long)nty * n_tau));
+    const size_t st = (size_t)nty * n_tau;  // stride between consecutive k
     const double *f = S + (size_t)c * n_k * st + (size_t)ty * n_tau + j;
     double *m = M + (size_t)c * n_k * st + (size_t)ty * n_tau + j;
     m[0] = 0.0;
@@ -100,9 +102,23 @@ int launch_spline_sources(const double *d_S, double *d_M, const double *d_kg, co
     const long n_sys = (long)n_cosmo * 3 * n_tau;
     dim3 grid((unsigned)((n_sys + BLOCK - 1) / BLOCK)), block(BLOCK);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(spline_m_kernel, grid, block, 0, s, d_S, d_M, d_kg, d_lo, d_dinv, n_cosmo, n_k, n_tau);
+    hipLaunchKernelGGL(spline_m_kernel, grid, block, 0, s, d_S, d_M, d_kg, d_lo, d_dinv, n_cosmo, n_k, 3, n_tau);
     hipLaunchKernelGGL(spline_eval_kernel, grid, block, 0, s, d_S, d_M, d_kg, d_seg, d_kt, d_St, n_cosmo, n_k, n_tau,
                        n_kt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("spline launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+int launch_spline_m(const double *d_F, double *d_M, const double *d_kg, const double *d_lo, const double *d_dinv,
+                    int n_cosmo, int n_k, int nty, int n_tau, void *stream) {
+    const long n_sys = (long)n_cosmo * nty * n_tau;
+    dim3 grid((unsigned)((n_sys + BLOCK - 1) / BLOCK)), block(BLOCK);
+    hipLaunchKernelGGL(spline_m_kernel, grid, block, 0, (hipStream_t)stream, d_F, d_M, d_kg, d_lo, d_dinv, n_cosmo,
+                       n_k, nty, n_tau);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("spline launch: ") + hipGetErrorString(e));

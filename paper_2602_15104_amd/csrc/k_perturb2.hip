@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                                                       int n_tau_all, DevPrec p, int G, double *__restrict__ Sout,
                                                       int *__restrict__ status, int *__restrict__ nsteps,
                                                       const int2 *__restrict__ items, int n_items,
-                                                      double *__restrict__ Pk) {
+                                                      double *__restrict__ Pk, double *__restrict__ Dm) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int gl = lane % G;
@@ -528,6 +528,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double rtol = small ? tb.rtol_small : tb.rtol_large;
     const double atol = small ? tb.atol_small : tb.atol_large;
     double *So = items ? tb.S + (size_t)ik * 3 * n_tau : Sout + ((size_t)c * n_k + ik) * 3 * n_tau;
+    // matter density contrast at the output times (batch launches only)
+    double *Dmo = (Dm && !items) ? Dm + ((size_t)c * n_k + ik) * n_tau : nullptr;
     const double *lo = tb.lna_src;
     const int ch = gl;  // chain handled by this lane in the sweeps
     const bool sweeper = ch < L.nch;
@@ -620,6 +622,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             So[jo] = 0.0;
             So[n_tau + jo] = 0.0;
             So[2 * n_tau + jo] = 0.0;
+            if (Dmo) Dmo[jo] = 0.0;
             ++jo;
         }
     } else {
@@ -1027,6 +1030,20 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                              p.dop * Hc * (gv * (tbp / k2 + alphap) + gp * (y(1) / k2 + alpha));
                     So[n_tau + jo] = p.isw * ek * k * (Hc * alphap + 2.0 * Hc * alpha - eta);
                     So[2 * n_tau + jo] = gv * Pi * 0.125;
+                    if (Dmo) {
+                        // sum rho_i delta_i / sum rho_i over CDM, baryons and massive
+                        // nu, scaled by a^3 (massive nu: a^-4 eps against a^-3)
+                        double num = tb.rt_c0 * y(L.rDC) + tb.rt_b0 * y(0), den = tb.rt_c0 + tb.rt_b0;
+                        if (MNU) {
+                            const double ia = rcp(so.a);
+                            for (int i = 0; i < L.nQ; ++i) {
+                                const double w1 = tb.pref_ncdm * tb.W[i] * eps_of(tb.q[i], so.am) * ia;
+                                num = fma(w1, y(L.bM + i * L.nPs), num);
+                                den += w1;
+                            }
+                        }
+                        Dmo[jo] = num / den;
+                    }
                 }
                 wsync();
                 ++jo;
@@ -1079,6 +1096,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             So[jo] = 0.0;
             So[n_tau + jo] = 0.0;
             So[2 * n_tau + jo] = 0.0;
+            if (Dmo) Dmo[jo] = 0.0;
         }
         if (items) {
             tb.status[ik] = st;
@@ -1113,7 +1131,7 @@ bool perturb2_supported(const DevPrec &p) {
 
 static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
                                int *d_status, int *d_nsteps, const int2 *d_items, int n_items, double *d_Pk,
-                               void *stream) {
+                               double *d_Dm, void *stream) {
     int R, G;
     group_shape(p, R, G);
     if (G > 64) {
@@ -1130,16 +1148,16 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
     const bool mnu = p.nq > 0;
     if (R == 2 && !mnu)
         hipLaunchKernelGGL((perturb2_kernel<2, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk);
+                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
     else if (R == 2)
         hipLaunchKernelGGL((perturb2_kernel<2, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk);
+                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
     else if (!mnu)
         hipLaunchKernelGGL((perturb2_kernel<5, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk);
+                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
     else
         hipLaunchKernelGGL((perturb2_kernel<5, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk);
+                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
@@ -1149,14 +1167,15 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
 }
 
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, double *d_Pk, void *stream) {
-    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, d_Pk, stream);
+                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream) {
+    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, d_Pk, d_Dm,
+                               stream);
 }
 
 int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_items, const DevPrec &p, void *stream) {
     static_assert(sizeof(WorkItem) == sizeof(int2), "work item layout");
     return launch_perturb2_any(d_tabs, 0, 0, 0, p, nullptr, nullptr, nullptr, reinterpret_cast<const int2 *>(d_items),
-                               n_items, nullptr, stream);
+                               n_items, nullptr, nullptr, stream);
 }
 
 }  // namespace cmbhip

@@ -627,6 +627,41 @@ int build_tables(const cmb_cosmo &cin, const cmb_prec &p, const double *k, int n
         double lo = T.lna_src[i > 0 ? i - 1 : i], hi = T.lna_src[i < n_tau - 1 ? i + 1 : i];
         T.w_src[i] = 0.5 * (hi - lo) / Hsrc[i];
     }
+
+    // lensing (App. B.5): chi_* from the visibility peak g = kappa' e^{-kappa}
+    // (conformal time), located on the table knots and refined by the vertex
+    // of the parabola through the three knots around the largest value
+    {
+        int j = 1;
+        double gmax = -1.0;
+        for (int i = 1; i < n; ++i) {
+            double g = std::exp(ldk[i] - kap[i]);
+            if (g > gmax) {
+                gmax = g;
+                j = i;
+            }
+        }
+        double gm = std::exp(ldk[j - 1] - kap[j - 1]), g0 = std::exp(ldk[j] - kap[j]),
+               gp = std::exp(ldk[j + 1] - kap[j + 1]);
+        double den = gm - 2.0 * g0 + gp;
+        double off = den != 0.0 ? 0.5 * (gm - gp) / den : 0.0;
+        T.lna_star = lna[j] + off * dl;
+        T.tau_star = std::exp(T.eval(3, T.lna_star));
+        T.chi_star = T.tau0 - T.tau_star;
+    }
+    // Limber weights per output time: w_j / chi_j (3/2 a^2 rho_m)^2 ((chi_* - chi_j)/chi_*)^2
+    // for 0 < chi_j < chi_*, rho_m over CDM, baryons and massive neutrinos
+    T.lens_w.assign(n_tau, 0.0);
+    for (int i = 0; i < n_tau; ++i) {
+        const double chi = T.chi_src[i];
+        if (!(chi > 0.0 && chi < T.chi_star)) continue;
+        const double a = std::exp(T.lna_src[i]);
+        double rn, pn;
+        m.ncdm(a, rn, pn);
+        const double src = 1.5 * a * a * (m.rt_m0 / (a * a * a) + rn);
+        const double f = (T.chi_star - chi) / T.chi_star;
+        T.lens_w[i] = T.w_src[i] / chi * src * src * f * f;
+    }
     return CMB_OK;
 }
 

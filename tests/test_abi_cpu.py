@@ -41,7 +41,7 @@ def test_exports_match_header(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.abi_version() == 1
+    assert lib.abi_version() == 2
     c, p = lib.defaults()
     # App. A.2 defaults
     assert c["omega_b"] == 0.02237 and c["omega_cdm"] == 0.120 and c["h"] == 0.6736
@@ -151,6 +151,13 @@ def test_table_parity_with_oracle(name):
         np.testing.assert_allclose(tp["W"], to.bg.W, rtol=1e-13)
         assert abs(tp["pref_ncdm"] / to.bg.pref_ncdm - 1) < 1e-14
         assert abs(tp["m_over_T"] / to.bg.m_over_T - 1) < 1e-14
+    # lensing: visibility peak and Limber weights (App. B.5)
+    from oracle import lensing as LN
+    _, tau_s, chi_s = LN.visibility_peak(to)
+    assert abs(tp["tau_star"] / tau_s - 1) < 1e-10 and abs(tp["chi_star"] / chi_s - 1) < 1e-12
+    lw = LN.limber_weights(to)
+    assert np.array_equal(tp["lens_w"] == 0, lw == 0)
+    np.testing.assert_allclose(tp["lens_w"], lw, rtol=1e-10, atol=0)
 
 
 def test_massive_neutrinos_need_nodes(lib):

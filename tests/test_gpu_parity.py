@@ -619,3 +619,109 @@ def test_los_bessel3_config1_error(ctx):
     tt, te, ee = cl_err(C.cpu().numpy()[0], g["Cl"][0])
     _say("config1 three-region vs exact: TT", tt, "TE", te, "EE", ee)
     assert tt < 5e-2 and te < 5e-2 and ee < 5e-2
+
+
+# ---------------------------------------------------------------- lensing potential (Limber)
+def _gpu_matter(ctx, tabs, want_pk=True):
+    import torch
+    B, n_k, n_tau = len(tabs), len(tabs[0].k), tabs[0].n_tau
+    S = torch.empty((B, n_k, 3, n_tau), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((B, n_k), dtype=torch.int32, device="cuda:0")
+    Pk = torch.empty((B, n_k), dtype=torch.float64, device="cuda:0") if want_pk else None
+    Dm = torch.empty((B, n_k, n_tau), dtype=torch.float64, device="cuda:0")
+    ctx.perturb_matter(tabs, S, st, Pk=Pk, Dm=Dm)
+    torch.cuda.synchronize()
+    return S, st, Pk, Dm
+
+
+@pytest.mark.parametrize("case", ["small", "small_massive"])
+def test_delta_m_and_limber_parity(ctx, case):
+    """delta_m at the output times (cmb_perturb_matter) against the oracle's
+    per mode (relative max-norm <= 1e-8), the sources equal cmb_perturb's
+    bitwise, and C_l^psipsi (cmb_lensing_potential, l <= 400) against the
+    oracle's Limber sum on its own delta_m (<= 1e-6)."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    from oracle import lensing as LN
+    wl = W.small_case(n_k=24, n_tau=200, ell_max=40, k_min=1e-4, k_max=0.2)
+    wl.prec["max_steps"] = 6000
+    if case == "small_massive":
+        wl = _massive(wl, 0.3, 4, 6)
+    _say("case limber", case)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    S, st, Pk, Dm = _gpu_matter(ctx, [tab])
+    ref = run_gpu(ctx, [tab], 2)
+    assert np.array_equal(S.cpu().numpy()[0], ref["S"][0])
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    So, Dmo, sto, nso = O.perturb_dm(t_or)
+    assert np.all(st.cpu().numpy() == 0) and np.all(sto == 0)
+    Dg = Dm.cpu().numpy()[0]
+    e = max(np.max(np.abs(Dg[i] - Dmo[i])) / np.max(np.abs(Dmo[i])) for i in range(len(wl.k)))
+    assert np.array_equal(Dg == 0, Dmo == 0)
+    C = torch.empty((1, 401), dtype=torch.float64, device="cuda:0")
+    ctx.lensing_potential([tab], 400, Dm, C)
+    torch.cuda.synchronize()
+    Cg = C.cpu().numpy()[0]
+    Co = LN.limber_cl(t_or, Dmo, 400)
+    ce = np.max(np.abs(Cg[2:] / Co[2:] - 1))
+    _say("delta_m err", e, "Cpp err", ce)
+    assert e <= 1e-8 and ce <= 1e-6 and np.all(Cg[:2] == 0)
+
+
+def test_limber_same_input(ctx):
+    """Limber stage alone on seeded random delta_m (two cosmologies on one k
+    grid): against the oracle's sum to 1e-12, and each cosmology's result
+    equals its solo call bit for bit."""
+    import torch
+    import paper_2602_15104_amd as L
+    import oracle as O
+    from oracle import lensing as LN
+    wl = W.small_case(n_k=30, n_tau=300, ell_max=40, k_min=1e-4, k_max=0.5)
+    cosmos = W.perturbed_cosmologies(2, seed=9)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    rng = np.random.Generator(np.random.PCG64(23))
+    D = rng.standard_normal((2, len(wl.k), wl.n_tau))
+    dD = torch.tensor(D, device="cuda:0")
+    C = torch.empty((2, 3001), dtype=torch.float64, device="cuda:0")
+    C1 = torch.empty((1, 3001), dtype=torch.float64, device="cuda:0")
+    ctx.lensing_potential(tabs, 3000, dD, C)
+    ctx.lensing_potential(tabs[1:], 3000, dD[1:], C1)
+    torch.cuda.synchronize()
+    Cg = C.cpu().numpy()
+    assert np.array_equal(Cg[1], C1.cpu().numpy()[0])
+    for i, cc in enumerate(cosmos):
+        t_or = O.build_tables(cc, wl.prec, wl.k, wl.n_tau)
+        Co = LN.limber_cl(t_or, D[i], 3000)
+        nz = Co != 0
+        assert np.array_equal(Cg[i] != 0, nz)
+        assert np.max(np.abs(Cg[i][nz] / Co[nz] - 1)) < 1e-12
+    other = L.Tables(cosmos[0], wl.prec, wl.k * 1.001, wl.n_tau)
+    with pytest.raises(L.CmbError):
+        ctx.lensing_potential([tabs[0], other], 3000, dD, C)
+
+
+def test_limber_config1(ctx):
+    """Config 1 at full size: C_l^psipsi for l <= 3000 from the GPU's delta_m
+    against the oracle's Limber sum on the oracle's own delta_m of all 400
+    modes (<= 1e-6)."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    from oracle import lensing as LN
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    S, st, Pk, Dm = _gpu_matter(ctx, [tab], want_pk=False)
+    C = torch.empty((1, 3001), dtype=torch.float64, device="cuda:0")
+    ctx.lensing_potential([tab], 3000, Dm, C)
+    torch.cuda.synchronize()
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    So, Dmo, sto, nso = O.perturb_dm(t_or)
+    Co = LN.limber_cl(t_or, Dmo, 3000)
+    Cg = C.cpu().numpy()[0]
+    ce = np.max(np.abs(Cg[2:] / Co[2:] - 1))
+    l = np.arange(3001)
+    _say("config1 Cpp err", ce, "peak [l(l+1)]^2 C/2pi", np.max((l * (l + 1.0)) ** 2 * Cg / (2 * math.pi)))
+    assert ce <= 1e-6

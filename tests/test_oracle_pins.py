@@ -667,3 +667,85 @@ def test_los3_scheme_error_small(b3tab):
     C = O.cl(t.k, DT, DE, 80, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
     e = np.max(np.abs(C[0, 2:] / r["Cl"][0, 2:] - 1))
     assert 0 < e < 1e-2
+
+
+# ---------------------------------------------------------------- P16 lensing potential (Limber)
+def test_visibility_peak(tab12):
+    """chi_*: the visibility kappa' e^-kappa is stationary there (centred
+    difference of the oracle's splines), and tau_* lies within 1% of the
+    paper's fiducial tau_rec (App. A.2)."""
+    from oracle import lensing as LN
+    t = tab12
+    lna_s, tau_s, chi_s = LN.visibility_peak(t)
+
+    def g(l):
+        dk, kap, cs2, tau, dkp = B.eval_thermo(t, l)
+        return dk * math.exp(-kap)
+
+    h = 1e-3
+    slope = (g(lna_s + h) - g(lna_s - h)) / (2 * h)
+    curv = (g(lna_s + h) - 2 * g(lna_s) + g(lna_s - h)) / h ** 2
+    assert abs(slope) < 2e-3 * abs(curv) * t.dl
+    assert abs(tau_s / GOLD["fiducials"]["tau_rec_fid_Mpc"] - 1) < 0.01
+    assert abs(chi_s - (t.tau0 - tau_s)) < 1e-9
+
+
+def test_delta_m_growth_late_times():
+    """Subhorizon delta_m at late times grows as the matter+Lambda growth
+    factor D(a) proportional to H(a) int_0^a da'/(a' H(a'))^3 (radiation and
+    neutrino free streaming below 0.5% there), and delta_m today equals the
+    one inside P(k) (eq. PK)."""
+    from scipy.integrate import quad
+    wl = W.small_case(n_k=6, n_tau=200, ell_max=20, k_min=0.02, k_max=0.08)
+    wl.prec["max_steps"] = 6000
+    t = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    S, Dm, st, ns = O.perturb_dm(t)
+    assert np.all(st == 0)
+    bg = t.bg
+    Om, OL = bg.rt_m0 / bg.H0 ** 2, bg.rt_L / bg.H0 ** 2
+
+    def D(a):
+        E = lambda x: math.sqrt(Om / x ** 3 + OL)  # noqa: E731
+        return E(a) * quad(lambda x: 1.0 / (x * E(x)) ** 3, 0, a, limit=200)[0]
+
+    j1 = int(np.argmin(np.abs(t.lna_src - math.log(0.25))))
+    for i in range(len(t.k)):
+        r = Dm[i, -1] / Dm[i, j1]
+        ex = D(1.0) / D(math.exp(t.lna_src[j1]))
+        assert abs(r / ex - 1) < 2e-3, (t.k[i], r, ex)  # measured 4.8e-4
+    pk = O.matter_pk(t, np.array([2]))
+    kk = t.k[2]
+    prim = t.cosmo["A_s"] * (kk / t.prec["k_pivot"]) ** (t.cosmo["n_s"] - 1)
+    assert abs(2 * math.pi ** 2 / kk ** 3 * prim * Dm[2, -1] ** 2 / pk[0] - 1) < 1e-12
+
+
+def test_limber_sum_vs_quadrature(tab12):
+    """With delta_m = c0 + c1 k (reproduced exactly by the natural spline) and
+    n_s = 1, the discrete Limber sum equals the continuous integral over ln a
+    (scipy quad of the closed-form integrand on the oracle's background) to
+    the output-time quadrature's accuracy."""
+    from scipy.integrate import quad
+    from oracle import lensing as LN
+    t = O.build_tables(dict(tab12.cosmo, n_s=1.0), tab12.prec, np.geomspace(1e-4, 2.0, 30), 400)
+    c0, c1 = 0.3, 40.0
+    Dm = (c0 + c1 * t.k)[:, None] * np.ones((1, len(t.lna_src)))
+    C = LN.limber_cl(t, Dm, 60)
+    lna_s, tau_s, chi_s = LN.visibility_peak(t)
+    bg = t.bg
+    A_s = t.cosmo["A_s"]
+    for l in (2, 10, 60):
+        nu = l + 0.5
+
+        def f(lna):
+            a = math.exp(lna)
+            tau = math.exp(B.spline_eval(t.cols["ln_tau"], t.M["ln_tau"], t.L0, t.dl, lna))
+            chi = t.tau0 - tau
+            kk = nu / chi
+            if not (t.k[0] <= kk <= t.k[-1]):
+                return 0.0
+            src = 1.5 * a * a * (bg.rt_m0 / a ** 3 + bg.rho_ncdm(a)[0])
+            return (1.0 / bg.Hc(a)) / chi * src ** 2 * ((chi_s - chi) / chi_s) ** 2 * A_s * (c0 + c1 * kk) ** 2 / kk ** 4
+
+        lo = max(lna_s, t.lna_src[0])
+        ref = 8 * math.pi ** 2 / nu ** 3 * quad(f, lo, -1e-9, limit=400, points=[math.log(1 / 401.0)])[0]
+        assert abs(C[l] / ref - 1) < 2e-3, (l, C[l], ref)
