@@ -238,6 +238,26 @@ int cmb_perturb_matter(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo,
 int cmb_lensing_potential(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Dm,
                           double *d_Clpp, void *hip_stream);
 
+/* Lensed CMB spectra (App. B.5) from full-sky correlation functions, after
+ * the correlation-function method the paper implements (Challinor & Lewis
+ * 2005): the deflection correlations C_gl and C_gl,2, sigma^2 = C_gl(0) -
+ * C_gl(beta), the small-deflection X functions, and the lensed correlation
+ * functions xi_T, xi_+, xi_-, xi_x to second order in C_gl,2, transformed back
+ * by an n_mu-point Gauss-Legendre rule over the whole range -1 <= cos(beta)
+ * <= 1 (the restricted-range "fast" variant is not offered).  Only the lensing
+ * change of each correlation function is transformed and added to the
+ * unlensed spectra.
+ *   d_Cl:   device [n_cosmo][3][L+1] unlensed TT, TE, EE (cmb_cl's layout, l < 2 ignored);
+ *   d_Clpp: device [n_cosmo][L+1] lensing-potential spectrum (cmb_lensing_potential);
+ *   d_Cll:  device [n_cosmo][4][ell_max+1] lensed TT, TE, EE, BB (zero for l < 2).
+ * Multipoles above L are taken as zero, so results near L miss the power
+ * that lensing moves down from above it: choose ell_max well below L (several
+ * hundred).  2 <= ell_max <= L <= 20000; n_mu of about L + ell_max/2 or more.
+ * The first call for a new (L, n_mu) builds the node tables on the host and
+ * synchronises hip_stream.  Errors: CMB_E_INVALID, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_lensed_cl(cmb_ctx *ctx, int n_cosmo, int L, const double *d_Cl, const double *d_Clpp, int ell_max, int n_mu,
+                  double *d_Cll, void *hip_stream);
+
 /* ------------------------------------------- three-region Bessel variant */
 /* The paper's three-region spherical Bessel scheme (App. B.4, below the
  * transfer integrals): for each l >= 1, j_l = 0 up to x_start(l) (the first x

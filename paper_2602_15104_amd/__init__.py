@@ -44,6 +44,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
+           "cmb_lensed_cl",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -122,6 +123,7 @@ def _declare(lib):
     lib.cmb_bessel3_table.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp]
     lib.cmb_perturb_matter.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.cmb_lensing_potential.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.cmb_lensed_cl.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -307,6 +309,15 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_lensing_potential(self._h, hs, len(tabs), int(ell_max), _ptr(Dm), _ptr(Clpp),
                                           _stream(stream)), "cmb_lensing_potential")
+
+    def lensed_cl(self, Cl, Clpp, ell_max, Cll, n_mu=None, stream=None):
+        """Lensed TT, TE, EE, BB [n][4][ell_max+1] from unlensed Cl[n][3][L+1]
+        and Clpp[n][L+1] (cmb_lensed_cl); n_mu defaults to L + ell_max/2 + 200."""
+        n, L = int(Cl.shape[0]), int(Cl.shape[2]) - 1
+        if n_mu is None:
+            n_mu = L + ell_max // 2 + 200
+        _check(_lib.cmb_lensed_cl(self._h, n, L, _ptr(Cl), _ptr(Clpp), int(ell_max), int(n_mu), _ptr(Cll),
+                                  _stream(stream)), "cmb_lensed_cl")
 
     def los_bessel3(self, tabs, ell_max, S, Delta, stream=None):
         """cmb_los with the three-region Bessel scheme (cmb_los_bessel3)."""

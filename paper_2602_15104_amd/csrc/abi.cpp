@@ -2,6 +2,7 @@
 // the ordering of the three stages on the caller's HIP stream.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdlib>
 #include <cmath>
@@ -114,6 +115,10 @@ struct cmb_ctx {
     void *b3_buf = nullptr;
     size_t b3_cap = 0;
     int b3_lmax = 0;
+    // lensed spectra: nodes | weights | recurrence coefficients | X factors | start values, for (lens_L, lens_nmu)
+    void *lens_buf = nullptr;
+    size_t lens_cap = 0;
+    int lens_L = 0, lens_nmu = 0;
     // cache key of the resident tables, their device descriptors and a host copy
     std::vector<unsigned long long> resident;
     cmbhip::DevTab *d_tabs = nullptr;
@@ -307,7 +312,8 @@ void cmb_ctx_destroy(cmb_ctx *c) {
     hipGetDevice(&prev);
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf, c->kt_buf, c->b3_buf}) hipFree(p);
+    for (void *p : {c->tab_buf, c->ws_buf, c->s_buf, c->d_buf, c->st_buf, c->kt_buf, c->b3_buf, c->lens_buf})
+        hipFree(p);
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->kt_stage) hipHostFree(c->kt_stage);
     hipSetDevice(prev);
@@ -319,7 +325,7 @@ void cmb_ctx_destroy(cmb_ctx *c) {
 namespace {
 
 size_t total_bytes(const cmb_ctx *c) {
-    return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap + c->kt_cap + c->b3_cap;
+    return c->tab_cap + c->ws_cap + c->s_cap + c->d_cap + c->st_cap + c->kt_cap + c->b3_cap + c->lens_cap;
 }
 
 int grow(cmb_ctx *c, void **buf, size_t *cap, size_t need, hipStream_t s) {
@@ -707,7 +713,102 @@ static int ensure_bessel3(cmb_ctx *c, int ell_max, hipStream_t s) {
     return CMB_OK;
 }
 
+// Wigner d^l_{m'm} at l = max(|m'|, |m|) by the explicit sum (long double)
+static double wigner_d_start(int mp, int m, double mu) {
+    const int l = std::max(std::abs(mp), std::abs(m));
+    auto fact = [](int n) {
+        long double f = 1.0L;
+        for (int i = 2; i <= n; ++i) f *= i;
+        return f;
+    };
+    const long double c2 = (1.0L + mu) / 2.0L, s2 = std::max((1.0L - mu) / 2.0L, 0.0L);
+    const long double pre = std::sqrt(fact(l + m) * fact(l - m) * fact(l + mp) * fact(l - mp));
+    long double out = 0.0L;
+    for (int k = 0; k <= 2 * l; ++k) {
+        const int a = l + m - k, b = k, cc = l - k - mp, d = k - m + mp;
+        if (a < 0 || b < 0 || cc < 0 || d < 0) continue;
+        const long double coef = ((k - m + mp) % 2 ? -1.0L : 1.0L) * pre / (fact(a) * fact(b) * fact(cc) * fact(d));
+        // exponents 2l-2k+m-m' and 2k-m+m' are even for every pair used
+        out += coef * std::pow(c2, (2 * l - 2 * k + m - mp) / 2) * std::pow(s2, (2 * k - m + mp) / 2);
+    }
+    return (double)out;
+}
+
+// host tables of the lensed-spectrum kernels for (L, n_mu), cached in the context
+static int ensure_lens_tables(cmb_ctx *c, int L, int n_mu, hipStream_t s) {
+    if (c->lens_L == L && c->lens_nmu == n_mu) return CMB_OK;
+    static const int PM[13][2] = {{0, 0}, {1, 1}, {1, -1}, {2, 2}, {2, -2}, {3, 1}, {3, -3},
+                                  {4, 0}, {4, -4}, {0, 2}, {3, -1}, {2, 0}, {-2, 4}};
+    std::vector<double> mu, w;
+    cmbhip::gauss_legendre_nodes(n_mu, mu, w);
+    const size_t n_coef = (size_t)(L + 1) * 13 * 3, n_lf = (size_t)(L + 1) * 4, n_st = (size_t)13 * n_mu;
+    std::vector<double> h(2 * (size_t)n_mu + n_coef + n_lf + n_st, 0.0);
+    double *hmu = h.data(), *hw = hmu + n_mu, *hcoef = hw + n_mu, *hlf = hcoef + n_coef, *hst = hlf + n_lf;
+    std::copy(mu.begin(), mu.end(), hmu);
+    std::copy(w.begin(), w.end(), hw);
+    for (int l = 0; l <= L; ++l) {
+        for (int p = 0; p < 13; ++p) {
+            const double mp = PM[p][0], m = PM[p][1];
+            double *cf = hcoef + ((size_t)l * 13 + p) * 3;
+            if (l < std::max(std::abs(PM[p][0]), std::abs(PM[p][1]))) continue;
+            if (l == 0) {  // d^1_00 = mu d^0_00
+                cf[0] = 1.0;
+                continue;
+            }
+            const double cl = l * std::sqrt(((l + 1.0) * (l + 1.0) - mp * mp) * ((l + 1.0) * (l + 1.0) - m * m));
+            cf[0] = (2.0 * l + 1.0) * l * (l + 1.0) / cl;
+            cf[1] = (2.0 * l + 1.0) * mp * m / cl;
+            cf[2] = (l + 1.0) * std::sqrt(std::max(((double)l * l - mp * mp) * ((double)l * l - m * m), 0.0)) / cl;
+        }
+        const double x = l;
+        hlf[4 * (size_t)l + 0] = 0.25 * std::sqrt(std::max((x + 2) * (x - 1) * x * (x + 1), 0.0));
+        hlf[4 * (size_t)l + 1] = -0.5 * std::sqrt(std::max((x + 2) * (x - 1), 0.0));
+        hlf[4 * (size_t)l + 2] = -0.5 * std::sqrt(std::max((x + 3) * (x - 2), 0.0));
+        hlf[4 * (size_t)l + 3] = 0.25 * std::sqrt(std::max((x + 4) * (x + 3) * (x - 2) * (x - 3), 0.0));
+    }
+    for (int p = 0; p < 13; ++p)
+        for (int i = 0; i < n_mu; ++i) hst[(size_t)p * n_mu + i] = wigner_d_start(PM[p][0], PM[p][1], mu[i]);
+    c->lens_L = c->lens_nmu = 0;
+    int rc = grow(c, &c->lens_buf, &c->lens_cap, h.size() * sizeof(double), s);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(c->lens_buf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is pageable and goes out of scope
+    if (e != hipSuccess) return herr(e, "lensing tables upload");
+    c->lens_L = L;
+    c->lens_nmu = n_mu;
+    return CMB_OK;
+}
+
 extern "C" {
+
+int cmb_lensed_cl(cmb_ctx *c, int n_cosmo, int L, const double *d_Cl, const double *d_Clpp, int ell_max, int n_mu,
+                  double *d_Cll, void *stream) {
+    if (!c || !d_Cl || !d_Clpp || !d_Cll || n_cosmo < 1 || n_cosmo > 65535) {
+        set_error("cmb_lensed_cl: NULL argument or n_cosmo outside [1, 65535]");
+        return CMB_E_INVALID;
+    }
+    if (L < 2 || L > 20000 || ell_max < 2 || ell_max > L || n_mu < 2 || n_mu > 200000) {
+        set_error("cmb_lensed_cl: need 2 <= ell_max <= L <= 20000 and 2 <= n_mu <= 200000");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_lens_tables(c, L, n_mu, s);
+    if (rc) return rc;
+    const int nblk = cmbhip::lens_back_blocks(n_mu);
+    const size_t n_xi = (size_t)n_cosmo * 4 * n_mu, n_part = (size_t)n_cosmo * nblk * 4 * (ell_max + 1);
+    rc = grow(c, &c->ws_buf, &c->ws_cap, sizeof(double) * (n_xi + n_part), s);
+    if (rc) return rc;
+    const double *mu = (const double *)c->lens_buf, *w = mu + n_mu, *coef = w + n_mu,
+                 *lf = coef + (size_t)(L + 1) * 13 * 3, *st = lf + (size_t)(L + 1) * 4;
+    double *xi = (double *)c->ws_buf, *part = xi + n_xi;
+    rc = cmbhip::launch_lensed_cl(n_cosmo, L, ell_max, n_mu, d_Cl, d_Clpp, mu, w, coef, lf, st, xi, part, d_Cll,
+                                  stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
 
 int cmb_bessel3_table(cmb_ctx *c, int ell_max, double *h_xs, double *h_x5, double *h_tab) {
     if (!c || ell_max < 1 || ell_max > 10000) {

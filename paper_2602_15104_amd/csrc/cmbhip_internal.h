@@ -100,6 +100,16 @@ int ell_cut(double x);  // host copy of the Bessel cut rule (tests)
 // per (cosmology, type, time)) into M of the same layout
 int launch_spline_m(const double *d_F, double *d_M, const double *d_kg, const double *d_lo, const double *d_dinv,
                     int n_cosmo, int n_k, int nty, int n_tau, void *stream);
+// m-point Gauss-Legendre nodes (descending) and weights on [-1, 1]
+void gauss_legendre_nodes(int m, std::vector<double> &x, std::vector<double> &w);
+// lensed spectra from full-sky correlation functions: host tables (nodes mu,
+// weights w, recurrence coefficients coef[L+1][13][3], X-function factors
+// lfac[L+1][4], start values start[13][n_mu]), workspace xi[n_cosmo][4][n_mu]
+// and part[n_cosmo][blocks][4][lmax+1]
+int lens_back_blocks(int n_mu);
+int launch_lensed_cl(int n_cosmo, int L, int lmax, int n_mu, const double *d_Cl, const double *d_Clpp,
+                     const double *d_mu, const double *d_w, const double *d_coef, const double *d_lfac,
+                     const double *d_start, double *d_xi, double *d_part, double *d_Cll, void *stream);
 // lensing potential by Limber's approximation (App. B.5): Clpp[c][0..ell_max]
 // from the matter density contrast Dm[c][n_k][n_tau] and its spline M in k
 int launch_limber(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, const double *d_Dm,

@@ -125,6 +125,13 @@ static void gauss_legendre(int m, std::vector<long double> &x, std::vector<long 
     }
 }
 
+void gauss_legendre_nodes(int m, std::vector<double> &x, std::vector<double> &w) {
+    std::vector<long double> xl, wl;
+    gauss_legendre(m, xl, wl);
+    x.assign(xl.begin(), xl.end());
+    w.assign(wl.begin(), wl.end());
+}
+
 // eigenvalues d and first eigenvector components z0 of the symmetric
 // tridiagonal matrix (d on the diagonal, e[i] between i and i+1)
 static bool tridiag_eigen(std::vector<long double> &d, std::vector<long double> e, std::vector<long double> &z0) {
