@@ -293,9 +293,38 @@ def main():
         variants["los_bessel3"] = {"ms_per_batch": float(np.median(t3[1:])), "los_ms": float(np.mean(kt["los"])),
                                    "first_call_s_incl_table": t_b3, "batch": B}
         del D3
+        # lensing: K1 with delta_m at the output times, the Limber potential
+        # spectrum, and lensed TT/TE/EE/BB (l <= 2000 from l <= 2500, 3700 nodes)
+        Dm = torch.empty((B, n_k, n_tau), dtype=torch.float64, device=dev)
+        Pp = torch.empty((B, lmax + 1), dtype=torch.float64, device=dev)
+        l_out, n_mu = 2000, 3700
+        Cll = torch.empty((B, 4, l_out + 1), dtype=torch.float64, device=dev)
+        ctx.lensed_cl(C, Pp.zero_(), l_out, Cll, n_mu=n_mu)  # node tables outside the timing
+        torch.cuda.synchronize()
+        e2 = torch.cuda.Event(enable_timing=True)
+        tm, tl, tz = [], [], []
+        for r in range(3):
+            e0.record()
+            ctx.perturb_matter(tabs, S, st, Dm=Dm, nsteps=ns)
+            e1.record()
+            ctx.lensing_potential(tabs, lmax, Dm, Pp)
+            e2.record()
+            torch.cuda.synchronize()
+            tm.append(e0.elapsed_time(e1))
+            tl.append(e1.elapsed_time(e2))
+            e0.record()
+            ctx.lensed_cl(C, Pp, l_out, Cll, n_mu=n_mu)
+            e1.record()
+            torch.cuda.synchronize()
+            tz.append(e0.elapsed_time(e1))
+        variants["lensing"] = {"perturb_with_delta_m_ms": float(np.median(tm[1:])),
+                               "limber_ms": float(np.median(tl[1:])), "lensed_cl_ms": float(np.median(tz[1:])),
+                               "lensed_l_max": l_out, "unlensed_l_max": lmax, "n_mu": n_mu, "batch": B}
+        del Dm, Pp, Cll
         print(f"[bench] variants: transfer grid {variants['transfer_grid']['ms_per_batch']:.1f} ms, "
               f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
-              f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms", file=sys.stderr, flush=True)
+              f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
+              f"{variants['lensing']}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic flops / measured duration)
     exs = [t.export() for t in tabs]
