@@ -87,7 +87,12 @@ def lib():
             ip = ctypes.POINTER(ctypes.c_int)
             L.oracle_perturb.restype = ctypes.c_int
             L.oracle_perturb.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double,
-                                         ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, ip, ip, dp, ctypes.c_int, dp]
+                                         ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, ip, ip, dp, ctypes.c_int, dp,
+                                         dp, dp, ctypes.c_int]
+            L.oracle_perturb_many_hist.restype = ctypes.c_int
+            L.oracle_perturb_many_hist.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_int, dp, dp,
+                                                   dp, dp, ctypes.c_int, dp, dp, ip, ip, ip, dp, ip, ctypes.c_int,
+                                                   ctypes.c_int]
             L.oracle_rhs.restype = None
             L.oracle_rhs.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, ctypes.c_double,
                                      dp, dp]
@@ -224,6 +229,94 @@ def delta_m_of_state(t, lna: float, y) -> float:
     return lib().oracle_delta_m(ctypes.byref(b.tab), ctypes.byref(p), float(lna), _dp(y))
 
 
+def perturb_hist(t, hist=None, hist_n=None):
+    """All modes, recording each mode's accepted-step history (hist[n_k][cap]:
+    the start, then every accepted step size; counts hist_n), or, given
+    hist/hist_n, replaying them without error control.
+    Returns (S, status, nsteps, hist, hist_n)."""
+    k = np.ascontiguousarray(t.k, dtype=np.float64)
+    lna0 = np.ascontiguousarray(t.lna_i, dtype=np.float64)
+    rtol, atol = tolerances(t.prec, k)
+    n_out = len(t.lna_src)
+    cap = int(t.prec["max_steps"]) + 1
+    replay = hist is not None
+    if not replay:
+        hist = np.zeros((len(k), cap))
+        hist_n = np.zeros(len(k), dtype=np.int32)
+    else:
+        hist = np.ascontiguousarray(hist, dtype=np.float64)
+        hist_n = np.ascontiguousarray(hist_n, dtype=np.int32)
+        cap = hist.shape[1]
+    S = np.zeros((len(k), 3, n_out))
+    st = np.zeros(len(k), dtype=np.int32)
+    ns = np.zeros(len(k), dtype=np.int32)
+    na = np.zeros(len(k), dtype=np.int32)
+    b = _Bound(t)
+    p = make_prec(t.prec, len(t.bg.q))
+    lna_out = np.ascontiguousarray(t.lna_src, dtype=np.float64)
+    lib().oracle_perturb_many_hist(ctypes.byref(b.tab), ctypes.byref(p), len(k), _dp(k), _dp(lna0), _dp(rtol),
+                                   _dp(atol), n_out, _dp(lna_out), _dp(S), _ip(st), _ip(ns), _ip(na), _dp(hist),
+                                   _ip(hist_n), cap, 1 if replay else 0)
+    return S, st, ns, hist, hist_n
+
+
+JAC_PARAMS = ("h", "omega_b", "omega_cdm", "tau_reio")
+
+
+def cl_dns(k, DT, DE, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: float = 0.05):
+    """dC_l/dn_s: the k quadrature of cl with P(k) ln(k/k_pivot) in place of
+    P(k) (C_l depends on n_s only through the primordial spectrum)."""
+    k = np.asarray(k, dtype=np.float64)
+    kl = np.concatenate(([k[0]], k[:-1]))
+    kr = np.concatenate((k[1:], [k[-1]]))
+    f = 0.5 * (kr - kl) * A_s * (k / k_pivot) ** (n_s - 1.0) * np.log(k / k_pivot) / k
+    out = np.zeros((3, ell_max + 1))
+    out[0, 2:] = 4 * math.pi * (DT * DT) @ f
+    if pol:
+        out[1, 2:] = 4 * math.pi * (DT * DE) @ f
+        out[2, 2:] = 4 * math.pi * (DE * DE) @ f
+    return out
+
+
+def jacobian(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, rel: float = 1e-4, order: int = 4):
+    """dC_l/dtheta [6][3][ell_max+1] for theta = (h, omega_b, omega_cdm, ln A_s,
+    n_s, tau_reio).  For h, omega_b, omega_cdm and tau_reio: finite
+    differences at steps of rel (relative), every perturbed cosmology replaying
+    the base cosmology's accepted steps (the derivative of the frozen-step
+    discrete map); order 2 is the central difference (f(+e) - f(-e))/(2e),
+    order 4 the five-point (8 (f(+e) - f(-e)) - (f(+2e) - f(-2e)))/(12 e).
+    For ln A_s C_l itself, for n_s the primordial-weight quadrature cl_dns.
+    Returns (C_l, J, status of the base run)."""
+    if order not in (2, 4):
+        raise ValueError("order must be 2 or 4")
+    t = build_tables(cosmo, prec, k, n_tau)
+    S, st, ns, hist, hn = perturb_hist(t)
+    DT, DE = los(t, S, ell_max, pol)
+    C = cl(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    J = np.zeros((6, 3, ell_max + 1))
+    slot = {"h": 0, "omega_b": 1, "omega_cdm": 2, "tau_reio": 5}
+
+    def at(name, mult):
+        c2 = dict(cosmo)
+        c2[name] = cosmo[name] * (1.0 + mult * rel)
+        t2 = build_tables(c2, prec, k, n_tau)
+        S2 = perturb_hist(t2, hist, hn)[0]
+        D2T, D2E = los(t2, S2, ell_max, pol)
+        return cl(t2.k, D2T, D2E, ell_max, pol, c2["A_s"], c2["n_s"], prec["k_pivot"])
+
+    for name in JAC_PARAMS:
+        e = rel * cosmo[name]
+        d1 = at(name, 1.0) - at(name, -1.0)
+        if order == 2:
+            J[slot[name]] = d1 / (2.0 * e)
+        else:
+            d2 = at(name, 2.0) - at(name, -2.0)
+            J[slot[name]] = (8.0 * d1 - d2) / (12.0 * e)
+    J[3] = C
+    J[4] = cl_dns(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    return C, J, st
+
+
 def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None, y0=None, want_y: bool = False,
                 rtol: float | None = None, atol: float | None = None, acc_cap: int = 0, want_diag: bool = False):
     """One mode with full control (tests): custom start, output times,
@@ -249,7 +342,8 @@ def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None
     b = _Bound(t)
     st = lib().oracle_perturb(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna0), n_out, _dp(lna_out), _dp(S),
                               _dp(Y) if want_y else None, _dp(y0a) if y0a is not None else None, ctypes.byref(ns),
-                              ctypes.byref(na), _dp(acc) if acc_cap else None, acc_cap, _dp(D) if want_diag else None)
+                              ctypes.byref(na), _dp(acc) if acc_cap else None, acc_cap, _dp(D) if want_diag else None,
+                              None, None, 0)
     out = {"S": S, "status": st, "nsteps": ns.value, "naccept": na.value, "N": N}
     if want_diag:
         out["diag"] = D  # h', eta', alpha, alpha' per output time

@@ -452,11 +452,16 @@ static void sources_at(const otab_t *tb, const oprec_t *p, const olayout_t *L, d
  *   yout (optional): [n_out][N] dense-output states.
  *   y0 (optional): initial state overriding the adiabatic one.
  *   acc_lna (optional): accepted step end points, up to acc_cap of them.
+ *   acc_h (optional): accepted step sizes, up to acc_cap of them.
+ *   fixed (optional): replay; fixed[0] is the start (overriding lna0) and
+ *     fixed[1..n_fixed] the step sizes, taken without error control (the
+ *     recorded start and acc_h of another run).
  * Returns a status code; nsteps = attempted steps, naccept = accepted.
  */
 int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, int n_out, const double *lna_out,
                    double *S, double *yout, const double *y0, int *nsteps, int *naccept, double *acc_lna,
-                   int acc_cap, double *diag) {
+                   int acc_cap, double *diag, double *acc_h,
+                   const double *fixed, int n_fixed) {
     olayout_t L;
     make_layout(p, &L);
     int N = L.N;
@@ -472,7 +477,7 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
     for (int i = 0; i < 3 * n_out; ++i) S[i] = 0.0;
     int status = O_OK;
     int ns = 0, na = 0;
-    double t = lna0;
+    double t = fixed ? fixed[0] : lna0;
     obg_t b;
     background_at(tb, t, &b);
     if (y0)
@@ -485,8 +490,8 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
     while (jo < n_out && lna_out[jo] < t) ++jo;
 
     /* starting step (Hairer, Norsett & Wanner, Sec. II.4), order 4 */
-    double h;
-    {
+    double h = 0.0;
+    if (!fixed) {
         double d0 = rms_norm(N, y, y, NULL, p->rtol, p->atol);
         double d1 = rms_norm(N, f, y, NULL, p->rtol, p->atol);
         double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
@@ -515,7 +520,14 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
             break;
         }
         int last = 0;
-        if (h >= -t) {
+        if (fixed) {
+            if (na >= n_fixed) {
+                status = O_MAX_STEPS;
+                break;
+            }
+            h = fixed[1 + na];
+            last = t + h >= 0.0;
+        } else if (h >= -t) {
             h = -t;
             last = 1;
         }
@@ -553,8 +565,9 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
             break;
         }
         double fac;
-        if (E <= 1.0) {
+        if (fixed || E <= 1.0) {
             double tn = last ? 0.0 : t + h;
+            if (acc_h && na < acc_cap) acc_h[na] = h;
             if (tn >= 0.0) tn = 0.0;
             /* dense output */
             while (jo < n_out && lna_out[jo] <= tn) {
@@ -583,7 +596,7 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
             fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -0.25)));
         }
         h *= fac;
-        if (t < 0.0 && h < 1e-12) {
+        if (!fixed && t < 0.0 && h < 1e-12) {
             status = O_STEP_UNDERFLOW;
             break;
         }
@@ -606,7 +619,32 @@ int oracle_perturb_many(const otab_t *tb, const oprec_t *p0, int nk, const doubl
         p.rtol = rtol[i];
         p.atol = atol[i];
         status[i] = oracle_perturb(tb, &p, k[i], lna0[i], n_out, lna_out, S + (size_t)i * 3 * n_out, NULL, NULL,
-                                   &nsteps[i], &naccept[i], NULL, 0, NULL);
+                                   &nsteps[i], &naccept[i], NULL, 0, NULL, NULL, NULL, 0);
+    }
+    return 0;
+}
+
+/* All modes with their accepted-step histories hist[nk][cap] (entry 0 the
+   start, then every accepted end point; cap >= max_steps + 1), or, with
+   replay != 0, replaying those histories (counts hn[nk]) without error control. */
+int oracle_perturb_many_hist(const otab_t *tb, const oprec_t *p0, int nk, const double *k, const double *lna0,
+                             const double *rtol, const double *atol, int n_out, const double *lna_out, double *S,
+                             int *status, int *nsteps, int *naccept, double *hist, int *hn, int cap, int replay) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = nk - 1; i >= 0; --i) {
+        oprec_t p = *p0;
+        p.rtol = rtol[i];
+        p.atol = atol[i];
+        double *hi = hist + (size_t)i * cap;
+        if (replay) {
+            status[i] = oracle_perturb(tb, &p, k[i], hi[0], n_out, lna_out, S + (size_t)i * 3 * n_out, NULL, NULL,
+                                       &nsteps[i], &naccept[i], NULL, 0, NULL, NULL, hi, hn[i]);
+        } else {
+            hi[0] = lna0[i];
+            status[i] = oracle_perturb(tb, &p, k[i], lna0[i], n_out, lna_out, S + (size_t)i * 3 * n_out, NULL, NULL,
+                                       &nsteps[i], &naccept[i], NULL, cap - 1, NULL, hi + 1, NULL, 0);
+            hn[i] = naccept[i] < cap - 1 ? naccept[i] : cap - 1;
+        }
     }
     return 0;
 }
@@ -624,7 +662,7 @@ int oracle_perturb_many_dm(const otab_t *tb, const oprec_t *p0, int nk, const do
         p.atol = atol[i];
         double *Y = (double *)calloc((size_t)n_out * N, sizeof(double));
         status[i] = oracle_perturb(tb, &p, k[i], lna0[i], n_out, lna_out, S + (size_t)i * 3 * n_out, Y, NULL,
-                                   &nsteps[i], &naccept[i], NULL, 0, NULL);
+                                   &nsteps[i], &naccept[i], NULL, 0, NULL, NULL, NULL, 0);
         for (int j = 0; j < n_out; ++j) {
             /* a state row that the integration never produced is still all zero */
             const double *y = Y + (size_t)j * N;

@@ -904,3 +904,66 @@ def test_lensing_first_order_flat_sky_limit():
               1: -l * l * R * cX(l) + np.sum(kern * cX(l1s) * c2)}
         for i, ref in fl.items():
             assert abs(A[i, l] / ref - 1) < 0.03, (l, i, A[i, l], ref)
+
+
+# ---------------------------------------------------------------- P18 parameter derivatives
+@pytest.fixture(scope="module")
+def jac_case():
+    wl = W.small_case(n_k=16, n_tau=150, ell_max=200, k_max=0.1)
+    return wl
+
+
+def test_replay_reproduces_run(jac_case):
+    """Replaying a run's own recorded start and step sizes reproduces its
+    sources bit for bit (the same sequence of times and stages)."""
+    wl = jac_case
+    t = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    S, st, ns, hist, hn = O.perturb_hist(t)
+    assert np.array_equal(S, O.perturb(t)[0]) and np.all(st == 0)
+    assert np.all(hn == O.perturb(t)[3])  # one history entry per accepted step
+    S2, st2, ns2, _, _ = O.perturb_hist(t, hist, hn)
+    assert np.array_equal(S2, S) and np.all(ns2 == hn)
+
+
+def test_jacobian_stencils_consistent(jac_case):
+    """Frozen steps make the discrete map smooth: the five-point derivative at
+    rel 1e-4 and at 2e-4 agree to 1e-6 of each row (measured <= 1.6e-7), and
+    the central difference differs from it only by its O(e^2) truncation."""
+    wl = jac_case
+    C, J4, st = O.jacobian(wl.cosmo, wl.prec, wl.k, wl.n_tau, 120, True, rel=1e-4, order=4)
+    _, J4b, _ = O.jacobian(wl.cosmo, wl.prec, wl.k, wl.n_tau, 120, True, rel=2e-4, order=4)
+    _, J2, _ = O.jacobian(wl.cosmo, wl.prec, wl.k, wl.n_tau, 120, True, rel=1e-4, order=2)
+    assert np.all(st == 0)
+    for p in (0, 1, 2, 5):
+        m = np.max(np.abs(J4[p][:, 2:]))
+        assert np.max(np.abs(J4b[p][:, 2:] - J4[p][:, 2:])) < 1e-6 * m, p
+        assert np.max(np.abs(J2[p][:, 2:] - J4[p][:, 2:])) < 1e-4 * m, p
+    assert np.array_equal(J4[3], C)
+
+
+def test_dcl_dns_analytic(tab12):
+    """dC/dn_s by the ln(k/k_pivot)-weighted quadrature against a five-point
+    difference of the oracle's C_l in n_s on the same transfer functions."""
+    t = tab12
+    rng = np.random.default_rng(2)
+    S = rng.standard_normal((len(t.k), 3, len(t.chi_src)))
+    DT, DE = O.los(t, S, 20, True)
+    ns, e = 0.965, 1e-3
+    f = lambda x: O.cl(t.k, DT, DE, 20, True, 2e-9, x, 0.05)  # noqa: E731
+    fd = (8 * (f(ns + e) - f(ns - e)) - (f(ns + 2 * e) - f(ns - 2 * e))) / (12 * e)
+    an = O.cl_dns(t.k, DT, DE, 20, True, 2e-9, ns, 0.05)
+    assert np.max(np.abs(an[:, 2:] - fd[:, 2:])) < 1e-9 * np.max(np.abs(an[:, 2:]))
+
+
+def test_dcl_dtau_reio_high_l():
+    """Above the reionisation scales the spectra scale as e^{-2 tau_reio}:
+    dC/dtau = -2 C (on average over l = 250-300 within 2.5% for EE and over
+    l = 200-300 within 10% for TT; late-time sources and the coarse k grid
+    scatter single multipoles by ~10%)."""
+    wl = W.small_case(n_k=120, n_tau=200, ell_max=300, k_min=1e-4, k_max=0.05)
+    wl.prec["max_steps"] = 6000
+    C, J, st = O.jacobian(wl.cosmo, wl.prec, wl.k, wl.n_tau, 300, True, rel=1e-4, order=2)
+    assert np.all(st == 0)
+    ree = J[5, 2, 250:301] / C[2, 250:301]
+    rtt = J[5, 0, 200:301] / C[0, 200:301]
+    assert abs(np.mean(ree) + 2) < 0.05 and abs(np.mean(rtt) + 2) < 0.2
