@@ -210,6 +210,39 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
 int cmb_spectra_on_grid(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
                         const double *kt, int n_kt, double *d_St, double *d_Delta, double *d_Cl, void *hip_stream);
 
+/* ---------------------------------------------------- parameter derivatives */
+/* Step histories of the perturbation integration (App. A.2 solver options):
+ * cmb_perturb_record runs cmb_perturb and writes, per mode, the start ln a_i
+ * and the size of every accepted step into d_hist[n_cosmo][n_k][hist_cap]
+ * (entry 0 the start) with the counts in d_hist_n[n_cosmo][n_k];
+ * cmb_perturb_replay integrates each mode from its recorded start with
+ * exactly those steps and no error control (the same tables replay a run bit
+ * for bit; other tables give the frozen-step discrete map, whose finite
+ * differences carry no step-control noise).  hist_cap >= max_steps + 1.
+ * Errors as cmb_perturb. */
+int cmb_perturb_record(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                       int32_t *d_nsteps, double *d_hist, int32_t *d_hist_n, int hist_cap, void *hip_stream);
+int cmb_perturb_replay(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, const double *d_hist,
+                       const int32_t *d_hist_n, int hist_cap, double *d_S, int32_t *d_status, int32_t *d_nsteps,
+                       void *hip_stream);
+
+/* Spectra and their derivatives with respect to theta = (h, omega_b,
+ * omega_cdm, ln A_s, n_s, tau_reio) for a batch of cosmologies sharing one k
+ * grid (each with tau_reio given):
+ *   d_Cl: device [n_cosmo][3][ell_max+1]  TT, TE, EE as cmb_solve;
+ *   d_J:  device [n_cosmo][6][3][ell_max+1]  dC/dtheta_p.
+ * For h, omega_b, omega_cdm and tau_reio the host builds the tables at
+ * theta_p (1 +- rel) (and +- 2 rel for order 4) on worker threads; every
+ * perturbed cosmology replays its base cosmology's recorded steps, and the
+ * spectra combine by the central (order 2) or five-point (order 4) stencil
+ * with step e = rel theta_p.  dC/d ln A_s = C; dC/dn_s is the k quadrature
+ * with P(k) ln(k/k_pivot).  d_status [n_cosmo][n_k]: the base run's status,
+ * or a failing replay's.  0 < rel <= 0.01.  Synchronises hip_stream before
+ * returning (the perturbed tables are temporary).  Errors: CMB_E_INVALID,
+ * CMB_E_UNSUPPORTED, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_jacobian(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double rel, int order,
+                 double *d_Cl, double *d_J, int32_t *d_status, void *hip_stream);
+
 /* ---------------------------------------------------------------- lensing */
 /* cmb_perturb plus the matter outputs (App. B.4 eq. PK, App. B.5): either
  * pointer may be NULL, not both.

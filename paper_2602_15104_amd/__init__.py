@@ -44,7 +44,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
-           "cmb_lensed_cl",
+           "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_jacobian",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -124,6 +124,12 @@ def _declare(lib):
     lib.cmb_perturb_matter.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.cmb_lensing_potential.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_lensed_cl.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
+    lib.cmb_perturb_record.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                       _vp]
+    lib.cmb_perturb_replay.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
+                                       _vp]
+    lib.cmb_jacobian.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 _vp, _vp, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -309,6 +315,24 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_lensing_potential(self._h, hs, len(tabs), int(ell_max), _ptr(Dm), _ptr(Clpp),
                                           _stream(stream)), "cmb_lensing_potential")
+
+    def perturb_record(self, tabs, S, status, hist, hist_n, nsteps=None, stream=None):
+        """cmb_perturb recording the accepted steps into hist[n][n_k][cap], hist_n[n][n_k]."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_record(self._h, hs, len(tabs), _ptr(S), _ptr(status), _ptr(nsteps), _ptr(hist),
+                                       _ptr(hist_n), int(hist.shape[-1]), _stream(stream)), "cmb_perturb_record")
+
+    def perturb_replay(self, tabs, hist, hist_n, S, status, nsteps=None, stream=None):
+        """Integrate every mode on its recorded steps (cmb_perturb_replay)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_replay(self._h, hs, len(tabs), _ptr(hist), _ptr(hist_n), int(hist.shape[-1]),
+                                       _ptr(S), _ptr(status), _ptr(nsteps), _stream(stream)), "cmb_perturb_replay")
+
+    def jacobian(self, tabs, ell_max, Cl, J, status, rel=1e-4, order=4, stream=None):
+        """C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s, tau_reio) (cmb_jacobian)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_jacobian(self._h, hs, len(tabs), int(ell_max), float(rel), int(order), _ptr(Cl), _ptr(J),
+                                 _ptr(status), _stream(stream)), "cmb_jacobian")
 
     def lensed_cl(self, Cl, Clpp, ell_max, Cll, n_mu=None, stream=None):
         """Lensed TT, TE, EE, BB [n][4][ell_max+1] from unlensed Cl[n][3][L+1]

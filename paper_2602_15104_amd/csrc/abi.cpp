@@ -10,7 +10,9 @@
 #include <limits>
 #include <mutex>
 #include <new>
+#include <memory>
 #include <string>
+#include <thread>
 
 #include "cmbhip_internal.h"
 
@@ -779,7 +781,243 @@ static int ensure_lens_tables(cmb_ctx *c, int L, int n_mu, hipStream_t s) {
     return CMB_OK;
 }
 
+// DevTab copies (with step-history pointers) and n_extra doubles, staged
+// through the context's small buffer; synchronises the stream first (the
+// staging may still be read by a previous call)
+static int upload_devtabs(cmb_ctx *c, const std::vector<cmbhip::DevTab> &v, const std::vector<double> &extra,
+                          hipStream_t s, cmbhip::DevTab **d_tabs, double **d_extra) {
+    const size_t o_x = align256(sizeof(cmbhip::DevTab) * v.size());
+    const size_t bytes = o_x + align256(sizeof(double) * std::max<size_t>(extra.size(), 1));
+    int rc = grow(c, &c->kt_buf, &c->kt_cap, bytes, s);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    if (bytes > c->kt_stage_cap) {
+        if (c->kt_stage) hipHostFree(c->kt_stage);
+        c->kt_stage = nullptr;
+        c->kt_stage_cap = 0;
+        e = hipHostMalloc(&c->kt_stage, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return herr(e, "hipHostMalloc");
+        c->kt_stage_cap = bytes;
+    }
+    std::memcpy(c->kt_stage, v.data(), sizeof(cmbhip::DevTab) * v.size());
+    if (!extra.empty()) std::memcpy((char *)c->kt_stage + o_x, extra.data(), sizeof(double) * extra.size());
+    e = hipMemcpyAsync(c->kt_buf, c->kt_stage, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return herr(e, "hipMemcpyAsync (descriptors)");
+    *d_tabs = (cmbhip::DevTab *)c->kt_buf;
+    if (d_extra) *d_extra = (double *)((char *)c->kt_buf + o_x);
+    return CMB_OK;
+}
+
+// K1 over tabs with step histories: cosmology i records into (replay = false)
+// or replays (replay = true) hist + base[i] n_k cap, hist_n + base[i] n_k
+static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const std::vector<int> &base,
+                        double *d_hist, int32_t *d_hist_n, int cap, bool replay, double *d_S, int32_t *d_status,
+                        int32_t *d_nsteps, hipStream_t s) {
+    Batch b;
+    int rc = check_batch(tabs, n, b);
+    if (rc) return rc;
+    if (!cmbhip::perturb2_supported(b.prec)) {
+        set_error("step histories are built into the cooperative perturbation kernel only");
+        return CMB_E_UNSUPPORTED;
+    }
+    if (cap < tabs[0]->t.prec.max_steps + 1) {
+        set_error("step history capacity below max_steps + 1");
+        return CMB_E_INVALID;
+    }
+    rc = upload(c, tabs, n, s);
+    if (rc) return rc;
+    std::vector<cmbhip::DevTab> v(c->h_tabs);
+    for (int i = 0; i < n; ++i) {
+        double *h = d_hist + (size_t)base[i] * b.n_k * cap;
+        int *hn = d_hist_n + (size_t)base[i] * b.n_k;
+        v[i].hist_cap = cap;
+        if (replay) {
+            v[i].hist_in = h;
+            v[i].hist_in_n = hn;
+        } else {
+            v[i].hist_out = h;
+            v[i].hist_out_n = hn;
+        }
+    }
+    cmbhip::DevTab *dt = nullptr;
+    rc = upload_devtabs(c, v, {}, s, &dt, nullptr);
+    if (rc) return rc;
+    int32_t *ns = d_nsteps;
+    if (!ns) {
+        rc = grow(c, &c->st_buf, &c->st_cap, sizeof(int32_t) * (size_t)n * b.n_k, s);
+        if (rc) return rc;
+        ns = (int32_t *)c->st_buf;
+    }
+    return cmbhip::launch_perturb2(dt, n, b.n_k, b.n_tau, b.prec, d_S, d_status, ns, nullptr, nullptr, s);
+}
+
 extern "C" {
+
+int cmb_perturb_record(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
+                       int32_t *d_nsteps, double *d_hist, int32_t *d_hist_n, int hist_cap, void *stream) {
+    if (!c || !d_S || !d_status || !d_hist || !d_hist_n || n_cosmo < 1) {
+        set_error("cmb_perturb_record: NULL argument");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    std::vector<int> base(n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) base[i] = i;
+    int rc = perturb_hist(c, tabs, n_cosmo, base, d_hist, d_hist_n, hist_cap, false, d_S, d_status, d_nsteps,
+                          (hipStream_t)stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_perturb_replay(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, const double *d_hist,
+                       const int32_t *d_hist_n, int hist_cap, double *d_S, int32_t *d_status, int32_t *d_nsteps,
+                       void *stream) {
+    if (!c || !d_S || !d_status || !d_hist || !d_hist_n || n_cosmo < 1) {
+        set_error("cmb_perturb_replay: NULL argument");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    std::vector<int> base(n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) base[i] = i;
+    int rc = perturb_hist(c, tabs, n_cosmo, base, const_cast<double *>(d_hist), const_cast<int32_t *>(d_hist_n),
+                          hist_cap, true, d_S, d_status, d_nsteps, (hipStream_t)stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double rel, int order,
+                 double *d_Cl, double *d_J, int32_t *d_status, void *stream) {
+    if (!c || !tabs || !d_Cl || !d_J || !d_status || n_cosmo < 1) {
+        set_error("cmb_jacobian: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000 || !(rel > 0.0 && rel <= 0.01) || (order != 2 && order != 4)) {
+        set_error("cmb_jacobian: need 2 <= ell_max <= 10000, 0 < rel <= 0.01 and order 2 or 4");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    for (int i = 0; i < n_cosmo; ++i)
+        if (!std::isfinite(tabs[i]->t.cosmo.tau_reio) || tabs[i]->t.k != tabs[0]->t.k) {
+            set_error("cmb_jacobian: every cosmology needs tau_reio (not z_reio) and the same k grid");
+            return CMB_E_INVALID;
+        }
+    if (b.n_tau > cmbhip::los_max_tau()) {
+        set_error("n_tau above the line-of-sight kernel's limit");
+        return CMB_E_UNSUPPORTED;
+    }
+    const int nb = n_cosmo, nm = order == 4 ? 4 : 2, n_k = b.n_k, n_tau = b.n_tau;
+    const double mult[4] = {1.0, -1.0, 2.0, -2.0};
+    const int slot[4] = {0, 1, 2, 5};  // h, omega_b, omega_cdm, tau_reio in (h, wb, wc, ln A_s, n_s, tau)
+    // perturbed tables on host threads: pert[p][m nb + cb]
+    std::vector<std::vector<std::unique_ptr<cmb_tables>>> pert(4);
+    std::vector<int> brc(4 * nm * nb, CMB_OK);
+    {
+        std::vector<std::pair<int, int>> jobs;
+        for (int p = 0; p < 4; ++p) {
+            pert[p].resize(nm * nb);
+            for (int j = 0; j < nm * nb; ++j) jobs.emplace_back(p, j);
+        }
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (size_t q; (q = next.fetch_add(1)) < jobs.size();) {
+                const int p = jobs[q].first, j = jobs[q].second, m = j / nb, cb = j % nb;
+                const cmbhip::Tables &t0 = tabs[cb]->t;
+                cmb_cosmo cc = t0.cosmo;
+                double *v = p == 0 ? &cc.h : p == 1 ? &cc.omega_b : p == 2 ? &cc.omega_cdm : &cc.tau_reio;
+                *v *= 1.0 + mult[m] * rel;
+                std::unique_ptr<cmb_tables> t(new (std::nothrow) cmb_tables);
+                int r = t ? CMB_OK : CMB_E_NOMEM;
+                try {
+                    if (r == CMB_OK) r = cmbhip::build_tables(cc, t0.prec, t0.k.data(), n_k, n_tau, t->t);
+                } catch (const std::exception &) {
+                    r = CMB_E_INVALID;
+                }
+                if (r == CMB_OK) t->t.uid = cmbhip::g_uid.fetch_add(1);
+                brc[(size_t)p * nm * nb + j] = r;
+                pert[p][j] = std::move(t);
+            }
+        };
+        unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned i = 0; i < nth; ++i) th.emplace_back(work);
+        for (auto &x : th) x.join();
+        for (int r : brc)
+            if (r != CMB_OK) {
+                set_error("cmb_jacobian: a perturbed table build failed");
+                return r;
+            }
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int cap = tabs[0]->t.prec.max_steps + 1;
+    const int n3 = 3 * (ell_max + 1), nl = ell_max - 1;
+    const size_t n_run = (size_t)nm * nb;  // cosmologies per replay launch
+    // workspace: hist | hist_n | replay status | C of the stencil points
+    const size_t o_hn = align256(sizeof(double) * (size_t)nb * n_k * cap);
+    const size_t o_rs = o_hn + align256(sizeof(int32_t) * (size_t)nb * n_k);
+    const size_t o_cp = o_rs + align256(sizeof(int32_t) * n_run * n_k);
+    const size_t ws = o_cp + align256(sizeof(double) * n_run * n3);
+    rc = grow(c, &c->ws_buf, &c->ws_cap, ws, s);
+    if (rc) return rc;
+    rc = grow(c, &c->s_buf, &c->s_cap, sizeof(double) * n_run * n_k * 3 * n_tau, s);
+    if (rc) return rc;
+    rc = grow(c, &c->d_buf, &c->d_cap, sizeof(double) * n_run * 2 * nl * n_k, s);
+    if (rc) return rc;
+    char *w = (char *)c->ws_buf;
+    double *hist = (double *)w, *Cp = (double *)(w + o_cp);
+    int32_t *hn = (int32_t *)(w + o_hn), *rst = (int32_t *)(w + o_rs);
+    double *S = (double *)c->s_buf, *D = (double *)c->d_buf;
+    // base: record, project, C_l; ln A_s slot = C_l, n_s slot = ln-weighted quadrature
+    std::vector<int> base(n_run);
+    for (size_t j = 0; j < n_run; ++j) base[j] = (int)(j % nb);
+    rc = perturb_hist(c, tabs, nb, base, hist, hn, cap, false, S, d_status, nullptr, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_los(c->d_tabs, nb, n_k, n_tau, ell_max, b.polar, b.s_pol, S, D, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl(c->d_tabs, nb, n_k, ell_max, D, d_Cl, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl_ex(c->d_tabs, nb, n_k, ell_max, D, d_J + 3 * n3, (long)6 * n3, 0, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl_ex(c->d_tabs, nb, n_k, ell_max, D, d_J + 4 * n3, (long)6 * n3, 1, s);
+    if (rc) return rc;
+    // the four table parameters: replays of the base steps at the stencil points
+    for (int p = 0; p < 4; ++p) {
+        std::vector<const cmb_tables *> run(n_run);
+        for (size_t j = 0; j < n_run; ++j) run[j] = pert[p][j].get();
+        rc = perturb_hist(c, run.data(), (int)n_run, base, hist, hn, cap, true, S, rst, nullptr, s);
+        if (rc) return rc;
+        rc = cmbhip::launch_los(c->d_tabs, (int)n_run, n_k, n_tau, ell_max, b.polar, b.s_pol, S, D, s);
+        if (rc) return rc;
+        rc = cmbhip::launch_cl(c->d_tabs, (int)n_run, n_k, ell_max, D, Cp, s);
+        if (rc) return rc;
+        std::vector<double> e(nb);
+        for (int cb = 0; cb < nb; ++cb) {
+            const cmb_cosmo &cc = tabs[cb]->t.cosmo;
+            const double v = p == 0 ? cc.h : p == 1 ? cc.omega_b : p == 2 ? cc.omega_cdm : cc.tau_reio;
+            e[cb] = rel * v;
+        }
+        cmbhip::DevTab *unused = nullptr;
+        double *d_e = nullptr;
+        rc = upload_devtabs(c, {}, e, s, &unused, &d_e);
+        if (rc) return rc;
+        rc = cmbhip::launch_fd(nb, ell_max, order, Cp, d_e, d_J + (size_t)slot[p] * n3, (long)6 * n3, s);
+        if (rc) return rc;
+        rc = cmbhip::launch_merge_status(nb, n_k, nm, rst, d_status, s);
+        if (rc) return rc;
+    }
+    hipError_t e = hipStreamSynchronize(s);  // the perturbed tables are freed on return
+    if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    set_error("");
+    return CMB_OK;
+}
 
 int cmb_lensed_cl(cmb_ctx *c, int n_cosmo, int L, const double *d_Cl, const double *d_Clpp, int ell_max, int n_mu,
                   double *d_Cll, void *stream) {

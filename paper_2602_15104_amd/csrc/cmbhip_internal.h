@@ -47,6 +47,14 @@ struct DevTab {
     const double *lens_w;     // [n_tau] Limber weights of the lensing potential
     double *S;                // work-list launches only: this cosmology's [n_k][3][n_tau] sources
     int *status, *nsteps;     //   and [n_k] status / step counts
+    // accepted-step histories [n_k][hist_cap] (entry 0: start, then the size
+    // of every accepted step): replayed from hist_in (no error control)
+    // and/or recorded into hist_out with their counts; NULL when unused
+    const double *hist_in;
+    const int *hist_in_n;
+    double *hist_out;
+    int *hist_out_n;
+    int hist_cap, hist_pad;
     double L0, inv_dl;
     int n_tab, n_k, n_tau, pad;
     double tau0, R_nu;
@@ -89,6 +97,13 @@ int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_ma
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
               void *stream);
 int los_max_tau();
+// K3 with an output stride per cosmology and optionally the ln(k/k_pivot)
+// weight (dC/dn_s); finite-difference stencils and replay status merging
+int launch_cl_ex(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
+                 long out_stride, int dlog, void *stream);
+int launch_fd(int n_base, int ell_max, int order, const double *d_C, const double *d_e, double *d_J, long j_stride,
+              void *stream);
+int launch_merge_status(int n_base, int n_k, int n_rep, const int *d_rep, int *d_st, void *stream);
 // sources of the perturbation grid interpolated in k onto kt (natural cubic
 // splines; elimination factors lo/dinv and intervals seg from the host); M is
 // workspace of the size of S

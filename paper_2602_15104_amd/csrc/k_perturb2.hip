@@ -523,7 +523,13 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const DevTab &tb = tabs[c];
     const int n_tau = items ? tb.n_tau : n_tau_all;
     const double k = tb.k[ik];
-    const double t0 = tb.lna_start[ik];
+    // step history: replay the accepted step sizes hin[1..hin_n] from the
+    // start hin[0] without error control, or record this mode's into hout
+    // (same start and sizes: the same sequence of times, bit for bit)
+    const double *hin = tb.hist_in ? tb.hist_in + (size_t)ik * tb.hist_cap : nullptr;
+    const int hin_n = hin ? min(tb.hist_in_n[ik], tb.hist_cap - 1) : 0;
+    double *hout = tb.hist_out ? tb.hist_out + (size_t)ik * tb.hist_cap : nullptr;
+    const double t0 = hin ? hin[0] : tb.lna_start[ik];
     const bool small = k < tb.k_split;
     const double rtol = small ? tb.rtol_small : tb.rtol_large;
     const double atol = small ? tb.atol_small : tb.atol_large;
@@ -629,8 +635,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         while (jo < n_tau && lo[jo] < t0) ++jo;
     }
     double t = t0;
-    double h;
-    {
+    double h = 0.0;
+    if (!hin) {
         double d0 = rms(w.y, w.y, nullptr);
         double d1 = rms(w.K[0], w.y, nullptr);
         double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
@@ -652,7 +658,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / 4.0;
     const double b3 = p.dcoeff / 4.0;
     double lEp = 0.0, lEpp = 0.0;  // logs of the previous two accepted error norms
-    int ns = 0, st = CMB_K_OK;
+    int ns = 0, na = 0, st = CMB_K_OK;
+    if (hout && gl == 0) hout[0] = t0;
 
     while (t < 0.0) {
         if (ns >= p.max_steps) {
@@ -660,7 +667,14 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             break;
         }
         bool last = false;
-        if (h >= -t) {
+        if (hin) {
+            if (na >= hin_n) {
+                st = CMB_K_MAX_STEPS;
+                break;
+            }
+            h = hin[1 + na];
+            last = t + h >= 0.0;
+        } else if (h >= -t) {
             h = -t;
             last = true;
         }
@@ -990,9 +1004,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             break;
         }
         double fac;
-        if (E <= 1.0) {
+        if (hin || E <= 1.0) {
             double tn = last ? 0.0 : t + h;
             if (tn >= 0.0) tn = 0.0;
+            if (hout && gl == 0 && na + 1 < tb.hist_cap) hout[1 + na] = h;
+            ++na;
             double hh = tn - t;
             while (jo < n_tau && lo[jo] <= tn) {
                 double th = hh > 0.0 ? (lo[jo] - t) / hh : 1.0;
@@ -1063,7 +1079,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -0.25)));
         }
         h *= fac;
-        if (t < 0.0 && h < 1e-12) {
+        if (!hin && t < 0.0 && h < 1e-12) {
             st = CMB_K_STEP_UNDERFLOW;
             break;
         }
@@ -1098,6 +1114,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             So[2 * n_tau + jo] = 0.0;
             if (Dmo) Dmo[jo] = 0.0;
         }
+        if (hout) tb.hist_out_n[ik] = na < tb.hist_cap ? na : tb.hist_cap - 1;
         if (items) {
             tb.status[ik] = st;
             tb.nsteps[ik] = ns;

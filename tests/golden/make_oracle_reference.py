@@ -1,6 +1,6 @@
 """Write the oracle spectra used by the GPU parity tests at full size.
 
-    python tests/golden/make_oracle_reference.py [config1] [config2] [config1_transfer]
+    python tests/golden/make_oracle_reference.py [config1] [config2] [config1_transfer] [config1_jacobian]
 
 Calls only the CPU oracle (package ``oracle``) and the seeded workload
 generator; re-run it whenever the oracle's arithmetic changes.  Outputs, for
@@ -12,6 +12,9 @@ plus, for config 2, the per-mode step counts (oracle_config2_nsteps.npy), and
   tests/golden/oracle_config1_transfer_cl.npy  config 1's sources interpolated
                                       onto the App. A.2 transfer grid for
                                       l_max = 2500, projected and integrated there
+  tests/golden/oracle_config1_jacobian.npy  dC_l/d(h, omega_b, omega_cdm, ln A_s,
+                                      n_s, tau_reio) [6][3][2501] for config 1
+                                      (five-point stencil, rel 1e-4, frozen steps)
 """
 import os
 import sys
@@ -28,6 +31,14 @@ import oracle as O  # noqa: E402
 
 def main(which):
     for name in which:
+        if name.endswith("_jacobian"):
+            wl = getattr(W, name.replace("_jacobian", ""))()
+            t0 = time.time()
+            C, J, st = O.jacobian(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True, rel=1e-4, order=4)
+            assert np.all(st == 0)
+            np.save(os.path.join(HERE, f"oracle_{name}.npy"), J)
+            print(f"wrote oracle_{name}.npy in {time.time() - t0:.1f} s", flush=True)
+            continue
         transfer = name.endswith("_transfer")
         wl = getattr(W, name.replace("_transfer", ""))()
         t0 = time.time()

@@ -813,3 +813,95 @@ def test_lensed_cl_config1(ctx):
          "BB/EE at 1000", o[3, 1000] / o[2, 1000])
     assert tt < 1e-6 and te < 1e-6 and ee < 1e-6 and bb < 1e-6
     assert 0.01 < lens_tt < 0.5 and 1e-3 < o[3, 1000] / o[2, 1000] < 0.1
+
+
+# ---------------------------------------------------------------- parameter derivatives
+def test_record_replay_bitwise(ctx):
+    """cmb_perturb_record equals cmb_perturb bit for bit and records one entry
+    per accepted step; cmb_perturb_replay of the same tables reproduces the
+    sources bit for bit; replaying another cosmology on these steps runs."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=20, n_tau=100, ell_max=40, k_max=0.1)
+    cosmos = W.perturbed_cosmologies(2, seed=13)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    cap = wl.prec["max_steps"] + 1
+    S = torch.empty((2, len(wl.k), 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((2, len(wl.k)), dtype=torch.int32, device="cuda:0")
+    ns = torch.empty_like(st)
+    H = torch.empty((2, len(wl.k), cap), dtype=torch.float64, device="cuda:0")
+    Hn = torch.empty_like(st)
+    ctx.perturb_record(tabs, S, st, H, Hn, nsteps=ns)
+    S2 = torch.empty_like(S)
+    st2 = torch.empty_like(st)
+    ns2 = torch.empty_like(st)
+    ctx.perturb_replay(tabs, H, Hn, S2, st2, nsteps=ns2)
+    S3 = torch.empty_like(S)
+    ctx.perturb_replay(tabs[::-1], H, Hn, S3, st2)
+    torch.cuda.synchronize()
+    ref = run_gpu(ctx, tabs, 2)
+    assert np.array_equal(S.cpu().numpy(), ref["S"]) and np.all(st.cpu().numpy() == 0)
+    assert np.array_equal(S2.cpu().numpy(), ref["S"])
+    assert np.array_equal(ns2.cpu().numpy(), Hn.cpu().numpy())
+    assert np.all(Hn.cpu().numpy() <= ns.cpu().numpy())
+    assert np.all(np.isfinite(S3.cpu().numpy()))
+
+
+@pytest.mark.parametrize("order", [4, 2])
+def test_jacobian_parity(ctx, order):
+    """cmb_jacobian against the oracle's frozen-step derivatives for two
+    cosmologies (16 modes, l <= 120): every parameter's row to 1e-6 of its
+    largest value; the ln A_s row is C_l itself."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=16, n_tau=150, ell_max=120, k_max=0.1)
+    cosmos = W.perturbed_cosmologies(2, seed=21)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    lm = wl.ell_max
+    C = torch.empty((2, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    J = torch.empty((2, 6, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((2, len(wl.k)), dtype=torch.int32, device="cuda:0")
+    ctx.jacobian(tabs, lm, C, J, st, rel=1e-4, order=order)
+    torch.cuda.synchronize()
+    Cg, Jg = C.cpu().numpy(), J.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    for i, cc in enumerate(cosmos):
+        Co, Jo, sto = O.jacobian(cc, wl.prec, wl.k, wl.n_tau, lm, True, rel=1e-4, order=order)
+        assert np.array_equal(Jg[i, 3], Cg[i])
+        for p in range(6):
+            m = np.max(np.abs(Jo[p][:, 2:]))
+            e = np.max(np.abs(Jg[i, p][:, 2:] - Jo[p][:, 2:])) / m
+            _say("jacobian order", order, "cosmology", i, "param", p, "err", e)
+            assert e < 1e-6, (i, p, e)
+
+
+def test_jacobian_config1(ctx):
+    """Config 1 (400 modes, 2000 times, l <= 2500), fiducial cosmology:
+    cmb_jacobian (five-point, rel 1e-4) against the stored oracle derivatives
+    (tests/golden/make_oracle_reference.py), each row to 1e-6 of its largest
+    value."""
+    import torch
+    import paper_2602_15104_amd as L
+    ref = os.path.join(GOLD, "oracle_config1_jacobian.npy")
+    if not os.path.exists(ref):
+        pytest.skip("stored oracle derivatives absent")
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    lm = wl.ell_max
+    C = torch.empty((1, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    J = torch.empty((1, 6, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((1, len(wl.k)), dtype=torch.int32, device="cuda:0")
+    ctx.jacobian([tab], lm, C, J, st, rel=1e-4, order=4)
+    torch.cuda.synchronize()
+    Jg, Jo = J.cpu().numpy()[0], np.load(ref)
+    assert np.all(st.cpu().numpy() == 0)
+    for p in range(6):
+        m = np.max(np.abs(Jo[p][:, 2:]))
+        e = np.max(np.abs(Jg[p][:, 2:] - Jo[p][:, 2:])) / m
+        _say("config1 jacobian param", p, "err", e)
+        assert e < 1e-6
