@@ -321,10 +321,26 @@ def main():
                                "limber_ms": float(np.median(tl[1:])), "lensed_cl_ms": float(np.median(tz[1:])),
                                "lensed_l_max": l_out, "unlensed_l_max": lmax, "n_mu": n_mu, "batch": B}
         del Dm, Pp, Cll
+        # parameter derivatives: C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s,
+        # tau_reio) for the batch (five-point frozen-step stencil, rel 1e-4;
+        # host table builds of the perturbed cosmologies included)
+        Jc = torch.empty((B, 3, lmax + 1), dtype=torch.float64, device=dev)
+        Jj = torch.empty((B, 6, 3, lmax + 1), dtype=torch.float64, device=dev)
+        Js = torch.empty((B, n_k), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        tj0 = time.perf_counter()
+        ctx.jacobian(tabs, lmax, Jc, Jj, Js, rel=1e-4, order=4)
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - tj0
+        variants["jacobian"] = {"s_per_batch": tj, "gradients_per_s": B / tj, "order": 4, "rel": 1e-4,
+                                "cosmologies_integrated": B * 17, "batch": B,
+                                "modes_not_ok": int((Js != 0).sum().item())}
+        del Jc, Jj, Js
         print(f"[bench] variants: transfer grid {variants['transfer_grid']['ms_per_batch']:.1f} ms, "
               f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
               f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
-              f"{variants['lensing']}", file=sys.stderr, flush=True)
+              f"{variants['lensing']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s",
+              file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic flops / measured duration)
     exs = [t.export() for t in tabs]

@@ -243,6 +243,23 @@ int cmb_perturb_replay(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo,
 int cmb_jacobian(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double rel, int order,
                  double *d_Cl, double *d_J, int32_t *d_status, void *hip_stream);
 
+/* Reverse mode of the spectrum side (the first two steps of the discrete
+ * adjoint): given dL/dC_l for a scalar L of the spectra, the gradient with
+ * respect to the sources, dL/dS, through the transposes of the k quadrature
+ * (eq. c_ell_def) and of the line-of-sight projection (App. B.4):
+ *   G_T = 4 pi w_k P(k)/k (2 gTT Delta_T + gTE Delta_E),
+ *   G_E = 4 pi w_k P(k)/k (gTE Delta_T + 2 gEE Delta_E),
+ *   dL/dS_T0 = w_j sum_l G_T j_l,  dL/dS_T1 = w_j sum_l G_T j_l',
+ *   dL/dS_T2 = w_j sum_l [s_pol G_T (3 j_l'' + j_l)/2 + c_l sqrt(6) G_E j_l/x^2],
+ * with the projection kernel's Bessel recurrence and cut.
+ *   d_Delta: device [n_cosmo][2][ell_max-1][n_k] (cmb_los at these sources);
+ *   d_gCl:   device [n_cosmo][3][ell_max+1] dL/dC_l (TT, TE, EE; l < 2 ignored);
+ *   d_gS:    device [n_cosmo][n_k][3][n_tau] dL/dS.
+ * Asynchronous on hip_stream.  Errors: CMB_E_INVALID, CMB_E_UNSUPPORTED,
+ * CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_spectra_adjoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta,
+                        const double *d_gCl, double *d_gS, void *hip_stream);
+
 /* ---------------------------------------------------------------- lensing */
 /* cmb_perturb plus the matter outputs (App. B.4 eq. PK, App. B.5): either
  * pointer may be NULL, not both.

@@ -115,6 +115,9 @@ def lib():
             L.oracle_matter_pk.restype = ctypes.c_double
             L.oracle_bessel.restype = None
             L.oracle_bessel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_longdouble)]
+            L.oracle_los_adjoint.restype = None
+            L.oracle_los_adjoint.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_int, dp]
             L.oracle_los.restype = None
             L.oracle_los.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int, dp, dp]
@@ -430,6 +433,33 @@ def los(t, S: np.ndarray, ell_max: int, pol: bool, k=None, chi=None, w=None, s_p
     lib().oracle_los(len(k), _dp(k), len(chi), _dp(chi), _dp(w), _dp(S), ell_max, sp, 1 if pol else 0, _dp(DT),
                      _dp(DE))
     return DT, DE
+
+
+def cl_adjoint(k, DT, DE, gC, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: float = 0.05):
+    """Transpose of cl: given gC[3][ell_max+1] = dL/dC_l (TT, TE, EE), the
+    gradients dL/dDelta_T and dL/dDelta_E [l-2][k]:
+      G_T = 4 pi w_k P(k)/k (2 gTT Delta_T + gTE Delta_E),
+      G_E = 4 pi w_k P(k)/k (gTE Delta_T + 2 gEE Delta_E)."""
+    k = np.asarray(k, dtype=np.float64)
+    kl = np.concatenate(([k[0]], k[:-1]))
+    kr = np.concatenate((k[1:], [k[-1]]))
+    f = 4 * math.pi * 0.5 * (kr - kl) * A_s * (k / k_pivot) ** (n_s - 1.0) / k
+    g = np.asarray(gC)[:, 2:ell_max + 1][:, :, None]
+    GT = f * (2 * g[0] * DT + (g[1] * DE if pol else 0.0))
+    GE = f * (g[1] * DT + 2 * g[2] * DE) if pol else np.zeros_like(DT)
+    return GT, GE
+
+
+def los_adjoint(t, GT, GE, ell_max: int, pol: bool, k=None, s_pol: float | None = None):
+    """Transpose of los: dL/dS [k][3][n_tau] from dL/dDelta_T, dL/dDelta_E."""
+    k = np.ascontiguousarray(t.k if k is None else k, dtype=np.float64)
+    chi = np.ascontiguousarray(t.chi_src, dtype=np.float64)
+    w = np.ascontiguousarray(t.w_src, dtype=np.float64)
+    gS = np.zeros((len(k), 3, len(chi)))
+    sp = t.prec["scale_pol"] if s_pol is None else s_pol
+    lib().oracle_los_adjoint(len(k), _dp(k), len(chi), _dp(chi), _dp(w), _dp(np.ascontiguousarray(GT)),
+                             _dp(np.ascontiguousarray(GE)), ell_max, sp, 1 if pol else 0, _dp(gS))
+    return gS
 
 
 def cl(k, DT, DE, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: float = 0.05):

@@ -134,6 +134,53 @@ void oracle_los(int nk, const double *k, int ntau, const double *chi, const doub
     }
 }
 
+/* Transpose of oracle_los: given G_T[l][k], G_E[l][k] (rows l-2), the
+   gradient with respect to the sources, gS[k][3][ntau]:
+     gS_T0 = w_j sum_l G_T j_l,   gS_T1 = w_j sum_l G_T j_l',
+     gS_T2 = w_j sum_l [s_pol G_T (3 j_l'' + j_l)/2 + c_l sqrt(6) G_E j_l/x^2],
+   c_l = sqrt(3 (l+2)!/(8 (l-2)!)) (the E part only with want_E). */
+void oracle_los_adjoint(int nk, const double *k, int ntau, const double *chi, const double *w, const double *GT,
+                        const double *GE, int lmax, double s_pol, int want_E, double *gS) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ik = nk - 1; ik >= 0; --ik) {
+        long double *jl = (long double *)malloc(sizeof(long double) * (lmax + 2));
+        double *g0 = gS + (size_t)ik * 3 * ntau, *g1 = g0 + ntau, *g2 = g1 + ntau;
+        for (int j = 0; j < ntau; ++j) {
+            double x = k[ik] * chi[j];
+            oracle_bessel(lmax + 1, x, jl);
+            long double a0 = 0, a1 = 0, a2 = 0;
+            for (int l = 2; l <= lmax; ++l) {
+                long double J, Jp, Rt2, Je;
+                if (x == 0.0) {
+                    J = 0.0L;
+                    Jp = 0.0L;
+                    Rt2 = (l == 2) ? 0.2L : 0.0L;
+                    Je = (l == 2) ? 1.0L / 15.0L : 0.0L;
+                } else {
+                    long double X = x;
+                    J = jl[l];
+                    Jp = jl[l - 1] - (l + 1.0L) * J / X;
+                    long double Jpp = -2.0L * Jp / X + ((long double)l * (l + 1.0L) / (X * X) - 1.0L) * J;
+                    Rt2 = 0.5L * (3.0L * Jpp + J);
+                    Je = J / (X * X);
+                }
+                long double gt = GT[(size_t)(l - 2) * nk + ik];
+                a0 += gt * J;
+                a1 += gt * Jp;
+                a2 += s_pol * gt * Rt2;
+                if (want_E) {
+                    long double cl = sqrtl(3.0L * (l + 2.0L) * (l + 1.0L) * l * (l - 1.0L) / 8.0L);
+                    a2 += cl * sqrtl(6.0L) * (long double)GE[(size_t)(l - 2) * nk + ik] * Je;
+                }
+            }
+            g0[j] = (double)(w[j] * a0);
+            g1[j] = (double)(w[j] * a1);
+            g2[j] = (double)(w[j] * a2);
+        }
+        free(jl);
+    }
+}
+
 /* Cl[3][lmax+1] (TT, TE, EE; l < 2 zero) from the transfer functions. */
 void oracle_cl(int nk, const double *k, int lmax, const double *DT, const double *DE, int want_E, double A_s,
                double n_s, double k_pivot, double *Cl) {

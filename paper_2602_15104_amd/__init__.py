@@ -45,6 +45,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
            "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_jacobian",
+           "cmb_spectra_adjoint",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -128,6 +129,7 @@ def _declare(lib):
                                        _vp]
     lib.cmb_perturb_replay.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                        _vp]
+    lib.cmb_spectra_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
     lib.cmb_jacobian.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                  _vp, _vp, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
@@ -327,6 +329,12 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_perturb_replay(self._h, hs, len(tabs), _ptr(hist), _ptr(hist_n), int(hist.shape[-1]),
                                        _ptr(S), _ptr(status), _ptr(nsteps), _stream(stream)), "cmb_perturb_replay")
+
+    def spectra_adjoint(self, tabs, ell_max, Delta, gCl, gS, stream=None):
+        """dL/dS from dL/dC_l through the transposed quadrature and projection."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_spectra_adjoint(self._h, hs, len(tabs), int(ell_max), _ptr(Delta), _ptr(gCl), _ptr(gS),
+                                        _stream(stream)), "cmb_spectra_adjoint")
 
     def jacobian(self, tabs, ell_max, Cl, J, status, rel=1e-4, order=4, stream=None):
         """C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s, tau_reio) (cmb_jacobian)."""

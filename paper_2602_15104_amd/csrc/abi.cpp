@@ -1019,6 +1019,37 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     return CMB_OK;
 }
 
+int cmb_spectra_adjoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta,
+                        const double *d_gCl, double *d_gS, void *stream) {
+    if (!c || !d_Delta || !d_gCl || !d_gS) {
+        set_error("cmb_spectra_adjoint: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000) {
+        set_error("ell_max must be in [2, 10000]");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    if (b.n_tau > cmbhip::los_max_tau()) {
+        set_error("n_tau above the line-of-sight kernel's limit");
+        return CMB_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    rc = grow(c, &c->ws_buf, &c->ws_cap, sizeof(double) * (size_t)n_cosmo * 2 * (ell_max - 1) * b.n_k, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_spectra_adjoint(c->d_tabs, n_cosmo, b.n_k, b.n_tau, ell_max, b.polar, b.s_pol, d_Delta, d_gCl,
+                                        (double *)c->ws_buf, d_gS, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
 int cmb_lensed_cl(cmb_ctx *c, int n_cosmo, int L, const double *d_Cl, const double *d_Clpp, int ell_max, int n_mu,
                   double *d_Cll, void *stream) {
     if (!c || !d_Cl || !d_Clpp || !d_Cll || n_cosmo < 1 || n_cosmo > 65535) {

@@ -97,6 +97,11 @@ int launch_los(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_ma
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
               void *stream);
 int los_max_tau();
+// reverse mode of K3 then K2: dL/dC_l -> G = dL/dDelta (workspace, Delta's
+// layout) -> dL/dS in the sources' layout
+int launch_spectra_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E,
+                           double s_pol, const double *d_Delta, const double *d_gC, double *d_G, double *d_gS,
+                           void *stream);
 // K3 with an output stride per cosmology and optionally the ln(k/k_pivot)
 // weight (dC/dn_s); finite-difference stencils and replay status merging
 int launch_cl_ex(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,

@@ -194,7 +194,190 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
     }
 }
 
+// Transposes (reverse-mode gradients of the spectra with respect to the
+// sources).  K3^T, one thread per (cosmology, l, k):
+//   G_T = 4 pi w_k P(k)/k (2 gTT Delta_T + gTE Delta_E),
+//   G_E = 4 pi w_k P(k)/k (gTE Delta_T + 2 gEE Delta_E).
+// K2^T, the decomposition of los_kernel (one 256-lane workgroup per
+// (cosmology, k), lanes own output times, the same Bessel seeding and walk in
+// l), each lane summing over l for its own times:
+//   gS_T0 = w sum_l G_T j_l,  gS_T1 = w sum_l G_T j_l',
+//   gS_T2 = w sum_l [s_pol G_T (3 j_l'' + j_l)/2 + c_l sqrt(6) G_E j_l/x^2],
+// with j' = (l/x) j_l - j_{l+1} and (3j''+j)/2 = -(3/x) j' + (3l(l+1)/(2x^2) - 1) j.
+// No cross-lane sums: every output is written by the lane that owns it.
+__global__ void __launch_bounds__(256) cl_adj_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                     int ell_max, int want_E, const double *__restrict__ Delta,
+                                                     const double *__restrict__ gC, double *__restrict__ G) {
+    const int nl = ell_max - 1;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)n_cosmo * nl * n_k) return;
+    const int ik = (int)(t % n_k);
+    const int li = (int)((t / n_k) % nl);
+    const int c = (int)(t / ((long)nl * n_k));
+    const DevTab &tb = tabs[c];
+    const double ki = tb.k[ik];
+    const double kl = ik > 0 ? tb.k[ik - 1] : ki, kr = ik + 1 < n_k ? tb.k[ik + 1] : ki;
+    const double f = 4.0 * 3.14159265358979323846 * 0.5 * (kr - kl) * tb.A_s * pow(ki / tb.k_pivot, tb.n_s - 1.0) / ki;
+    const double *D = Delta + (size_t)c * 2 * nl * n_k;
+    const double dT = D[(size_t)li * n_k + ik], dE = D[(size_t)(nl + li) * n_k + ik];
+    const double *g = gC + (size_t)c * 3 * (ell_max + 1);
+    const int l = li + 2;
+    const double gtt = g[l], gte = want_E ? g[(ell_max + 1) + l] : 0.0, gee = want_E ? g[2 * (ell_max + 1) + l] : 0.0;
+    double *o = G + (size_t)c * 2 * nl * n_k;
+    o[(size_t)li * n_k + ik] = f * (2.0 * gtt * dT + gte * dE);
+    o[(size_t)(nl + li) * n_k + ik] = want_E ? f * (gte * dT + 2.0 * gee * dE) : 0.0;
+}
+
+template <int M>
+__global__ void __launch_bounds__(BLOCK) los_adj_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                        int n_tau, int ell_max, int want_E, double s_pol,
+                                                        const double *__restrict__ G, double *__restrict__ gS) {
+    __shared__ int s_lstart;
+    const int tid = threadIdx.x;
+    const int c = blockIdx.x % n_cosmo;
+    const int ik = n_k - 1 - (int)(blockIdx.x / n_cosmo);
+    const DevTab &tb = tabs[c];
+    const double k = tb.k[ik];
+    const int nl = ell_max - 1;
+    const double *GT = G + (size_t)c * 2 * nl * n_k;
+    const double *GE = GT + (size_t)nl * n_k;
+    double *g0 = gS + ((size_t)c * n_k + ik) * 3 * n_tau, *g1 = g0 + n_tau, *g2 = g1 + n_tau;
+    const int ltop = ell_max + 1;
+    double rx[M], jl[M], jp[M], a0[M], a1[M], a2[M];
+    int lact[M];
+    bool zero[M];
+    int my_lmax = 1;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int j = tid + m * BLOCK;
+        lact[m] = 1;
+        zero[m] = false;
+        rx[m] = jl[m] = jp[m] = a0[m] = a1[m] = a2[m] = 0.0;
+        if (j >= n_tau) continue;
+        const double x = k * tb.chi_src[j];
+        if (x == 0.0) {
+            zero[m] = true;  // only l = 2 contributes: (3j''+j)/2 = 1/5, j/x^2 = 1/15
+            continue;
+        }
+        const double ix = 1.0 / x;
+        rx[m] = ix;
+        double sx, cx;
+        sincos(x, &sx, &cx);
+        const double j0 = sx * ix, j1 = (sx * ix - cx) * ix;
+        if (x >= ltop + 32) {
+            double a = j0, b = j1;
+            for (int l = 1; l < ltop; ++l) {
+                const double nb = (2.0 * l + 1.0) * ix * b - a;
+                a = b;
+                b = nb;
+            }
+            jp[m] = b;
+            jl[m] = a;
+            lact[m] = ell_max;
+        } else {
+            const int lc = ell_cut_rule(x);
+            const int la = lc < ell_max ? lc : ell_max;
+            const int ls = ell_start_rule(x);
+            double hi = 0.0, lo = 1e-200, rp = 0.0, rl = 0.0;
+            for (int l = ls; l > 0; --l) {
+                const double nlo = (2.0 * l + 1.0) * ix * lo - hi;
+                hi = lo;
+                lo = nlo;
+                if (l - 1 == la) {
+                    rp = hi;
+                    rl = lo;
+                }
+                if (fabs(lo) > 1e250) {
+                    lo *= 1e-250;
+                    hi *= 1e-250;
+                    rp *= 1e-250;
+                    rl *= 1e-250;
+                }
+            }
+            const double sc = (fabs(j0) >= fabs(j1)) ? j0 / lo : j1 / hi;
+            jp[m] = rp * sc;
+            jl[m] = rl * sc;
+            lact[m] = la;
+        }
+        my_lmax = lact[m] > my_lmax ? lact[m] : my_lmax;
+    }
+    if (tid == 0) s_lstart = 1;
+    __syncthreads();
+    atomicMax(&s_lstart, my_lmax);
+    __syncthreads();
+    const int lstart = s_lstart;
+    for (int l = lstart; l >= 2; --l) {
+        const double fl = (double)l;
+        const double gt = GT[(size_t)(l - 2) * n_k + ik];
+        const double ge = want_E ? GE[(size_t)(l - 2) * n_k + ik] * sqrt(3.0 * (fl + 2.0) * (fl + 1.0) * fl * (fl - 1.0) / 8.0) *
+                                       2.449489742783178098
+                                 : 0.0;
+        const double c21 = 2.0 * fl + 1.0, q = fl * (fl + 1.0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (l <= lact[m]) {
+                const double j = jl[m], j1 = jp[m], ix = rx[m];
+                const double d = fl * ix * j - j1;  // j_l'
+                a0[m] = fma(gt, j, a0[m]);
+                a1[m] = fma(gt, d, a1[m]);
+                const double r2 = fma(-3.0 * ix, d, (1.5 * q * ix * ix - 1.0) * j);
+                a2[m] = fma(s_pol * gt, r2, fma(ge, j * ix * ix, a2[m]));
+                jp[m] = j;
+                jl[m] = fma(c21 * ix, j, -j1);
+            }
+        }
+    }
+    const double gt2 = GT[ik];
+    const double ge2 = want_E ? GE[ik] * sqrt(3.0 * 4.0 * 3.0 * 2.0 * 1.0 / 8.0) * 2.449489742783178098 : 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int j = tid + m * BLOCK;
+        if (j >= n_tau) continue;
+        if (zero[m]) a2[m] = s_pol * gt2 * 0.2 + ge2 / 15.0;
+        const double w = tb.w_src[j];
+        g0[j] = w * a0[m];
+        g1[j] = w * a1[m];
+        g2[j] = w * a2[m];
+    }
+}
+
 }  // namespace
+
+int launch_spectra_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E,
+                           double s_pol, const double *d_Delta, const double *d_gC, double *d_G, double *d_gS,
+                           void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const long n = (long)n_cosmo * (ell_max - 1) * n_k;
+    hipLaunchKernelGGL(cl_adj_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_tabs, n_cosmo, n_k, ell_max,
+                       want_E, d_Delta, d_gC, d_G);
+    dim3 grid((unsigned)(n_cosmo * n_k)), block(BLOCK);
+    const int M = (n_tau + BLOCK - 1) / BLOCK;
+    if (M <= 1)
+        hipLaunchKernelGGL(los_adj_kernel<1>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol,
+                           d_G, d_gS);
+    else if (M <= 2)
+        hipLaunchKernelGGL(los_adj_kernel<2>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol,
+                           d_G, d_gS);
+    else if (M <= 4)
+        hipLaunchKernelGGL(los_adj_kernel<4>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol,
+                           d_G, d_gS);
+    else if (M <= 8)
+        hipLaunchKernelGGL(los_adj_kernel<8>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol,
+                           d_G, d_gS);
+    else if (M <= 16)
+        hipLaunchKernelGGL(los_adj_kernel<16>, grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, ell_max, want_E, s_pol,
+                           d_G, d_gS);
+    else {
+        set_error("n_tau too large for the line-of-sight kernel");
+        return CMB_E_UNSUPPORTED;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("adjoint launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
 
 int los_max_tau() { return BLOCK * 16; }
 

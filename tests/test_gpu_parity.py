@@ -905,3 +905,65 @@ def test_jacobian_config1(ctx):
         e = np.max(np.abs(Jg[p][:, 2:] - Jo[p][:, 2:])) / m
         _say("config1 jacobian param", p, "err", e)
         assert e < 1e-6
+
+
+# ---------------------------------------------------------------- spectrum-side adjoint
+def test_spectra_adjoint_parity(ctx):
+    """cmb_spectra_adjoint on seeded sources and seeded dL/dC_l (40 modes to
+    k = 0.1, 300 output times, l <= 150): against the oracle's transposed
+    quadrature and projection, per (k, type) to 1e-9 of its largest value."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=40, n_tau=300, ell_max=150, k_max=0.1)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    rng = np.random.Generator(np.random.PCG64(31))
+    S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
+    gC = rng.standard_normal((1, 3, wl.ell_max + 1))
+    dS = torch.tensor(S, device="cuda:0")
+    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    gS = torch.empty_like(dS)
+    ctx.los([tab], wl.ell_max, dS, D)
+    ctx.spectra_adjoint([tab], wl.ell_max, D, torch.tensor(gC, device="cuda:0"), gS)
+    torch.cuda.synchronize()
+    DT, DE = O.los(t_or, S[0], wl.ell_max, True)
+    GT, GE = O.cl_adjoint(t_or.k, DT, DE, gC[0], wl.ell_max, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
+    go = O.los_adjoint(t_or, GT, GE, wl.ell_max, True)
+    e = src_err(gS.cpu().numpy()[0], go)
+    _say("spectra adjoint err", e)
+    assert e <= 1e-9
+
+
+def test_spectra_adjoint_dot_product_config1(ctx):
+    """Config 1 size (400 modes, 2000 times, l <= 2500): for the quadratic
+    map S -> L = sum gC C_l(S), <dL/dS, V> equals the central difference of L
+    along a seeded direction V (exact for a quadratic up to rounding)."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    S = torch.tensor(g["S"], device="cuda:0")
+    rng = np.random.Generator(np.random.PCG64(37))
+    V = torch.tensor(rng.standard_normal(g["S"].shape) * np.abs(g["S"]).max(axis=-1, keepdims=True), device="cuda:0")
+    gC = torch.tensor(rng.standard_normal((1, 3, wl.ell_max + 1)) / np.maximum(np.abs(g["Cl"]), 1e-30),
+                      device="cuda:0")
+    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
+
+    def loss(Sx):
+        ctx.los([tab], wl.ell_max, Sx, D)
+        ctx.cl([tab], wl.ell_max, D, C)
+        torch.cuda.synchronize()
+        return float((gC[:, :, 2:] * C[:, :, 2:]).sum().item())
+
+    e = 1e-3
+    fd = (loss(S + e * V) - loss(S - e * V)) / (2 * e)
+    ctx.los([tab], wl.ell_max, S, D)
+    gS = torch.empty_like(S)
+    ctx.spectra_adjoint([tab], wl.ell_max, D, gC, gS)
+    torch.cuda.synchronize()
+    ad = float((gS * V).sum().item())
+    _say("config1 adjoint dot product", ad, fd, ad / fd - 1)
+    assert abs(ad / fd - 1) < 1e-8

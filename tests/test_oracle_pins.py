@@ -967,3 +967,24 @@ def test_dcl_dtau_reio_high_l():
     ree = J[5, 2, 250:301] / C[2, 250:301]
     rtt = J[5, 0, 200:301] / C[0, 200:301]
     assert abs(np.mean(ree) + 2) < 0.05 and abs(np.mean(rtt) + 2) < 0.2
+
+
+def test_spectra_adjoint_dot_product(tab12):
+    """The oracle's transposed quadrature and projection: <dL/dS, V> equals
+    the central difference of L = sum gC C_l(S) along V (exact for this
+    quadratic map up to rounding)."""
+    t = tab12
+    rng = np.random.default_rng(0)
+    S = rng.standard_normal((len(t.k), 3, len(t.chi_src)))
+    gC = rng.standard_normal((3, 21))
+
+    def L(Sx):
+        DT, DE = O.los(t, Sx, 20, True)
+        return float(np.sum(gC[:, 2:] * O.cl(t.k, DT, DE, 20, True, 2e-9, 0.96)[:, 2:]))
+
+    DT, DE = O.los(t, S, 20, True)
+    GT, GE = O.cl_adjoint(t.k, DT, DE, gC, 20, True, 2e-9, 0.96)
+    gS = O.los_adjoint(t, GT, GE, 20, True)
+    V = rng.standard_normal(S.shape)
+    fd = (L(S + 1e-3 * V) - L(S - 1e-3 * V)) / 2e-3
+    assert abs(np.sum(gS * V) / fd - 1) < 1e-11
