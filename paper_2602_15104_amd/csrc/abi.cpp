@@ -849,7 +849,7 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
         if (rc) return rc;
         ns = (int32_t *)c->st_buf;
     }
-    return cmbhip::launch_perturb2(dt, n, b.n_k, b.n_tau, b.prec, d_S, d_status, ns, nullptr, nullptr, s);
+    return cmbhip::launch_perturb2(dt, n, b.n_k, b.n_tau, b.prec, d_S, d_status, ns, nullptr, nullptr, s, true);
 }
 
 extern "C" {

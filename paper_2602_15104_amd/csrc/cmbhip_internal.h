@@ -85,7 +85,7 @@ int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const 
                    double *d_S, int *d_status, int *d_nsteps, void *stream);
 size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream);
+                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream, bool hist = false);
 bool perturb2_supported(const DevPrec &p);
 // work list of (cosmology, mode) pairs; outputs through each DevTab's S/status/nsteps
 struct WorkItem {

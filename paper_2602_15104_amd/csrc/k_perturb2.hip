@@ -474,7 +474,7 @@ __device__ inline double aff(const Aff &a, double H, double E, double P) { retur
 // Sout/status/nsteps, largest k first) or the work list items[n_items] of
 // (cosmology, mode) pairs, each cosmology with its own grids and its own
 // output arrays in its DevTab (ragged batches of the serving runtime).
-template <int R, bool MNU>
+template <int R, bool MNU, bool HIST>
 __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
                                                       int n_tau_all, DevPrec p, int G, double *__restrict__ Sout,
                                                       int *__restrict__ status, int *__restrict__ nsteps,
@@ -526,9 +526,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     // step history: replay the accepted step sizes hin[1..hin_n] from the
     // start hin[0] without error control, or record this mode's into hout
     // (same start and sizes: the same sequence of times, bit for bit)
-    const double *hin = tb.hist_in ? tb.hist_in + (size_t)ik * tb.hist_cap : nullptr;
+    // (compiled in only for the history instances: the plain ones carry no
+    // pointers or branches for it)
+    const double *hin = (HIST && tb.hist_in) ? tb.hist_in + (size_t)ik * tb.hist_cap : nullptr;
     const int hin_n = hin ? min(tb.hist_in_n[ik], tb.hist_cap - 1) : 0;
-    double *hout = tb.hist_out ? tb.hist_out + (size_t)ik * tb.hist_cap : nullptr;
+    double *hout = (HIST && tb.hist_out) ? tb.hist_out + (size_t)ik * tb.hist_cap : nullptr;
     const double t0 = hin ? hin[0] : tb.lna_start[ik];
     const bool small = k < tb.k_split;
     const double rtol = small ? tb.rtol_small : tb.rtol_large;
@@ -1148,7 +1150,7 @@ bool perturb2_supported(const DevPrec &p) {
 
 static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
                                int *d_status, int *d_nsteps, const int2 *d_items, int n_items, double *d_Pk,
-                               double *d_Dm, void *stream) {
+                               double *d_Dm, bool hist, void *stream) {
     int R, G;
     group_shape(p, R, G);
     if (G > 64) {
@@ -1163,18 +1165,19 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
     size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     const bool mnu = p.nq > 0;
-    if (R == 2 && !mnu)
-        hipLaunchKernelGGL((perturb2_kernel<2, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
-    else if (R == 2)
-        hipLaunchKernelGGL((perturb2_kernel<2, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
-    else if (!mnu)
-        hipLaunchKernelGGL((perturb2_kernel<5, false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
-    else
-        hipLaunchKernelGGL((perturb2_kernel<5, true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S,
-                           d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm);
+#define CMB_K1_LAUNCH(R_, M_, H_)                                                                                 \
+    hipLaunchKernelGGL((perturb2_kernel<R_, M_, H_>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, \
+                       d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm)
+    if (R == 2 && !mnu) {
+        if (hist) CMB_K1_LAUNCH(2, false, true); else CMB_K1_LAUNCH(2, false, false);
+    } else if (R == 2) {
+        if (hist) CMB_K1_LAUNCH(2, true, true); else CMB_K1_LAUNCH(2, true, false);
+    } else if (!mnu) {
+        if (hist) CMB_K1_LAUNCH(5, false, true); else CMB_K1_LAUNCH(5, false, false);
+    } else {
+        if (hist) CMB_K1_LAUNCH(5, true, true); else CMB_K1_LAUNCH(5, true, false);
+    }
+#undef CMB_K1_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("perturb2 launch: ") + hipGetErrorString(e));
@@ -1184,15 +1187,15 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
 }
 
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
-                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream) {
-    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, d_Pk, d_Dm,
+                    int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream, bool hist) {
+    return launch_perturb2_any(d_tabs, n_cosmo, n_k, n_tau, p, d_S, d_status, d_nsteps, nullptr, 0, d_Pk, d_Dm, hist,
                                stream);
 }
 
 int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_items, const DevPrec &p, void *stream) {
     static_assert(sizeof(WorkItem) == sizeof(int2), "work item layout");
     return launch_perturb2_any(d_tabs, 0, 0, 0, p, nullptr, nullptr, nullptr, reinterpret_cast<const int2 *>(d_items),
-                               n_items, nullptr, nullptr, stream);
+                               n_items, nullptr, nullptr, false, stream);
 }
 
 }  // namespace cmbhip
