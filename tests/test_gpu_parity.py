@@ -967,3 +967,40 @@ def test_spectra_adjoint_dot_product_config1(ctx):
     ad = float((gS * V).sum().item())
     _say("config1 adjoint dot product", ad, fd, ad / fd - 1)
     assert abs(ad / fd - 1) < 1e-8
+
+
+def test_new_entry_points_reject_bad_arguments(ctx):
+    """Argument errors of the lensing, derivative and variant entry points
+    come back as CmbError (CMB_E_INVALID) without touching the device."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=8, n_tau=40, ell_max=20)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    dev = "cuda:0"
+    Cl = torch.zeros((1, 3, 101), dtype=torch.float64, device=dev)
+    P = torch.zeros((1, 101), dtype=torch.float64, device=dev)
+    out = torch.zeros((1, 4, 101), dtype=torch.float64, device=dev)
+    with pytest.raises(L.CmbError):
+        ctx.lensed_cl(Cl, P, 101, out, n_mu=200)  # ell_max above L
+    with pytest.raises(L.CmbError):
+        ctx.lensed_cl(Cl, P, 50, out, n_mu=1)  # too few nodes
+    J = torch.zeros((1, 6, 3, 21), dtype=torch.float64, device=dev)
+    C = torch.zeros((1, 3, 21), dtype=torch.float64, device=dev)
+    st = torch.zeros((1, 8), dtype=torch.int32, device=dev)
+    for rel, order in ((0.0, 4), (0.5, 4), (1e-4, 3)):
+        with pytest.raises(L.CmbError):
+            ctx.jacobian([tab], 20, C, J, st, rel=rel, order=order)
+    c_z = dict(wl.cosmo)
+    c_z["tau_reio"] = float("nan")
+    c_z["z_reio"] = 8.0
+    tz = L.Tables(c_z, wl.prec, wl.k, wl.n_tau)
+    with pytest.raises(L.CmbError):
+        ctx.jacobian([tz], 20, C, J, st)  # derivatives need tau_reio
+    S = torch.zeros((1, 8, 3, 40), dtype=torch.float64, device=dev)
+    H = torch.zeros((1, 8, 10), dtype=torch.float64, device=dev)  # capacity below max_steps + 1
+    with pytest.raises(L.CmbError):
+        ctx.perturb_record([tab], S, st, H, st)
+    with pytest.raises(L.CmbError):
+        ctx.lensing_potential([tab], 1, torch.zeros((1, 8, 40), dtype=torch.float64, device=dev), P)
+    with pytest.raises(L.CmbError):
+        ctx.bessel3_table(0)
