@@ -734,21 +734,18 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         pc[q] = pb[(3 - q) * STR + F_CC];
                         pp[q] = pb[(3 - q) * STR + F_CP];
                     }
-                    for (int j0 = cn - 2; j0 >= 4; j0 -= 4) {
+                    // one block: rows j0 .. j0-3 from (cr, cc, cp) while the next
+                    // block's values load into (nr, nc, np); two blocks per trip with
+                    // the buffers alternating, so no register copies between blocks
+                    auto up_block = [&](const double(&cr)[4], const double(&cc)[4], const double(&cp)[4],
+                                        double(&nr)[4], double(&nc)[4], double(&np)[4], int j0) {
                         double *cbk = m.rec(j0 - 3 + cb);
-                        double cr[4], cc[4], cp[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            cr[q] = pr[q];
-                            cc[q] = pc[q];
-                            cp[q] = pp[q];
-                        }
                         const double *nb = cbk - 4 * STR;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            pr[q] = nb[(3 - q) * STR + F_RY];
-                            pc[q] = nb[(3 - q) * STR + F_CC];
-                            pp[q] = nb[(3 - q) * STR + F_CP];
+                            nr[q] = nb[(3 - q) * STR + F_RY];
+                            nc[q] = nb[(3 - q) * STR + F_CC];
+                            np[q] = nb[(3 - q) * STR + F_CP];
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
@@ -766,7 +763,14 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         M1 *= f;
                         M2 *= f;
                         S1 *= f;
+                    };
+                    double qr[4], qc[4], qp[4];
+                    int j0 = cn - 2;
+                    for (; j0 >= 8; j0 -= 8) {
+                        up_block(pr, pc, pp, qr, qc, qp, j0);
+                        up_block(qr, qc, qp, pr, pc, pp, j0 - 4);
                     }
+                    if (j0 >= 4) up_block(pr, pc, pp, qr, qc, qp, j0);
                 }
                 // top rows 3 .. 0 carry the couplings; the row below is held as
                 // 1/pivot (ibp), eliminated rhs / pivot (rpi) and subdiagonal (alb)
@@ -953,19 +957,16 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     }
                 }
                 double *const spare = m.rec(-1);
-                for (int j0 = 4; j0 < cn; j0 += 4) {
-                    double cu[4], cv[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        cu[q] = pu[q];
-                        cv[q] = pv[q];
-                    }
+                // one block from (cu, cv) while the next loads into (nu, nv); two
+                // blocks per trip with alternating buffers
+                auto down_block = [&](const double(&cu)[4], const double(&cv)[4], double(&nu)[4], double(&nv)[4],
+                                      int j0) {
                     double *cbk = m.rec(cb + j0);
                     const double *nb = cbk + 4 * STR;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        pu[q] = nb[q * STR + F_U];
-                        pv[q] = nb[q * STR + F_V];
+                        nu[q] = nb[q * STR + F_U];
+                        nv[q] = nb[q * STR + F_V];
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -973,7 +974,14 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         double *dst = (j0 + q < cn) ? cbk + q * STR : spare;
                         dst[F_RY] = yprev;
                     }
+                };
+                double qu[4], qv[4];
+                int j0 = 4;
+                for (; j0 + 4 < cn; j0 += 8) {
+                    down_block(pu, pv, qu, qv, j0);
+                    down_block(qu, qv, pu, pv, j0 + 4);
                 }
+                if (j0 < cn) down_block(pu, pv, qu, qv, j0);
             }
             wsync();
             // (E) row lanes: K = (Y - R)/g
