@@ -321,6 +321,20 @@ def main():
                                "limber_ms": float(np.median(tl[1:])), "lensed_cl_ms": float(np.median(tz[1:])),
                                "lensed_l_max": l_out, "unlensed_l_max": lmax, "n_mu": n_mu, "batch": B}
         del Dm, Pp, Cll
+        # reverse mode of the spectrum side: dL/dS from dL/dC_l (transposed k
+        # quadrature and projection) for the batch, at the batch's Delta
+        gCl = torch.ones((B, 3, lmax + 1), dtype=torch.float64, device=dev)
+        gS = torch.empty_like(S)
+        ta = []
+        for r in range(3):
+            e0.record()
+            ctx.spectra_adjoint(tabs, lmax, D, gCl, gS)
+            e1.record()
+            torch.cuda.synchronize()
+            ta.append(e0.elapsed_time(e1))
+        variants["spectra_adjoint"] = {"ms_per_batch": float(np.median(ta[1:])), "batch": B,
+                                       "los_ms": float(np.mean(kt["los"]))}
+        del gCl, gS
         # parameter derivatives: C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s,
         # tau_reio) for the batch (five-point frozen-step stencil, rel 1e-4;
         # host table builds of the perturbed cosmologies included)
@@ -339,7 +353,8 @@ def main():
         print(f"[bench] variants: transfer grid {variants['transfer_grid']['ms_per_batch']:.1f} ms, "
               f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
               f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
-              f"{variants['lensing']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s",
+              f"{variants['lensing']}, spectra adjoint {variants['spectra_adjoint']['ms_per_batch']:.1f} ms, "
+              f"jacobian {variants['jacobian']['s_per_batch']:.2f} s",
               file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic flops / measured duration)

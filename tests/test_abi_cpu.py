@@ -201,3 +201,18 @@ def test_transfer_kgrid_errors(lib, args):
     k_max_cmb rule leaves empty."""
     with pytest.raises(lib.CmbError):
         lib.transfer_kgrid(*args)
+
+
+def test_autograd_parameter_mapping():
+    """cl_of_params' theta columns map onto the cosmology: ln A_s becomes A_s,
+    tau_reio replaces z_reio, every other entry of the base is kept."""
+    from paper_2602_15104_amd import autograd as AG
+    base = W.fiducial()
+    base["z_reio"] = 7.7
+    c = AG._cosmo_at(base, [0.7, 0.0225, 0.118, math.log(2.0e-9), 0.96, 0.06])
+    assert AG.PARAMS == ("h", "omega_b", "omega_cdm", "ln_A_s", "n_s", "tau_reio")
+    assert c["h"] == 0.7 and c["omega_b"] == 0.0225 and c["omega_cdm"] == 0.118 and c["n_s"] == 0.96
+    assert abs(c["A_s"] / 2.0e-9 - 1) < 1e-15 and c["tau_reio"] == 0.06 and math.isnan(c["z_reio"])
+    assert all(c[q] == base[q] for q in base if q not in ("h", "omega_b", "omega_cdm", "A_s", "n_s", "tau_reio",
+                                                            "z_reio") and not (isinstance(base[q], float)
+                                                                               and math.isnan(base[q])))
