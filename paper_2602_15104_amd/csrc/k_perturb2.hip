@@ -837,17 +837,16 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             // (D0) row lanes turn the continuants of the generic rows into the
             // downward recurrence y_j = U_j - V_j y_{j-1}:
             // U_j = T_j / N_j = S_j / (u M_j),  V_j = a_j N_{j+1} / N_j = -CA_j M_{j+1} / M_j
+            // (selects rather than a branch per row, so the rows' loads and
+            // reciprocals overlap; other rows keep their values)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double *q = m.rec(gl * R + r);
-                const double ca = q[F_CA];
-                if (ca != 0.0) {
-                    const double iM = rcp(q[F_M]);
-                    const double u = q[F_U] * iM;
-                    const double v = -ca * q[F_MN] * iM;
-                    q[F_U] = u;
-                    q[F_V] = v;
-                }
+                const double ca = q[F_CA], fm = q[F_M], fu = q[F_U], fmn = q[F_MN], fv = q[F_V];
+                const double iM = rcp(fm);
+                const bool gen = ca != 0.0;
+                q[F_U] = gen ? fu * iM : fu;
+                q[F_V] = gen ? -ca * fmn * iM : fv;
             }
             // (C) couplings: 3x3 (2x2 without polarisation) system, one lane
             if (gl == 0) {
@@ -891,34 +890,22 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     Aff G0 = T(1, 0), G2 = T(1, 2);
                     Aff eP{2.0 * F3.v0 + G0.v0 + G2.v0, 2.0 * F3.vH + G0.vH + G2.vH, 2.0 * F3.vE + G0.vE + G2.vE,
                            2.0 * F3.vP + G0.vP + G2.vP};
-                    double mm[3][4] = {{1.0 - eH.vH, -eH.vE, -eH.vP, eH.v0},
-                                       {-eE.vH, 1.0 - eE.vE, -eE.vP, eE.v0},
-                                       {-eP.vH, -eP.vE, 1.0 - eP.vP, eP.v0}};
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) {
-                        int piv = cc;
-#pragma unroll
-                        for (int rr = cc + 1; rr < 3; ++rr)
-                            if (fabs(mm[rr][cc]) > fabs(mm[piv][cc])) piv = rr;
-                        if (piv != cc) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                double tt = mm[cc][q];
-                                mm[cc][q] = mm[piv][q];
-                                mm[piv][q] = tt;
-                            }
-                        }
-                        const double ipv = rcp(mm[cc][cc]);
-#pragma unroll
-                        for (int rr = cc + 1; rr < 3; ++rr) {
-                            double f = mm[rr][cc] * ipv;
-#pragma unroll
-                            for (int q = cc; q < 4; ++q) mm[rr][q] -= f * mm[cc][q];
-                        }
-                    }
-                    P = mm[2][3] * rcp(mm[2][2]);
-                    E = (mm[1][3] - mm[1][2] * P) * rcp(mm[1][1]);
-                    H = (mm[0][3] - mm[0][1] * E - mm[0][2] * P) * rcp(mm[0][0]);
+                    // (I - coupling) (h', eta', Pi) = rhs by the adjugate: nine
+                    // cofactors, one reciprocal of the determinant (a shorter
+                    // dependence chain on this one lane than elimination)
+                    const double a00 = 1.0 - eH.vH, a01 = -eH.vE, a02 = -eH.vP;
+                    const double a10 = -eE.vH, a11 = 1.0 - eE.vE, a12 = -eE.vP;
+                    const double a20 = -eP.vH, a21 = -eP.vE, a22 = 1.0 - eP.vP;
+                    const double b0 = eH.v0, b1 = eE.v0, b2 = eP.v0;
+                    const double c00 = fma(a11, a22, -a12 * a21), c01 = fma(a12, a20, -a10 * a22);
+                    const double c02 = fma(a10, a21, -a11 * a20), c10 = fma(a02, a21, -a01 * a22);
+                    const double c11 = fma(a00, a22, -a02 * a20), c12 = fma(a01, a20, -a00 * a21);
+                    const double c20 = fma(a01, a12, -a02 * a11), c21 = fma(a02, a10, -a00 * a12);
+                    const double c22 = fma(a00, a11, -a01 * a10);
+                    const double idet = rcp(fma(a00, c00, fma(a01, c01, a02 * c02)));
+                    H = fma(c00, b0, fma(c10, b1, c20 * b2)) * idet;
+                    E = fma(c01, b0, fma(c11, b1, c21 * b2)) * idet;
+                    P = fma(c02, b0, fma(c12, b1, c22 * b2)) * idet;
                 } else {
                     double a11 = 1.0 - eH.vH, a12 = -eH.vE, a21 = -eE.vH, a22 = 1.0 - eE.vE;
                     const double idet = rcp(a11 * a22 - a12 * a21);
