@@ -772,18 +772,25 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     }
                     if (j0 >= 4) up_block(pr, pc, pp, qr, qc, qp, j0);
                 }
-                // top rows 3 .. 0 carry the couplings; the row below is held as
-                // 1/pivot (ibp), eliminated rhs / pivot (rpi) and subdiagonal (alb)
-                double ibp = 0.0, rpi = 0.0, alb = 0.0;
+                // top rows 3 .. 0 carry the couplings.  Their elimination goes on
+                // in continuant form, with no division on the dependent path: in
+                // the common scale of these rows (N_j / u^(cn-4)),
+                //   Q_j = be_j Q_{j+1} - ga_j b_{j+1} Q_{j+2},  Z_j = z_j Q_{j+1} - ga_j Z_{j+1}
+                // for z the rhs and each coupling column, where the generic row 4
+                // enters as Q_4 = M_4, b_4 Q_5 = -CA_4 M_5, Z_4 = S_4 / u (zero for
+                // the couplings).  Then pivot_j = Q_j / Q_{j+1} and z'_j / pivot_j =
+                // Z_j / Q_j: the four reciprocals are independent of one another.
+                // (A four-row chain starts from Q_4 = 1, Q_5 = 0, Z_4 = 0.)
+                double Q1 = 1.0, Q2 = 0.0, bq1 = 0.0, Z0 = 0.0, ZH = 0.0, ZE = 0.0, ZP = 0.0;
                 if (cn >= 5) {
                     const double *r4 = m.rec(cb + 4);
-                    const double iM = rcp(r4[F_M]);
-                    ibp = r4[F_MN] * iM * iu;
-                    rpi = r4[F_U] * iM;
-                    alb = -u * r4[F_CA];
+                    Q1 = r4[F_M];
+                    Q2 = r4[F_MN];
+                    bq1 = -r4[F_CA];
+                    Z0 = r4[F_U];
                 }
-                double eH = 0.0, eE = 0.0, eP = 0.0;
-                double ib[4], r0[4], rH[4], rE[4], rP[4], al[4];
+                double Qs[5], z0[4], zH[4], zE[4], zP[4], al[4];
+                Qs[4] = Q1;
 #pragma unroll
                 for (int j = 3; j >= 0; --j) {
                     const RowCo cc = top_coef<MNU>(ty, j, L, s, p, vq, dl_ch);
@@ -797,40 +804,38 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         xH = fma(cl, g * (2.0 / 3.0), xH);
                         rho = fma(cl, m.ry(L.rDG), rho);
                     }
-                    // (for a four-row chain the row below j = 3 is absent: ibp = rpi = 0)
-                    const double mm = ga * ibp;
-                    be = fma(-mm, alb, be);
-                    rho = fma(-ga, rpi, rho);
-                    xH = fma(-mm, eH, xH);
-                    xE = fma(-mm, eE, xE);
-                    xP = fma(-mm, eP, xP);
-                    ibp = rcp(be);
-                    rpi = rho * ibp;
-                    eH = xH;
-                    eE = xE;
-                    eP = xP;
-                    alb = -g * cc.a;
-                    ib[j] = ibp;
-                    r0[j] = rho;
-                    rH[j] = xH;
-                    rE[j] = xE;
-                    rP[j] = xP;
-                    al[j] = alb;
+                    const double Q = fma(be, Q1, -(ga * bq1) * Q2);
+                    Z0 = fma(-ga, Z0, rho * Q1);
+                    ZH = fma(-ga, ZH, xH * Q1);
+                    ZE = fma(-ga, ZE, xE * Q1);
+                    ZP = fma(-ga, ZP, xP * Q1);
+                    Q2 = Q1;
+                    Q1 = Q;
+                    bq1 = -g * cc.a;
+                    Qs[j] = Q;
+                    z0[j] = Z0;
+                    zH[j] = ZH;
+                    zE[j] = ZE;
+                    zP[j] = ZP;
+                    al[j] = bq1;
                 }
+                // y_j = (z'_j - b_j y_{j-1} - x'_j . (h', eta', Pi)) / pivot_j as affine maps
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    double v0 = r0[j], vH = -rH[j], vE = -rE[j], vP = -rP[j];
+                    const double iQ = rcp(Qs[j]);
+                    double v0 = z0[j] * iQ, vH = -zH[j] * iQ, vE = -zE[j] * iQ, vP = -zP[j] * iQ;
                     if (j > 0) {
-                        v0 -= al[j] * top[j - 1].v0;
-                        vH -= al[j] * top[j - 1].vH;
-                        vE -= al[j] * top[j - 1].vE;
-                        vP -= al[j] * top[j - 1].vP;
+                        const double c = al[j] * (Qs[j + 1] * iQ);
+                        v0 = fma(-c, top[j - 1].v0, v0);
+                        vH = fma(-c, top[j - 1].vH, vH);
+                        vE = fma(-c, top[j - 1].vE, vE);
+                        vP = fma(-c, top[j - 1].vP, vP);
                     }
-                    top[j] = Aff{v0 * ib[j], vH * ib[j], vE * ib[j], vP * ib[j]};
-                    m.AX[4 + 16 * ch + 4 * j + 0] = top[j].v0;
-                    m.AX[4 + 16 * ch + 4 * j + 1] = top[j].vH;
-                    m.AX[4 + 16 * ch + 4 * j + 2] = top[j].vE;
-                    m.AX[4 + 16 * ch + 4 * j + 3] = top[j].vP;
+                    top[j] = Aff{v0, vH, vE, vP};
+                    m.AX[4 + 16 * ch + 4 * j + 0] = v0;
+                    m.AX[4 + 16 * ch + 4 * j + 1] = vH;
+                    m.AX[4 + 16 * ch + 4 * j + 2] = vE;
+                    m.AX[4 + 16 * ch + 4 * j + 3] = vP;
                 }
             }
             wsync();
