@@ -281,7 +281,11 @@ __device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p, 
 // time-independent multipliers of the row, the scaled continuants of the
 // upward sweep and the coefficients of the downward one.
 constexpr int STR = 10;
-constexpr int F_RY = 0, F_CC = 1, F_CP = 2, F_CA = 3, F_M = 4, F_MN = 5, F_U = 6, F_V = 7, F_CD = 8;
+constexpr int F_RY = 0, F_CC = 1, F_CP = 2, F_CA = 3, F_M = 4, F_MN = 5, F_U = 6, F_V = 7, F_CD = 8, F_X = 9;
+// record fields free between steps, one per output time of a batch of dense
+// outputs (the next step's stages rewrite them before reading them)
+constexpr int OUT_SLOTS = 6;
+__device__ inline int out_slot(int b) { return b == 0 ? F_RY : (b < 5 ? F_M + (b - 1) : F_X); }
 constexpr int PADR = 8;  // spare records before row 0 and after the last row
 
 struct Slab {
@@ -410,14 +414,14 @@ __device__ inline RowCo top_coef(int ty, int j, const Lay &L, const Bk &s, const
 // Massive-neutrino moments of a state held in the records (App. B.3 eq.
 // mnu_sum): delta rho, (rho + p) theta and (rho + p) sigma, in the units of rt.
 __device__ inline void ncdm_moments(const Slab &m, const Lay &L, const Bk &s, const DevTab &tb, double k,
-                                    double &drho, double &rpt, double &rps) {
+                                    double &drho, double &rpt, double &rps, int fld = F_RY) {
     drho = rpt = rps = 0.0;
     for (int i = 0; i < L.nQ; ++i) {
         const double q = tb.q[i], e = eps_of(q, s.am), w = s.pn4 * tb.W[i];
         const int b = L.bM + i * L.nPs;
-        drho += w * e * m.ry(b);
-        rpt += w * k * q * m.ry(b + 1);
-        rps += w * (2.0 / 3.0) * q * q / e * m.ry(b + 2);
+        drho += w * e * m.rec(b)[fld];
+        rpt += w * k * q * m.rec(b + 1)[fld];
+        rps += w * (2.0 / 3.0) * q * q / e * m.rec(b + 2)[fld];
     }
 }
 
@@ -1012,22 +1016,34 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             if (hout && gl == 0 && na + 1 < tb.hist_cap) hout[1 + na] = h;
             ++na;
             double hh = tn - t;
+            // the output times inside this step, in batches of up to OUT_SLOTS:
+            // the interpolated rows of output b go to record field out_slot(b)
+            // and lane b of the group evaluates its sources (per output the
+            // same arithmetic as one output at a time)
+            const int nb_max = G < OUT_SLOTS ? G : OUT_SLOTS;
             while (jo < n_tau && lo[jo] <= tn) {
-                double th = hh > 0.0 ? (lo[jo] - t) / hh : 1.0;
-                double th2 = th * th, th3 = th2 * th;
-                double h00 = 2.0 * th3 - 3.0 * th2 + 1.0, h10 = th3 - 2.0 * th2 + th;
-                double h01 = -2.0 * th3 + 3.0 * th2, h11 = th3 - th2;
+                int nb = 1;
+                while (nb < nb_max && jo + nb < n_tau && lo[jo + nb] <= tn) ++nb;
+                for (int b = 0; b < nb; ++b) {
+                    const int fld = out_slot(b);
+                    double th = hh > 0.0 ? (lo[jo + b] - t) / hh : 1.0;
+                    double th2 = th * th, th3 = th2 * th;
+                    double h00 = 2.0 * th3 - 3.0 * th2 + 1.0, h10 = th3 - 2.0 * th2 + th;
+                    double h01 = -2.0 * th3 + 3.0 * th2, h11 = th3 - th2;
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    m.ry(gl * R + r) = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
+                    for (int r = 0; r < R; ++r)
+                        m.rec(gl * R + r)[fld] =
+                            h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
+                }
                 wsync();
-                if (gl == 0) {
+                if (gl < nb) {
+                    const int jl = jo + gl, fld = out_slot(gl);
                     Bk so;
-                    bk_at<MNU>(tb, p, k, lo[jo], so);
-                    auto y = [&](int r) { return m.ry(r); };
+                    bk_at<MNU>(tb, p, k, lo[jl], so);
+                    auto y = [&](int r) { return m.rec(r)[fld]; };
                     double k2 = k * k;
                     double drho = 0.0, rpt = 0.0, rpsn = 0.0;
-                    if (MNU) ncdm_moments(m, L, so, tb, k, drho, rpt, rpsn);
+                    if (MNU) ncdm_moments(m, L, so, tb, k, drho, rpt, rpsn, fld);
                     double Hh = so.cH1 * y(L.rETA) + so.cH2 * (so.rc * y(L.rDC) + so.rb * y(0) + so.rg * y(L.rDG) +
                                                                so.rur * y(L.bV) + drho);
                     double Ee = so.cE *
@@ -1042,12 +1058,12 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     double alphap = -2.0 * alpha + (y(L.rETA) - 4.5 * so.a * so.a * rps / k2) * so.invHc;
                     double Pi = 2.0 * y(3) + (L.nG ? y(L.bG) + y(L.bG + 2) : 0.0);
                     double eta = y(L.rETA);
-                    So[jo] = p.sw * gv * (0.25 * y(L.rDG) + Hc * alphap) +
+                    So[jl] = p.sw * gv * (0.25 * y(L.rDG) + Hc * alphap) +
                              p.isw * (gv * (eta - Hc * alphap - 2.0 * Hc * alpha) +
                                       2.0 * Hc * ek * (Ee - so.Hcp * alpha - Hc * alphap)) +
                              p.dop * Hc * (gv * (tbp / k2 + alphap) + gp * (y(1) / k2 + alpha));
-                    So[n_tau + jo] = p.isw * ek * k * (Hc * alphap + 2.0 * Hc * alpha - eta);
-                    So[2 * n_tau + jo] = gv * Pi * 0.125;
+                    So[n_tau + jl] = p.isw * ek * k * (Hc * alphap + 2.0 * Hc * alpha - eta);
+                    So[2 * n_tau + jl] = gv * Pi * 0.125;
                     if (Dmo) {
                         // sum rho_i delta_i / sum rho_i over CDM, baryons and massive
                         // nu, scaled by a^3 (massive nu: a^-4 eps against a^-3)
@@ -1060,11 +1076,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                                 den += w1;
                             }
                         }
-                        Dmo[jo] = num / den;
+                        Dmo[jl] = num / den;
                     }
                 }
                 wsync();
-                ++jo;
+                jo += nb;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
