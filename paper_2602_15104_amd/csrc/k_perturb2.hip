@@ -54,12 +54,26 @@ __device__ inline double rcp(double b) {
     return fma(x, fma(e, e, e), x);
 }
 
-// Exchange point between the lanes of a wavefront: wait for this wave's LDS
-// operations to complete; the memory clobber keeps the compiler from moving
-// any load or store across it.  (A workgroup is one wavefront and LDS
-// operations of a wavefront execute in order, so no s_barrier is needed and
-// groups of a wavefront may sit in different branches.)
-__device__ inline void wsync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Exchange point between the lanes of a wavefront.  A workgroup is one
+// wavefront, and the LDS executes a wavefront's DS instructions in the order
+// they are issued, so a value one lane stores is seen by any lane's later
+// load; what must not happen is the compiler moving a load or store across
+// the exchange (it reasons per lane and would see no dependence).  The
+// memory clobber forbids that and emits no instruction: no s_barrier, and no
+// wait for outstanding stores (each load still waits for its own data).
+// Groups of a wavefront may therefore sit in different branches.
+__device__ inline void wsync() { __asm__ volatile("" ::: "memory"); }
+
+// v of another lane of the same 16-lane row, selected by a DPP control word
+// (both 32-bit halves moved; every lane of the row is active wherever this is
+// used, since a group's lanes take the same branches)
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 struct Bk {  // background and per-stage constants at one ln a
     double a, Hc, Hcp, rg, rur, rc, rb;
@@ -610,8 +624,16 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     };
     full_rhs(w.y, w.K[0], s);
 
+    // sum over the group's lanes, the same bits in every lane (each step adds
+    // two partial sums that every lane of the pair forms in the same order):
+    // DPP permutes inside a 16-lane row (swap neighbours, swap pairs, mirror
+    // the half row, mirror the row), lane shuffles only for groups above 16
     auto group_sum = [&](double v) {
-        for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+        v += dpp_f64<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+        v += dpp_f64<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+        if (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+        if (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+        for (int o = 16; o < G; o <<= 1) v += __shfl_xor(v, o, G);
         return v;
     };
     auto rms = [&](const double *v, const double *y1, const double *y2) {
