@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -914,45 +915,55 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     const int nb = n_cosmo, nm = order == 4 ? 4 : 2, n_k = b.n_k, n_tau = b.n_tau;
     const double mult[4] = {1.0, -1.0, 2.0, -2.0};
     const int slot[4] = {0, 1, 2, 5};  // h, omega_b, omega_cdm, tau_reio in (h, wb, wc, ln A_s, n_s, tau)
-    // perturbed tables on host threads: pert[p][m nb + cb]
+    // perturbed tables on host threads, pert[p][m nb + cb], built in parameter
+    // order while the device records the base steps and replays the
+    // parameters already built (each replay waits only for its own tables)
     std::vector<std::vector<std::unique_ptr<cmb_tables>>> pert(4);
+    for (int p = 0; p < 4; ++p) pert[p].resize(nm * nb);
     std::vector<int> brc(4 * nm * nb, CMB_OK);
-    {
-        std::vector<std::pair<int, int>> jobs;
-        for (int p = 0; p < 4; ++p) {
-            pert[p].resize(nm * nb);
-            for (int j = 0; j < nm * nb; ++j) jobs.emplace_back(p, j);
+    std::vector<int> built(4, 0);
+    std::mutex bmu;
+    std::condition_variable bcv;
+    std::atomic<size_t> next{0};
+    const size_t n_jobs = (size_t)4 * nm * nb;
+    auto work = [&]() {
+        for (size_t q; (q = next.fetch_add(1)) < n_jobs;) {
+            const int p = (int)(q / ((size_t)nm * nb)), j = (int)(q % ((size_t)nm * nb)), m = j / nb, cb = j % nb;
+            const cmbhip::Tables &t0 = tabs[cb]->t;
+            cmb_cosmo cc = t0.cosmo;
+            double *v = p == 0 ? &cc.h : p == 1 ? &cc.omega_b : p == 2 ? &cc.omega_cdm : &cc.tau_reio;
+            *v *= 1.0 + mult[m] * rel;
+            std::unique_ptr<cmb_tables> t(new (std::nothrow) cmb_tables);
+            int r = t ? CMB_OK : CMB_E_NOMEM;
+            try {
+                if (r == CMB_OK) r = cmbhip::build_tables(cc, t0.prec, t0.k.data(), n_k, n_tau, t->t);
+            } catch (const std::exception &) {
+                r = CMB_E_INVALID;
+            }
+            if (r == CMB_OK) t->t.uid = cmbhip::g_uid.fetch_add(1);
+            brc[(size_t)p * nm * nb + j] = r;
+            pert[p][j] = std::move(t);
+            std::lock_guard<std::mutex> bl(bmu);
+            if (++built[p] == nm * nb) bcv.notify_all();
         }
-        std::atomic<size_t> next{0};
-        auto work = [&]() {
-            for (size_t q; (q = next.fetch_add(1)) < jobs.size();) {
-                const int p = jobs[q].first, j = jobs[q].second, m = j / nb, cb = j % nb;
-                const cmbhip::Tables &t0 = tabs[cb]->t;
-                cmb_cosmo cc = t0.cosmo;
-                double *v = p == 0 ? &cc.h : p == 1 ? &cc.omega_b : p == 2 ? &cc.omega_cdm : &cc.tau_reio;
-                *v *= 1.0 + mult[m] * rel;
-                std::unique_ptr<cmb_tables> t(new (std::nothrow) cmb_tables);
-                int r = t ? CMB_OK : CMB_E_NOMEM;
-                try {
-                    if (r == CMB_OK) r = cmbhip::build_tables(cc, t0.prec, t0.k.data(), n_k, n_tau, t->t);
-                } catch (const std::exception &) {
-                    r = CMB_E_INVALID;
-                }
-                if (r == CMB_OK) t->t.uid = cmbhip::g_uid.fetch_add(1);
-                brc[(size_t)p * nm * nb + j] = r;
-                pert[p][j] = std::move(t);
-            }
-        };
-        unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    };
+    struct Joiner {  // every worker is joined on every return path
         std::vector<std::thread> th;
-        for (unsigned i = 0; i < nth; ++i) th.emplace_back(work);
-        for (auto &x : th) x.join();
-        for (int r : brc)
-            if (r != CMB_OK) {
-                set_error("cmb_jacobian: a perturbed table build failed");
-                return r;
-            }
+        ~Joiner() {
+            for (auto &x : th) x.join();
+        }
+    } workers;
+    {
+        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        for (unsigned i = 0; i < nth; ++i) workers.th.emplace_back(work);
     }
+    auto wait_built = [&](int p) {
+        std::unique_lock<std::mutex> bl(bmu);
+        bcv.wait(bl, [&] { return built[p] == nm * nb; });
+        for (int j = 0; j < nm * nb; ++j)
+            if (brc[(size_t)p * nm * nb + j] != CMB_OK) return brc[(size_t)p * nm * nb + j];
+        return (int)CMB_OK;
+    };
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
@@ -990,6 +1001,12 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     if (rc) return rc;
     // the four table parameters: replays of the base steps at the stencil points
     for (int p = 0; p < 4; ++p) {
+        rc = wait_built(p);
+        if (rc) {
+            set_error("cmb_jacobian: a perturbed table build failed");
+            hipStreamSynchronize(s);  // launches already queued use tables freed on return
+            return rc;
+        }
         std::vector<const cmb_tables *> run(n_run);
         for (size_t j = 0; j < n_run; ++j) run[j] = pert[p][j].get();
         rc = perturb_hist(c, run.data(), (int)n_run, base, hist, hn, cap, true, S, rst, nullptr, s);
