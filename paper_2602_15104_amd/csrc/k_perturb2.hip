@@ -492,9 +492,13 @@ __device__ inline double aff(const Aff &a, double H, double E, double P) { retur
 // Sout/status/nsteps, largest k first) or the work list items[n_items] of
 // (cosmology, mode) pairs, each cosmology with its own grids and its own
 // output arrays in its DevTab (ragged batches of the serving runtime).
-template <int R, bool MNU, bool HIST>
+// RN: rows per lane of the groups whose error-norm summation order the
+// instance keeps (RN = R, or RN = 5 for a whole wavefront per mode with R = 2
+// standing in for groups of Gn lanes with five rows each).
+template <int R, bool MNU, bool HIST, int RN>
 __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
-                                                      int n_tau_all, DevPrec p, int G, double *__restrict__ Sout,
+                                                      int n_tau_all, DevPrec p, int G, int Gn,
+                                                      double *__restrict__ Sout,
                                                       int *__restrict__ status, int *__restrict__ nsteps,
                                                       const int2 *__restrict__ items, int n_items,
                                                       double *__restrict__ Pk, double *__restrict__ Dm) {
@@ -628,26 +632,50 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     // two partial sums that every lane of the pair forms in the same order):
     // DPP permutes inside a 16-lane row (swap neighbours, swap pairs, mirror
     // the half row, mirror the row), lane shuffles only for groups above 16
-    auto group_sum = [&](double v) {
+    auto group_sum = [&](double v, int w) {
         v += dpp_f64<0xB1>(v);  // quad_perm [1, 0, 3, 2]
         v += dpp_f64<0x4E>(v);  // quad_perm [2, 3, 0, 1]
-        if (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
-        if (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
-        for (int o = 16; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+        if (w >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+        if (w >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+        for (int o = 16; o < w; o <<= 1) v += __shfl_xor(v, o, w);
         return v;
     };
+    // RMS error norm.  In a wide launch (a whole wavefront per mode, RN != R)
+    // the rows' terms are summed in the order of the narrow groups of Gn
+    // lanes with RN rows each, so a mode takes the same steps, bit for bit,
+    // in either shape (and so alone or in any batch).
     auto rms = [&](const double *v, const double *y1, const double *y2) {
+        auto term = [&](int r) {
+            double yy = fabs(y1[r]);
+            if (y2) yy = fmax(yy, fabs(y2[r]));
+            return v[r] * rcp(fma(rtol, yy, atol));
+        };
         double acc = 0.0;
+        if constexpr (RN == R) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (gl * R + r < N) {
-                double yy = fabs(y1[r]);
-                if (y2) yy = fmax(yy, fabs(y2[r]));
-                double q = v[r] * rcp(fma(rtol, yy, atol));
-                acc += q * q;
+            for (int r = 0; r < R; ++r) {
+                if (gl * R + r < N) {
+                    const double q = term(r);
+                    acc = fma(q, q, acc);
+                }
             }
+            acc = group_sum(acc, G);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) m.rec(gl * R + r)[F_X] = term(r);
+            wsync();
+            if (gl < Gn)
+                for (int r = 0; r < RN; ++r)
+                    if (RN * gl + r < N) {
+                        const double q = m.rec(RN * gl + r)[F_X];
+                        acc = fma(q, q, acc);
+                    }
+            acc = group_sum(acc, Gn);  // lanes from Gn on carry values nobody uses
+            const long long b = __double_as_longlong(acc);
+            acc = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(b >> 32), 0) << 32) |
+                                       (unsigned int)__builtin_amdgcn_readlane((int)(b & 0xffffffff), 0));
         }
-        return sqrt(group_sum(acc) / N);
+        return sqrt(acc / N);
     };
 
     int jo = 0;
@@ -1179,6 +1207,22 @@ static void group_shape(const DevPrec &p, int &R, int &G) {
     while (G < need) G <<= 1;
 }
 
+// Few modes (one wavefront each still fits the 1024 wavefront slots of the
+// chip at one per SIMD): a whole wavefront per mode, two rows per lane, so a
+// step's row-parallel work is shorter.  Per row, per chain and in the error
+// norm the arithmetic is that of the narrow groups, so results are the same
+// bits in either shape.
+static void wide_shape(const DevPrec &p, long n_sys, int &R, int &G) {
+    if (R != 5 || n_sys > 1024 || p.nq > 0) return;
+    const int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + p.nq * (p.nq > 0 ? p.lq + 1 : 0) + 3;
+    const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
+    int need = (N + 1) / 2;
+    if (need < nch) need = nch;
+    if (need > 64) return;
+    R = 2;
+    G = 64;
+}
+
 bool perturb2_supported(const DevPrec &p) {
     int R, G;
     group_shape(p, R, G);
@@ -1195,26 +1239,32 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
         set_error("hierarchy too large for the cooperative perturbation kernel");
         return CMB_E_UNSUPPORTED;
     }
-    int spw = 64 / G;
     long n_sys = d_items ? (long)n_items : (long)n_cosmo * n_k;
     if (n_sys <= 0) return CMB_OK;
+    const int Gn = G;  // the narrow group, whose error-norm order every shape keeps
+    wide_shape(p, n_sys, R, G);
+    int spw = 64 / G;
     dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
     const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
     size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     const bool mnu = p.nq > 0;
-#define CMB_K1_LAUNCH(R_, M_, H_)                                                                                 \
-    hipLaunchKernelGGL((perturb2_kernel<R_, M_, H_>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, d_S, \
-                       d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm)
-    if (R == 2 && !mnu) {
-        if (hist) CMB_K1_LAUNCH(2, false, true); else CMB_K1_LAUNCH(2, false, false);
+#define CMB_K1_LAUNCH(R_, M_, H_, RN_)                                                                  \
+    hipLaunchKernelGGL((perturb2_kernel<R_, M_, H_, RN_>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, \
+                       Gn, d_S, d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm)
+#define CMB_K1_LAUNCH3(R_, M_, H_) CMB_K1_LAUNCH(R_, M_, H_, R_)
+    if (G != Gn) {  // wide groups (massless hierarchies only) in the order of narrow groups of five rows
+        if (hist) CMB_K1_LAUNCH(2, false, true, 5); else CMB_K1_LAUNCH(2, false, false, 5);
+    } else if (R == 2 && !mnu) {
+        if (hist) CMB_K1_LAUNCH3(2, false, true); else CMB_K1_LAUNCH3(2, false, false);
     } else if (R == 2) {
-        if (hist) CMB_K1_LAUNCH(2, true, true); else CMB_K1_LAUNCH(2, true, false);
+        if (hist) CMB_K1_LAUNCH3(2, true, true); else CMB_K1_LAUNCH3(2, true, false);
     } else if (!mnu) {
-        if (hist) CMB_K1_LAUNCH(5, false, true); else CMB_K1_LAUNCH(5, false, false);
+        if (hist) CMB_K1_LAUNCH3(5, false, true); else CMB_K1_LAUNCH3(5, false, false);
     } else {
-        if (hist) CMB_K1_LAUNCH(5, true, true); else CMB_K1_LAUNCH(5, true, false);
+        if (hist) CMB_K1_LAUNCH3(5, true, true); else CMB_K1_LAUNCH3(5, true, false);
     }
+#undef CMB_K1_LAUNCH3
 #undef CMB_K1_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
