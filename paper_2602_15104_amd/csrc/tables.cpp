@@ -325,9 +325,13 @@ static double tau_reion(const Model &m, double zre) {
     return acc * hz / 3.0;
 }
 
+// Root of f in [lo, hi] (f(lo) <= 0 < f(hi)) by bisection to the last bit.  Once
+// the midpoint rounds onto an end point every further halving returns that
+// same point, so the search stops there.
 static double bisect(const std::function<double(double)> &f, double lo, double hi) {
     for (int it = 0; it < 100; ++it) {
         double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) return mid;
         if (f(mid) > 0.0)
             hi = mid;
         else
