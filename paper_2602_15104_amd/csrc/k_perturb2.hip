@@ -493,8 +493,8 @@ __device__ inline double aff(const Aff &a, double H, double E, double P) { retur
 // (cosmology, mode) pairs, each cosmology with its own grids and its own
 // output arrays in its DevTab (ragged batches of the serving runtime).
 // RN: rows per lane of the groups whose error-norm summation order the
-// instance keeps (RN = R, or RN = 5 for a whole wavefront per mode with R = 2
-// standing in for groups of Gn lanes with five rows each).
+// instance keeps (RN = R, or RN = 5 for wider groups with R = 2 or 3 standing
+// in for groups of Gn lanes with five rows each).
 template <int R, bool MNU, bool HIST, int RN>
 __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
                                                       int n_tau_all, DevPrec p, int G, int Gn,
@@ -671,9 +671,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         acc = fma(q, q, acc);
                     }
             acc = group_sum(acc, Gn);  // lanes from Gn on carry values nobody uses
-            const long long b = __double_as_longlong(acc);
-            acc = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(b >> 32), 0) << 32) |
-                                       (unsigned int)__builtin_amdgcn_readlane((int)(b & 0xffffffff), 0));
+            acc = __shfl(acc, 0, G);   // the group's first lane to the group
         }
         return sqrt(acc / N);
     };
@@ -1207,20 +1205,24 @@ static void group_shape(const DevPrec &p, int &R, int &G) {
     while (G < need) G <<= 1;
 }
 
-// Few modes (one wavefront each still fits the 1024 wavefront slots of the
-// chip at one per SIMD): a whole wavefront per mode, two rows per lane, so a
-// step's row-parallel work is shorter.  Per row, per chain and in the error
-// norm the arithmetic is that of the narrow groups, so results are the same
-// bits in either shape.
+// Few modes: wider groups while the launch still fits one round of the
+// chip's 1024 wavefront slots (one wavefront per SIMD), so a step's
+// row-parallel work is shorter: a whole wavefront per mode with two rows per
+// lane up to 1024 modes, 32 lanes with three rows up to 2048.  Per row, per
+// chain and in the error norm the arithmetic is that of the narrow groups,
+// so results are the same bits in every shape.  (Massless hierarchies whose
+// narrow groups have five rows per lane.)
 static void wide_shape(const DevPrec &p, long n_sys, int &R, int &G) {
-    if (R != 5 || n_sys > 1024 || p.nq > 0) return;
-    const int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + p.nq * (p.nq > 0 ? p.lq + 1 : 0) + 3;
-    const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
-    int need = (N + 1) / 2;
-    if (need < nch) need = nch;
-    if (need > 64) return;
-    R = 2;
-    G = 64;
+    if (R != 5 || p.nq > 0) return;
+    const int N = (p.lg + 2) + (p.lp > 0 ? p.lp + 1 : 0) + (p.ln + 1) + 3;
+    const int nch = p.lp > 0 ? 3 : 2;
+    if (n_sys <= 1024 && (N + 1) / 2 <= 64 && nch <= 64) {
+        R = 2;
+        G = 64;
+    } else if (n_sys <= 2048 && (N + 2) / 3 <= 32 && nch <= 32) {
+        R = 3;
+        G = 32;
+    }
 }
 
 bool perturb2_supported(const DevPrec &p) {
@@ -1253,8 +1255,10 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
     hipLaunchKernelGGL((perturb2_kernel<R_, M_, H_, RN_>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, \
                        Gn, d_S, d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm)
 #define CMB_K1_LAUNCH3(R_, M_, H_) CMB_K1_LAUNCH(R_, M_, H_, R_)
-    if (G != Gn) {  // wide groups (massless hierarchies only) in the order of narrow groups of five rows
+    if (G != Gn && R == 2) {  // wide groups (massless hierarchies) in the order of narrow groups of five rows
         if (hist) CMB_K1_LAUNCH(2, false, true, 5); else CMB_K1_LAUNCH(2, false, false, 5);
+    } else if (G != Gn) {
+        if (hist) CMB_K1_LAUNCH(3, false, true, 5); else CMB_K1_LAUNCH(3, false, false, 5);
     } else if (R == 2 && !mnu) {
         if (hist) CMB_K1_LAUNCH3(2, false, true); else CMB_K1_LAUNCH3(2, false, false);
     } else if (R == 2) {

@@ -193,23 +193,25 @@ def test_batch_invariance_and_determinism(ctx):
 
 
 def test_launch_shape_invariance(ctx):
-    """Config-1 hierarchy (79 rows) on 40 modes to k = 0.2: one cosmology alone
-    runs with a whole wavefront per mode, the same cosmology among 30 (1200
-    modes) with 16-lane groups; sources, step counts and C_ell are the same
-    bits either way."""
+    """Config-1 hierarchy (79 rows) on 40 modes to k = 0.2, one cosmology in
+    three launch shapes: alone (a whole wavefront per mode), among 30
+    cosmologies (1200 modes: 32-lane groups) and among 60 (2400 modes: 16-lane
+    groups); sources, step counts and C_ell are the same bits in all three."""
     import paper_2602_15104_amd as L
     wl = W.config1()
     k = W.log_grid(1e-4, 0.2, 40)
-    cosmos = W.perturbed_cosmologies(30, seed=19)
+    cosmos = W.perturbed_cosmologies(60, seed=19)
     for cc in cosmos:
         cc["N_nu_massless"] = 3.0
     tabs = [L.Tables(cc, wl.prec, k, 200) for cc in cosmos]
     a = run_gpu(ctx, [tabs[11]], 300)
-    b = run_gpu(ctx, tabs, 300)
-    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
-    assert np.array_equal(a["nsteps"][0], b["nsteps"][11])
-    assert np.array_equal(a["S"][0], b["S"][11])
-    assert np.array_equal(a["Cl"][0], b["Cl"][11])
+    b = run_gpu(ctx, tabs[:30], 300)
+    c = run_gpu(ctx, tabs, 300)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0) and np.all(c["status"] == 0)
+    for o in (b, c):
+        assert np.array_equal(a["nsteps"][0], o["nsteps"][11])
+        assert np.array_equal(a["S"][0], o["S"][11])
+        assert np.array_equal(a["Cl"][0], o["Cl"][11])
 
 
 def test_batched_parity_box_cosmologies(ctx):
