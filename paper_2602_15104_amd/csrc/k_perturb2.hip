@@ -6,7 +6,9 @@
 // equations of App. B.3 and App. C), mapped differently onto the hardware:
 //
 //  * a mode's state rows are spread over a group of G lanes (G = 16 for the
-//    79-row TT/TE/EE hierarchy, R = 5 rows per lane); every working vector
+//    79-row TT/TE/EE hierarchy, R = 5 rows per lane, in full launches; 64
+//    lanes with 2 rows or 32 with 3 when the launch has few modes, with the
+//    same arithmetic); every working vector
 //    (state, six stage derivatives, new state, stage right-hand side) lives
 //    in registers of the lane that owns the row, so no workspace traffic;
 //  * row-parallel work (stage right-hand sides, matrix entries of
@@ -18,9 +20,10 @@
 //    stream, so they advance in lock-step;
 //  * one lane solves the 3x3 system of the couplings h', eta', Pi, then the
 //    chain lanes substitute downwards and the row lanes pick up their rows;
-//  * a wavefront holds 64/G modes; lanes exchange data through LDS with
-//    wave-scope fences (a workgroup is one wavefront), so modes of one
-//    wavefront may branch independently.
+//  * a wavefront holds 64/G modes; lanes exchange data through LDS at
+//    compiler-only fences (a workgroup is one wavefront, whose DS
+//    instructions the LDS executes in order), so modes of one wavefront may
+//    branch independently.
 #include <hip/hip_runtime.h>
 
 #include "cmbhip_internal.h"
