@@ -334,7 +334,22 @@ def main():
             ta.append(e0.elapsed_time(e1))
         variants["spectra_adjoint"] = {"ms_per_batch": float(np.median(ta[1:])), "batch": B,
                                        "los_ms": float(np.mean(kt["los"]))}
-        del gCl, gS
+        # transposed source functions for one cosmology (dL/dy at every output
+        # time and state row: n_k n_tau rows doubles written)
+        rows = tabs[0].state_rows()
+        gY = torch.empty((1, n_k, n_tau, rows), dtype=torch.float64, device=dev)
+        tsa = []
+        for r in range(3):
+            e0.record()
+            ctx.sources_adjoint(tabs[:1], gS[:1], gY)
+            e1.record()
+            torch.cuda.synchronize()
+            tsa.append(e0.elapsed_time(e1))
+        t_sa = float(np.median(tsa[1:]))
+        by = 8.0 * n_k * n_tau * (rows + 3)
+        variants["sources_adjoint"] = {"ms_per_cosmology": t_sa, "bytes": by, "GB_per_s": by / (t_sa * 1e6),
+                                       "rows": rows}
+        del gCl, gS, gY
         # parameter derivatives: C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s,
         # tau_reio) for the batch (five-point frozen-step stencil, rel 1e-4;
         # host table builds of the perturbed cosmologies included)
@@ -354,6 +369,7 @@ def main():
               f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
               f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
               f"{variants['lensing']}, spectra adjoint {variants['spectra_adjoint']['ms_per_batch']:.1f} ms, "
+              f"sources adjoint {variants['sources_adjoint']['ms_per_cosmology']:.2f} ms per cosmology, "
               f"jacobian {variants['jacobian']['s_per_batch']:.2f} s",
               file=sys.stderr, flush=True)
 

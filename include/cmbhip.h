@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-#define CMB_ABI_VERSION 2
+#define CMB_ABI_VERSION 3
 
 /* call-level return codes */
 enum {
@@ -259,6 +259,34 @@ int cmb_jacobian(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int e
  * CMB_E_DEVICE, CMB_E_NOMEM. */
 int cmb_spectra_adjoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta,
                         const double *d_gCl, double *d_gS, void *hip_stream);
+
+/* Rows of one mode's perturbation state for these tables' hierarchy, in the
+ * order the perturbation kernel keeps them (the row index of
+ * cmb_sources_adjoint's output):
+ *   [delta_b, theta_b, theta_g, F_g2 .. F_g,lmax]     ell_gamma + 2 rows
+ *   [G_0 .. G_lpol]                                     ell_pol + 1 (none if 0)
+ *   [delta_nu, theta_nu, F_nu2 .. F_nu,lmax]          ell_nu + 1
+ *   [Psi_0 .. Psi_lncdm] per momentum node             n_q (ell_ncdm + 1)
+ *   [delta_c, eta, delta_g]                             3
+ * (F_2 = 2 sigma, photon and neutrino; App. B.3 and App. C variables).
+ * Returns that count, or CMB_E_INVALID for a NULL table. */
+int cmb_state_rows(const cmb_tables *tab);
+
+/* Reverse mode of the source functions (App. B.4, eq. source_functions),
+ * the third step of the spectrum's reverse sweep after cmb_spectra_adjoint:
+ * at a fixed output time the sources are linear in the state (theta_b'
+ * through the right-hand side's baryon row, h' and eta' through the Einstein
+ * constraints), so dL/dy = (dS/dy)^T dL/dS at every output time.
+ *   d_gS: device [n_cosmo][n_k][3][n_tau]  dL/dS_T0, dL/dS_T1, dL/dS_T2
+ *         (cmb_spectra_adjoint's layout);
+ *   d_gY: device [n_cosmo][n_k][n_tau][cmb_state_rows] dL/dy, rows as
+ *         cmb_state_rows lists; zero before each mode's start time (no
+ *         sources there) and in the rows the sources do not read.
+ * n_cosmo * n_k * n_tau * rows doubles (506 MB for one config-1 cosmology):
+ * callers with large batches pass them in parts.  Asynchronous on
+ * hip_stream.  Errors: CMB_E_INVALID, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_sources_adjoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, const double *d_gS, double *d_gY,
+                        void *hip_stream);
 
 /* ---------------------------------------------------------------- lensing */
 /* cmb_perturb plus the matter outputs (App. B.4 eq. PK, App. B.5): either

@@ -108,6 +108,9 @@ def lib():
                                                  dp, dp, ctypes.c_int, dp, dp, dp, ip, ip, ip]
             L.oracle_delta_m.restype = ctypes.c_double
             L.oracle_delta_m.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, dp]
+            L.oracle_sources_state.restype = None
+            L.oracle_sources_state.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double,
+                                               ctypes.c_double, dp, dp]
             L.oracle_state_size.restype = ctypes.c_int
             L.oracle_state_size.argtypes = [ctypes.POINTER(_OPrec)]
             L.oracle_matter_pk.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, dp,
@@ -230,6 +233,69 @@ def delta_m_of_state(t, lna: float, y) -> float:
     p = make_prec(t.prec, len(t.bg.q))
     y = np.ascontiguousarray(y, dtype=np.float64)
     return lib().oracle_delta_m(ctypes.byref(b.tab), ctypes.byref(p), float(lna), _dp(y))
+
+
+def sources_of_state(t, k: float, lna: float, y) -> np.ndarray:
+    """S_T0, S_T1, S_T2 (App. B.4) at ln a from a state in the oracle's layout."""
+    b = _Bound(t)
+    p = make_prec(t.prec, len(t.bg.q))
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(3)
+    lib().oracle_sources_state(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna), _dp(y), _dp(out))
+    return out
+
+
+def library_row_order(prec: dict, nq: int) -> np.ndarray:
+    """For each state row in the order the library documents (photon T chain
+    delta_b, theta_b, theta_g, F_2..; polarisation G_0..; neutrinos delta,
+    theta, F_2..; massive Psi_0.. per node; then delta_c, eta, delta_g), the
+    index of that variable in the oracle's state layout
+    (delta_c, delta_b, theta_b, photon delta_g, theta_g, F_2.., G.., nu.., Psi.., eta)."""
+    lg, lp, ln, lq = int(prec["ell_gamma"]), int(prec["ell_pol"]), int(prec["ell_nu"]), int(prec["ell_ncdm"])
+    g0 = 3
+    p0 = g0 + lg + 1
+    n0 = p0 + (lp + 1 if lp > 0 else 0)
+    m0 = n0 + ln + 1
+    eta = m0 + nq * (lq + 1)
+    rows = [1, 2, g0 + 1] + [g0 + l for l in range(2, lg + 1)]
+    if lp > 0:
+        rows += [p0 + l for l in range(lp + 1)]
+    rows += [n0 + l for l in range(ln + 1)]
+    for i in range(nq):
+        rows += [m0 + i * (lq + 1) + l for l in range(lq + 1)]
+    rows += [0, eta, g0]
+    return np.array(rows)
+
+
+def sources_adjoint(t, gS: np.ndarray) -> np.ndarray:
+    """dL/dy [n_k][n_tau][rows] from dL/dS [n_k][3][n_tau], rows in the
+    library's documented order, zero before each mode's start.  At a fixed time
+    the sources are linear in the state with no constant term, so column i of
+    dS/dy is S(e_i) for the unit vector e_i: this is the transpose of that map
+    by its definition, from the oracle's own source function."""
+    nq = len(t.bg.q)
+    N = state_size(t.prec, nq)
+    order = library_row_order(t.prec, nq)
+    lna_out = np.asarray(t.lna_src)
+    out = np.zeros((len(t.k), len(lna_out), N))
+    b = _Bound(t)
+    p = make_prec(t.prec, nq)
+    e = np.zeros(N)
+    col = np.zeros(3)
+    cols = np.zeros((N, 3))
+    for ik, k in enumerate(t.k):
+        for j, lna in enumerate(lna_out):
+            if lna < t.lna_i[ik]:
+                continue
+            for i in range(N):
+                e[:] = 0.0
+                e[i] = 1.0
+                lib().oracle_sources_state(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna), _dp(e),
+                                           _dp(col))
+                cols[i] = col
+            g = cols @ gS[ik, :, j]
+            out[ik, j] = g[order]
+    return out
 
 
 def perturb_hist(t, hist=None, hist_n=None):

@@ -676,6 +676,16 @@ int oracle_perturb_many_dm(const otab_t *tb, const oprec_t *p0, int nk, const do
     return 0;
 }
 
+/* The source functions S_T0, S_T1, S_T2 (App. B.4) at ln a = lna from a given
+   state y (the oracle's layout), for tests of the transposed source map. */
+void oracle_sources_state(const otab_t *tb, const oprec_t *p, double k, double lna, const double *y, double *S) {
+    olayout_t L;
+    make_layout(p, &L);
+    double *dy = (double *)malloc(sizeof(double) * (size_t)L.N);
+    sources_at(tb, p, &L, k, lna, y, dy, &S[0], &S[1], &S[2], NULL);
+    free(dy);
+}
+
 /* y' at (ln a, y) for tests. */
 void oracle_rhs(const otab_t *tb, const oprec_t *p, double k, double lna, const double *y, double *dy) {
     olayout_t L;

@@ -45,7 +45,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
            "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_jacobian",
-           "cmb_spectra_adjoint",
+           "cmb_spectra_adjoint", "cmb_state_rows", "cmb_sources_adjoint",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
 
@@ -130,6 +130,8 @@ def _declare(lib):
     lib.cmb_perturb_replay.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                        _vp]
     lib.cmb_spectra_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.cmb_state_rows.argtypes = [_vp]
+    lib.cmb_sources_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_jacobian.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                  _vp, _vp, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
@@ -214,6 +216,13 @@ class Tables:
     @property
     def handle(self):
         return self._h
+
+    def state_rows(self) -> int:
+        """Rows of one mode's perturbation state (cmb_state_rows)."""
+        n = int(_lib.cmb_state_rows(self.handle))
+        if n < 0:
+            _check(n, "cmb_state_rows")
+        return n
 
     def export(self) -> dict:
         v = CTableView()
@@ -335,6 +344,13 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_spectra_adjoint(self._h, hs, len(tabs), int(ell_max), _ptr(Delta), _ptr(gCl), _ptr(gS),
                                         _stream(stream)), "cmb_spectra_adjoint")
+
+    def sources_adjoint(self, tabs, gS, gY, stream=None):
+        """dL/dy [n][n_k][n_tau][state_rows] from dL/dS [n][n_k][3][n_tau]
+        (cmb_sources_adjoint)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_sources_adjoint(self._h, hs, len(tabs), _ptr(gS), _ptr(gY), _stream(stream)),
+               "cmb_sources_adjoint")
 
     def jacobian(self, tabs, ell_max, Cl, J, status, rel=1e-4, order=4, stream=None):
         """C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s, tau_reio) (cmb_jacobian)."""

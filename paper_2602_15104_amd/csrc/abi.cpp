@@ -1036,6 +1036,38 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     return CMB_OK;
 }
 
+int cmb_state_rows(const cmb_tables *tab) {
+    if (!tab) {
+        set_error("cmb_state_rows: NULL table");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    const cmb_tables *one[1] = {tab};
+    int rc = check_batch(one, 1, b);
+    if (rc) return rc;
+    return cmbhip::state_rows(b.prec);
+}
+
+int cmb_sources_adjoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, const double *d_gS, double *d_gY,
+                        void *stream) {
+    if (!c || !d_gS || !d_gY) {
+        set_error("cmb_sources_adjoint: NULL argument");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload(c, tabs, n_cosmo, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_sources_adjoint(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_gS, d_gY, stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
 int cmb_spectra_adjoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_Delta,
                         const double *d_gCl, double *d_gS, void *stream) {
     if (!c || !d_Delta || !d_gCl || !d_gS) {

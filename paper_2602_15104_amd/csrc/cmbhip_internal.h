@@ -99,6 +99,10 @@ int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const dou
 int los_max_tau();
 // reverse mode of K3 then K2: dL/dC_l -> G = dL/dDelta (workspace, Delta's
 // layout) -> dL/dS in the sources' layout
+// transposed source functions: gS [n_cosmo][n_k][3][n_tau] -> gY [n_cosmo][n_k][n_tau][state_rows(p)]
+int launch_sources_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, const double *d_gS,
+                           double *d_gY, void *stream);
+int state_rows(const DevPrec &p);
 int launch_spectra_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E,
                            double s_pol, const double *d_Delta, const double *d_gC, double *d_G, double *d_gS,
                            void *stream);

@@ -146,7 +146,7 @@ __device__ void bk_at(const DevTab &tb, const DevPrec &p, double k, double lna, 
 struct Lay {
     int N, nF, nG, nV, nQ, nPs, bG, bV, bM, rDC, rETA, rDG, nch;
 };
-__device__ inline Lay make_lay(const DevPrec &p) {
+__host__ __device__ inline Lay make_lay(const DevPrec &p) {
     Lay L;
     L.nF = p.lg + 2;
     L.nG = p.lp > 0 ? p.lp + 1 : 0;
@@ -1194,6 +1194,85 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     }
 }
 
+
+// Transposed source functions (reverse mode of App. B.4, eq. source_functions,
+// with respect to the state): for every (cosmology, k, output time) from the
+// mode's start on, dL/dy of each state row from dL/dS_T0, dL/dS_T1, dL/dS_T2.
+// The sources are linear in the state at a fixed time (theta_b' enters
+// through the baryon row of the right-hand side, h' and eta' through the
+// Einstein constraints), so this is the transpose of that linear map.  One
+// thread per output time; rows the sources do not read are zero.
+template <bool MNU>
+__global__ void __launch_bounds__(256) sources_adj_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                          int n_tau, DevPrec p, const double *__restrict__ gS,
+                                                          double *__restrict__ gY) {
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)n_cosmo * n_k * n_tau) return;
+    const int j = (int)(id % n_tau);
+    const long ck = id / n_tau;
+    const int ik = (int)(ck % n_k), c = (int)(ck / n_k);
+    const DevTab &tb = tabs[c];
+    const Lay L = make_lay(p);
+    double *G = gY + id * L.N;
+    for (int r = 0; r < L.N; ++r) G[r] = 0.0;
+    const double lna = tb.lna_src[j];
+    if (lna < tb.lna_start[ik]) return;  // no sources before the mode starts
+    const double k = tb.k[ik], k2 = k * k;
+    const double *gs = gS + ck * 3 * n_tau;
+    const double g0 = gs[j], g1 = gs[n_tau + j], g2 = gs[2 * n_tau + j];
+    Bk so;
+    bk_at<MNU>(tb, p, k, lna, so);
+    const double Hc = so.Hc, ek = exp(-so.kap), gv = so.dk * ek;
+    const double gp = (so.dkp + so.dk * so.dk * so.invHc) * ek;
+    // adjoints of the intermediate quantities of the forward formulas
+    double a_alphap = g0 * (p.sw * gv * Hc - p.isw * gv * Hc - 2.0 * p.isw * Hc * ek * Hc + p.dop * Hc * gv) +
+                      g1 * p.isw * ek * k * Hc;
+    double a_alpha = g0 * (-2.0 * p.isw * gv * Hc - 2.0 * p.isw * Hc * ek * so.Hcp + p.dop * Hc * gp) +
+                     g1 * 2.0 * p.isw * ek * k * Hc;
+    const double a_eta = g0 * p.isw * gv - g1 * p.isw * ek * k;
+    double a_Ee = g0 * 2.0 * p.isw * Hc * ek;
+    const double a_tbp = g0 * p.dop * Hc * gv / k2;
+    const double a_Pi = g2 * 0.125 * gv;
+    G[1] += g0 * p.dop * Hc * gp / k2;
+    G[L.rDG] += g0 * p.sw * gv * 0.25;
+    // alpha' = -2 alpha + (eta - 4.5 a^2 rps / k^2) / Hc
+    a_alpha += -2.0 * a_alphap;
+    G[L.rETA] += a_alphap * so.invHc + a_eta;
+    const double a_rps = -a_alphap * 4.5 * so.a * so.a * so.invHc / k2;
+    // alpha = Hc (h' + 6 eta') / (2 k^2), with h' = Hh and eta' = Ee below
+    const double a_Hh = a_alpha * Hc / (2.0 * k2);
+    a_Ee += a_alpha * 6.0 * Hc / (2.0 * k2);
+    // (rho + p) sigma, the anisotropic stress
+    G[3] += a_rps * (4.0 / 3.0) * so.rg + 2.0 * a_Pi;
+    G[L.bV + 2] += a_rps * (4.0 / 3.0) * so.rur;
+    if (L.nG) {
+        G[L.bG] += a_Pi;
+        G[L.bG + 2] += a_Pi;
+    }
+    // theta_b' of the right-hand side
+    G[0] += a_tbp * so.cs2 * so.k2H;
+    G[1] += a_tbp * (-1.0 - so.R * so.T);
+    G[2] += a_tbp * so.R * so.T;
+    // eta' constraint
+    G[1] += a_Ee * so.cE * so.rb;
+    G[2] += a_Ee * so.cE * (4.0 / 3.0) * so.rg;
+    G[L.bV + 1] += a_Ee * so.cE * (4.0 / 3.0) * so.rur;
+    // h' constraint
+    G[L.rETA] += a_Hh * so.cH1;
+    G[L.rDC] += a_Hh * so.cH2 * so.rc;
+    G[0] += a_Hh * so.cH2 * so.rb;
+    G[L.rDG] += a_Hh * so.cH2 * so.rg;
+    G[L.bV] += a_Hh * so.cH2 * so.rur;
+    // massive neutrinos: delta rho, (rho + p) theta, (rho + p) sigma of every node
+    for (int i = 0; i < (MNU ? L.nQ : 0); ++i) {
+        const double q = tb.q[i], e = eps_of(q, so.am), w = so.pn4 * tb.W[i];
+        const int b = L.bM + i * L.nPs;
+        G[b] += a_Hh * so.cH2 * w * e;
+        G[b + 1] += a_Ee * so.cE * w * k * q;
+        G[b + 2] += a_rps * w * (2.0 / 3.0) * q * q / e;
+    }
+}
+
 }  // namespace
 
 // Rows per lane and group size for a hierarchy of N rows: R = 5 and the
@@ -1292,5 +1371,25 @@ int launch_perturb2_items(const DevTab *d_tabs, const WorkItem *d_items, int n_i
     return launch_perturb2_any(d_tabs, 0, 0, 0, p, nullptr, nullptr, nullptr, reinterpret_cast<const int2 *>(d_items),
                                n_items, nullptr, nullptr, false, stream);
 }
+
+int launch_sources_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, const double *d_gS,
+                           double *d_gY, void *stream) {
+    const long n = (long)n_cosmo * n_k * n_tau;
+    if (n <= 0) return CMB_OK;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipStream_t s = (hipStream_t)stream;
+    if (p.nq > 0)
+        hipLaunchKernelGGL((sources_adj_kernel<true>), grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, p, d_gS, d_gY);
+    else
+        hipLaunchKernelGGL((sources_adj_kernel<false>), grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, p, d_gS, d_gY);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("sources adjoint launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+int state_rows(const DevPrec &p) { return make_lay(p).N; }
 
 }  // namespace cmbhip

@@ -41,7 +41,7 @@ def test_exports_match_header(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.abi_version() == 2
+    assert lib.abi_version() == 3
     c, p = lib.defaults()
     # App. A.2 defaults
     assert c["omega_b"] == 0.02237 and c["omega_cdm"] == 0.120 and c["h"] == 0.6736
@@ -216,3 +216,18 @@ def test_autograd_parameter_mapping():
     assert all(c[q] == base[q] for q in base if q not in ("h", "omega_b", "omega_cdm", "A_s", "n_s", "tau_reio",
                                                             "z_reio") and not (isinstance(base[q], float)
                                                                                and math.isnan(base[q])))
+
+
+@pytest.mark.parametrize("name", ["config0", "config1", "config2"])
+def test_state_rows(lib, name):
+    """cmb_state_rows: the documented row count, equal to the oracle's state
+    size and to its map onto the library's row order."""
+    import oracle as O
+    wl = getattr(W, name)()
+    t = lib.Tables(wl.cosmo, wl.prec, wl.k[:4].copy(), 10)
+    nq = int(wl.prec["n_q"]) if wl.cosmo.get("N_nu_massive", 0) > 0 else 0
+    p = wl.prec
+    rows = (p["ell_gamma"] + 2) + (p["ell_pol"] + 1 if p["ell_pol"] > 0 else 0) + (p["ell_nu"] + 1) + \
+        nq * (p["ell_ncdm"] + 1) + 3
+    assert t.state_rows() == rows
+    assert rows == O.state_size(p, nq) == len(O.library_row_order(p, nq))

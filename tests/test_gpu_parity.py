@@ -991,6 +991,79 @@ def test_spectra_adjoint_dot_product_config1(ctx):
     assert abs(ad / fd - 1) < 1e-8
 
 
+# ---------------------------------------------------------------- transposed sources
+@pytest.mark.parametrize("case", ["pol", "nopol", "massive"])
+def test_sources_adjoint_parity(ctx, case):
+    """cmb_sources_adjoint on seeded dL/dS (6 modes, 40 output times) against
+    the oracle's transpose of its own source map, built from unit vectors:
+    every (mode, time) row vector to 1e-10 of its largest entry; zero before
+    each mode's start."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    if case == "massive":
+        wl = _massive(W.small_case(n_k=6, n_tau=40, ell_max=20, k_max=0.1), 0.06, 3, 5)
+    else:
+        wl = W.small_case(n_k=6, n_tau=40, ell_max=20, k_max=0.1, polarization=(case == "pol"), ell_g=10)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    rng = np.random.Generator(np.random.PCG64(67))
+    gS = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
+    N = tab.state_rows()
+    gY = torch.full((1, len(wl.k), wl.n_tau, N), float("nan"), dtype=torch.float64, device="cuda:0")
+    ctx.sources_adjoint([tab], torch.tensor(gS, device="cuda:0"), gY)
+    torch.cuda.synchronize()
+    g = gY.cpu().numpy()[0]
+    o = O.sources_adjoint(t_or, gS[0])
+    assert g.shape == o.shape
+    worst = 0.0
+    for ik in range(len(wl.k)):
+        for j in range(wl.n_tau):
+            m = np.max(np.abs(o[ik, j]))
+            if m == 0.0:
+                assert np.all(g[ik, j] == 0.0), (ik, j)
+                continue
+            worst = max(worst, float(np.max(np.abs(g[ik, j] - o[ik, j])) / m))
+    _say("sources adjoint", case, "err", worst)
+    assert worst <= 1e-10
+
+
+def test_sources_adjoint_chain(ctx):
+    """The reverse sweep's first three steps chained on seeded sources and
+    seeded dL/dC_l: dL/dC_l -> dL/dS (cmb_spectra_adjoint at the projection of
+    those sources) -> dL/dy (cmb_sources_adjoint) for two cosmologies, against
+    the oracle's own projection and transposes of the same inputs."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=5, n_tau=40, ell_max=30, k_max=0.05)
+    cosmos = W.perturbed_cosmologies(2, seed=71)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    rng = np.random.Generator(np.random.PCG64(73))
+    S = rng.standard_normal((2, len(wl.k), 3, wl.n_tau))
+    gC = rng.standard_normal((2, 3, wl.ell_max + 1))
+    D = torch.empty((2, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    ctx.los(tabs, wl.ell_max, torch.tensor(S, device="cuda:0"), D)
+    gS = torch.empty((2, len(wl.k), 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+    ctx.spectra_adjoint(tabs, wl.ell_max, D, torch.tensor(gC, device="cuda:0"), gS)
+    N = tabs[0].state_rows()
+    gY = torch.empty((2, len(wl.k), wl.n_tau, N), dtype=torch.float64, device="cuda:0")
+    ctx.sources_adjoint(tabs, gS, gY)
+    torch.cuda.synchronize()
+    gYg = gY.cpu().numpy()
+    for i, cc in enumerate(cosmos):
+        t_or = O.build_tables(cc, wl.prec, wl.k, wl.n_tau)
+        DT, DE = O.los(t_or, S[i], wl.ell_max, True)
+        GT, GE = O.cl_adjoint(t_or.k, DT, DE, gC[i], wl.ell_max, True, cc["A_s"], cc["n_s"])
+        go = O.los_adjoint(t_or, GT, GE, wl.ell_max, True)
+        yo = O.sources_adjoint(t_or, go)
+        e = float(np.max(np.abs(gYg[i] - yo)) / np.max(np.abs(yo)))
+        _say("chain cosmology", i, "err", e)
+        assert e <= 1e-9
+
+
 # ---------------------------------------------------------------- torch.autograd exposure
 def test_autograd_spectra_from_sources(ctx):
     """spectra_from_sources for two cosmologies (40 modes to k = 0.1, 300

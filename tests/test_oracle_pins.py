@@ -988,3 +988,54 @@ def test_spectra_adjoint_dot_product(tab12):
     V = rng.standard_normal(S.shape)
     fd = (L(S + 1e-3 * V) - L(S - 1e-3 * V)) / 2e-3
     assert abs(np.sum(gS * V) / fd - 1) < 1e-11
+
+
+# ---------------------------------------------------------------- transposed sources
+@pytest.fixture(scope="module")
+def src_case():
+    wl = W.small_case(n_k=3, n_tau=30, ell_max=20, ell_g=8, k_max=0.1)
+    return O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+
+
+def test_sources_adjoint_dot_product(src_case):
+    """<dL/dS, S(y)> = <dL/dy, y> at every output time for seeded states y and
+    seeded dL/dS: the transposed source map against the forward one (App. B.4)."""
+    t = src_case
+    rng = np.random.Generator(np.random.PCG64(61))
+    gS = rng.standard_normal((len(t.k), 3, len(t.lna_src)))
+    gY = O.sources_adjoint(t, gS)
+    order = O.library_row_order(t.prec, len(t.bg.q))
+    N = len(order)
+    assert N == O.state_size(t.prec, len(t.bg.q))
+    assert sorted(order) == list(range(N))
+    for ik, k in enumerate(t.k):
+        for j in range(0, len(t.lna_src), 7):
+            y = rng.standard_normal(N)  # oracle layout
+            S = O.sources_of_state(t, k, t.lna_src[j], y)
+            lhs = float(gS[ik, :, j] @ S) if t.lna_src[j] >= t.lna_i[ik] else 0.0
+            rhs = float(gY[ik, j] @ y[order])
+            scale = float(np.abs(gS[ik, :, j]) @ np.abs(S)) + 1e-300
+            assert abs(lhs - rhs) <= 1e-12 * scale, (ik, j, lhs, rhs)
+
+
+def test_sources_adjoint_structure(src_case):
+    """Only S_T2 = g Pi / 8 with Pi = 2 F_g2 + G_0 + G_2 (App. B.4): dL/dS_T2 = 1
+    alone reaches the rows F_g2, G_0 and G_2, in the ratio 2 : 1 : 1; nothing
+    reaches any row before a mode's start."""
+    t = src_case
+    gS = np.zeros((len(t.k), 3, len(t.lna_src)))
+    gS[:, 2, :] = 1.0
+    gY = O.sources_adjoint(t, gS)
+    lg, lp = int(t.prec["ell_gamma"]), int(t.prec["ell_pol"])
+    f2, g0 = 3, lg + 2
+    for ik in range(len(t.k)):
+        for j in range(len(t.lna_src)):
+            row = gY[ik, j]
+            if t.lna_src[j] < t.lna_i[ik]:
+                assert np.all(row == 0.0)
+                continue
+            nz = set(np.nonzero(row)[0])
+            assert nz <= {f2, g0, g0 + 2}, nz
+            if row[f2] != 0.0:
+                assert lp > 0
+                assert abs(row[g0] / row[f2] - 0.5) < 1e-14 and abs(row[g0 + 2] / row[f2] - 0.5) < 1e-14
