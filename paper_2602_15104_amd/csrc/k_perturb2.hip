@@ -1200,25 +1200,17 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 // mode's start on, dL/dy of each state row from dL/dS_T0, dL/dS_T1, dL/dS_T2.
 // The sources are linear in the state at a fixed time (theta_b' enters
 // through the baryon row of the right-hand side, h' and eta' through the
-// Einstein constraints), so this is the transpose of that linear map.  One
-// thread per output time; rows the sources do not read are zero.
+// Einstein constraints), so this is the transpose of that linear map.  A block
+// of 64 lanes takes P consecutive output points: their rows (zero where the
+// sources do not read) are formed in LDS, one lane per point, and the block's
+// contiguous P N doubles then go out in coalesced 64-wide stores.
+constexpr int SADJ_LDS = 8192;  // at most this many doubles of LDS per block
 template <bool MNU>
-__global__ void __launch_bounds__(256) sources_adj_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
-                                                          int n_tau, DevPrec p, const double *__restrict__ gS,
-                                                          double *__restrict__ gY) {
-    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (long)n_cosmo * n_k * n_tau) return;
-    const int j = (int)(id % n_tau);
-    const long ck = id / n_tau;
-    const int ik = (int)(ck % n_k), c = (int)(ck / n_k);
-    const DevTab &tb = tabs[c];
-    const Lay L = make_lay(p);
-    double *G = gY + id * L.N;
-    for (int r = 0; r < L.N; ++r) G[r] = 0.0;
+__device__ void sources_adj_point(const DevTab &tb, const DevPrec &p, const Lay &L, int n_tau, int ik, int j,
+                                  const double *__restrict__ gs, double *G) {
     const double lna = tb.lna_src[j];
     if (lna < tb.lna_start[ik]) return;  // no sources before the mode starts
     const double k = tb.k[ik], k2 = k * k;
-    const double *gs = gS + ck * 3 * n_tau;
     const double g0 = gs[j], g1 = gs[n_tau + j], g2 = gs[2 * n_tau + j];
     Bk so;
     bk_at<MNU>(tb, p, k, lna, so);
@@ -1271,6 +1263,30 @@ __global__ void __launch_bounds__(256) sources_adj_kernel(const DevTab *__restri
         G[b + 1] += a_Ee * so.cE * w * k * q;
         G[b + 2] += a_rps * w * (2.0 / 3.0) * q * q / e;
     }
+}
+
+template <bool MNU>
+__global__ void __launch_bounds__(64) sources_adj_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                         int n_tau, DevPrec p, int P, const double *__restrict__ gS,
+                                                         double *__restrict__ gY) {
+    extern __shared__ double sg[];  // P rows-long records
+    const Lay L = make_lay(p);
+    const long total = (long)n_cosmo * n_k * n_tau;
+    const long first = (long)blockIdx.x * P;
+    const int np = (int)((total - first) < P ? (total - first) : P);  // points of this block
+    const int nd = np * L.N;
+    for (int i = threadIdx.x; i < nd; i += 64) sg[i] = 0.0;
+    __syncthreads();
+    if ((int)threadIdx.x < np) {
+        const long id = first + threadIdx.x;
+        const int j = (int)(id % n_tau);
+        const long ck = id / n_tau;
+        const int ik = (int)(ck % n_k), c = (int)(ck / n_k);
+        sources_adj_point<MNU>(tabs[c], p, L, n_tau, ik, j, gS + ck * 3 * n_tau, sg + threadIdx.x * L.N);
+    }
+    __syncthreads();
+    double *out = gY + first * L.N;
+    for (int i = threadIdx.x; i < nd; i += 64) out[i] = sg[i];
 }
 
 }  // namespace
@@ -1376,12 +1392,22 @@ int launch_sources_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau
                            double *d_gY, void *stream) {
     const long n = (long)n_cosmo * n_k * n_tau;
     if (n <= 0) return CMB_OK;
-    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const int rows = make_lay(p).N;
+    int P = SADJ_LDS / rows;  // output points per block, each one lane
+    if (P > 64) P = 64;
+    if (P < 1) {
+        set_error("state too large for the transposed-source kernel");
+        return CMB_E_UNSUPPORTED;
+    }
+    dim3 grid((unsigned)((n + P - 1) / P)), block(64);
+    const size_t lds = sizeof(double) * (size_t)P * rows;
     hipStream_t s = (hipStream_t)stream;
     if (p.nq > 0)
-        hipLaunchKernelGGL((sources_adj_kernel<true>), grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, p, d_gS, d_gY);
+        hipLaunchKernelGGL((sources_adj_kernel<true>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, P, d_gS,
+                           d_gY);
     else
-        hipLaunchKernelGGL((sources_adj_kernel<false>), grid, block, 0, s, d_tabs, n_cosmo, n_k, n_tau, p, d_gS, d_gY);
+        hipLaunchKernelGGL((sources_adj_kernel<false>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, P, d_gS,
+                           d_gY);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("sources adjoint launch: ") + hipGetErrorString(e));
