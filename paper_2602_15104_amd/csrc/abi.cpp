@@ -955,7 +955,13 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     } workers;
     {
         const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        for (unsigned i = 0; i < nth; ++i) workers.th.emplace_back(work);
+        try {
+            for (unsigned i = 0; i < nth; ++i) workers.th.emplace_back(work);
+        } catch (const std::exception &) {
+            // no thread could start: build every table here (started workers
+            // share the jobs and are joined on return)
+            if (workers.th.empty()) work();
+        }
     }
     auto wait_built = [&](int p) {
         std::unique_lock<std::mutex> bl(bmu);

@@ -479,10 +479,16 @@ int cmb_server_create(int device, const cmb_server_opts *opts, cmb_server **out)
             return CMB_E_DEVICE;
         }
     (void)hipSetDevice(prev);
-    cmb_server *raw = s.get();
-    for (int i = 0; i < nw; ++i) s->workers.emplace_back(worker_main, raw);
-    s->sched = std::thread(sched_main, raw);
-    *out = s.release();
+    cmb_server *raw = s.release();
+    try {
+        for (int i = 0; i < nw; ++i) raw->workers.emplace_back(worker_main, raw);
+        raw->sched = std::thread(sched_main, raw);
+    } catch (const std::exception &) {
+        cmb_server_destroy(raw);  // stops and joins whatever started, frees the device resources
+        cmbhip::set_error("cmb_server_create: thread creation failed");
+        return CMB_E_NOMEM;
+    }
+    *out = raw;
     cmbhip::set_error("");
     return CMB_OK;
 }
@@ -572,7 +578,7 @@ void cmb_server_destroy(cmb_server *s) {
         s->stop_sched = true;
         s->cv_sched.notify_all();
     }
-    s->sched.join();
+    if (s->sched.joinable()) s->sched.join();
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
