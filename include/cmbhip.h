@@ -269,7 +269,7 @@ int cmb_spectra_adjoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo
  *   [Psi_0 .. Psi_lncdm] per momentum node             n_q (ell_ncdm + 1)
  *   [delta_c, eta, delta_g]                             3
  * (F_2 = 2 sigma, photon and neutrino; App. B.3 and App. C variables).
- * Returns that count, or CMB_E_INVALID for a NULL table. */
+ * Returns that count (> 0), or -CMB_E_INVALID for a NULL table. */
 int cmb_state_rows(const cmb_tables *tab);
 
 /* Reverse mode of the source functions (App. B.4, eq. source_functions),

@@ -220,8 +220,8 @@ class Tables:
     def state_rows(self) -> int:
         """Rows of one mode's perturbation state (cmb_state_rows)."""
         n = int(_lib.cmb_state_rows(self.handle))
-        if n < 0:
-            _check(n, "cmb_state_rows")
+        if n <= 0:
+            _check(-n if n < 0 else 1, "cmb_state_rows")
         return n
 
     def export(self) -> dict:

@@ -1045,12 +1045,13 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
 int cmb_state_rows(const cmb_tables *tab) {
     if (!tab) {
         set_error("cmb_state_rows: NULL table");
-        return CMB_E_INVALID;
+        return -CMB_E_INVALID;
     }
     Batch b;
     const cmb_tables *one[1] = {tab};
     int rc = check_batch(one, 1, b);
-    if (rc) return rc;
+    if (rc) return -rc;
+    set_error("");
     return cmbhip::state_rows(b.prec);
 }
 

@@ -230,4 +230,5 @@ def test_state_rows(lib, name):
     rows = (p["ell_gamma"] + 2) + (p["ell_pol"] + 1 if p["ell_pol"] > 0 else 0) + (p["ell_nu"] + 1) + \
         nq * (p["ell_ncdm"] + 1) + 3
     assert t.state_rows() == rows
+    assert lib._lib.cmb_state_rows(None) == -1  # -CMB_E_INVALID
     assert rows == O.state_size(p, nq) == len(O.library_row_order(p, nq))

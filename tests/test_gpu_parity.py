@@ -1185,3 +1185,9 @@ def test_new_entry_points_reject_bad_arguments(ctx):
         ctx.lensing_potential([tab], 1, torch.zeros((1, 8, 40), dtype=torch.float64, device=dev), P)
     with pytest.raises(L.CmbError):
         ctx.bessel3_table(0)
+    gY = torch.zeros((1, 8, 40, tab.state_rows()), dtype=torch.float64, device=dev)
+    with pytest.raises(L.CmbError) as e:
+        ctx.sources_adjoint([tab], None, gY)  # dL/dS missing
+    assert e.value.name == "CMB_E_INVALID"
+    with pytest.raises(L.CmbError):
+        ctx.sources_adjoint([tab], S, None)
