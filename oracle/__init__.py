@@ -267,12 +267,13 @@ def library_row_order(prec: dict, nq: int) -> np.ndarray:
     return np.array(rows)
 
 
-def sources_adjoint(t, gS: np.ndarray) -> np.ndarray:
+def sources_adjoint(t, gS: np.ndarray, points=None) -> np.ndarray:
     """dL/dy [n_k][n_tau][rows] from dL/dS [n_k][3][n_tau], rows in the
     library's documented order, zero before each mode's start.  At a fixed time
     the sources are linear in the state with no constant term, so column i of
     dS/dy is S(e_i) for the unit vector e_i: this is the transpose of that map
-    by its definition, from the oracle's own source function."""
+    by its definition, from the oracle's own source function.  With points, a
+    list of (k index, time index), only those entries are filled."""
     nq = len(t.bg.q)
     N = state_size(t.prec, nq)
     order = library_row_order(t.prec, nq)
@@ -283,18 +284,18 @@ def sources_adjoint(t, gS: np.ndarray) -> np.ndarray:
     e = np.zeros(N)
     col = np.zeros(3)
     cols = np.zeros((N, 3))
-    for ik, k in enumerate(t.k):
-        for j, lna in enumerate(lna_out):
-            if lna < t.lna_i[ik]:
-                continue
-            for i in range(N):
-                e[:] = 0.0
-                e[i] = 1.0
-                lib().oracle_sources_state(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna), _dp(e),
-                                           _dp(col))
-                cols[i] = col
-            g = cols @ gS[ik, :, j]
-            out[ik, j] = g[order]
+    pts = points if points is not None else [(ik, j) for ik in range(len(t.k)) for j in range(len(lna_out))]
+    for ik, j in pts:
+        k, lna = t.k[ik], lna_out[j]
+        if lna < t.lna_i[ik]:
+            continue
+        for i in range(N):
+            e[:] = 0.0
+            e[i] = 1.0
+            lib().oracle_sources_state(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna), _dp(e), _dp(col))
+            cols[i] = col
+        g = cols @ gS[ik, :, j]
+        out[ik, j] = g[order]
     return out
 
 

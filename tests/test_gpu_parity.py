@@ -1028,6 +1028,37 @@ def test_sources_adjoint_parity(ctx, case):
     assert worst <= 1e-10
 
 
+def test_sources_adjoint_config1_sampled(ctx):
+    """Config 1 size (400 modes, 2000 output times, 79 rows; the launch the
+    bench times): cmb_sources_adjoint on seeded dL/dS against the oracle at 60
+    seeded (mode, time) points, each row vector to 1e-10 of its largest entry;
+    every point before its mode's start is zero."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.config1()
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    rng = np.random.Generator(np.random.PCG64(79))
+    gS = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
+    N = tab.state_rows()
+    gY = torch.empty((1, len(wl.k), wl.n_tau, N), dtype=torch.float64, device="cuda:0")
+    ctx.sources_adjoint([tab], torch.tensor(gS, device="cuda:0"), gY)
+    torch.cuda.synchronize()
+    pts = [(int(rng.integers(len(wl.k))), int(rng.integers(wl.n_tau))) for _ in range(60)]
+    o = O.sources_adjoint(t_or, gS[0], points=pts)
+    worst = 0.0
+    for ik, j in pts:
+        g = gY[0, ik, j].cpu().numpy()
+        m = np.max(np.abs(o[ik, j]))
+        if m == 0.0:
+            assert np.all(g == 0.0)
+            continue
+        worst = max(worst, float(np.max(np.abs(g - o[ik, j])) / m))
+    _say("config1 sources adjoint sampled err", worst)
+    assert worst <= 1e-10
+
+
 def test_sources_adjoint_chain(ctx):
     """The reverse sweep's first three steps chained on seeded sources and
     seeded dL/dC_l: dL/dC_l -> dL/dS (cmb_spectra_adjoint at the projection of
