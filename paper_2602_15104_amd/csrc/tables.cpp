@@ -340,6 +340,31 @@ static double bisect(const std::function<double(double)> &f, double lo, double h
     return 0.5 * (lo + hi);
 }
 
+// Root of an increasing f with f(lo) = flo <= 0 < f(hi) = fhi, for an f that is
+// expensive to evaluate: Illinois false position (the retained end's value
+// halved when the same end is kept twice) while the bracket is wider than
+// 1e-10 of its ends, then bisection to the last bit.
+static double root_bracketed(const std::function<double(double)> &f, double lo, double hi, double flo, double fhi) {
+    int keep = 0;  // -1: hi was moved last, +1: lo was moved last
+    for (int it = 0; it < 60 && hi - lo > 1e-10 * (1.0 + std::fabs(lo) + std::fabs(hi)); ++it) {
+        double x = (lo * fhi - hi * flo) / (fhi - flo);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        const double fx = f(x);
+        if (fx > 0.0) {
+            hi = x;
+            fhi = fx;
+            if (keep == -1) flo *= 0.5;
+            keep = -1;
+        } else {
+            lo = x;
+            flo = fx;
+            if (keep == 1) fhi *= 0.5;
+            keep = 1;
+        }
+    }
+    return bisect(f, lo, hi);
+}
+
 // second derivatives of the natural cubic spline on a uniform grid (Thomas algorithm)
 static void natural_spline(const std::vector<double> &f, double h, std::vector<double> &M) {
     int n = (int)f.size() - 1;
@@ -454,8 +479,9 @@ int build_tables(const cmb_cosmo &cin, const cmb_prec &p, const double *k, int n
     double zre = c.z_reio;
     if (std::isfinite(c.tau_reio)) {
         auto f = [&](double z) { return tau_reion(m, z) - c.tau_reio; };
-        if (!(f(0.0) < 0.0 && f(50.0) > 0.0)) return fail(CMB_E_ROOT, "tau_reio not bracketed by z_reion in [0, 50]");
-        zre = bisect(f, 0.0, 50.0);
+        const double f0 = f(0.0), f50 = f(50.0);
+        if (!(f0 < 0.0 && f50 > 0.0)) return fail(CMB_E_ROOT, "tau_reio not bracketed by z_reion in [0, 50]");
+        zre = root_bracketed(f, 0.0, 50.0, f0, f50);
     }
     Reion R(m, zre);
 
