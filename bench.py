@@ -350,6 +350,41 @@ def main():
         variants["sources_adjoint"] = {"ms_per_cosmology": t_sa, "bytes": by, "GB_per_s": by / (t_sa * 1e6),
                                        "rows": rows}
         del gCl, gS, gY
+        # trajectory checkpoints every 64 accepted steps: the batch's recorded
+        # steps replayed plain, replayed writing the checkpoints, and every
+        # segment replayed from its checkpoint (the forward recomputation of a
+        # checkpointed reverse sweep), into one source buffer
+        every = 64
+        cap = int(wl.prec["max_steps"]) + 1
+        Hh = torch.empty((B, n_k, cap), dtype=torch.float64, device=dev)
+        Hn = torch.empty((B, n_k), dtype=torch.int32, device=dev)
+        ctx.perturb_record(tabs, S, st, Hh, Hn)
+        ck = torch.empty((B, n_k, (cap - 1) // every + 1, 1 + 2 * rows), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        n_seg = int(Hn.max().item()) // every + 1
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        trp, tck, tsg = [], [], []
+        for r in range(3):
+            e0.record()
+            ctx.perturb_replay(tabs, Hh, Hn, S, st)
+            e1.record()
+            ctx.perturb_checkpoint(tabs, Hh, Hn, every, ck, S, st, replay=True)
+            e2.record()
+            for sg in range(n_seg):
+                ctx.perturb_segment(tabs, Hh, Hn, every, ck, sg, S, st)
+            e3.record()
+            torch.cuda.synchronize()
+            trp.append(e0.elapsed_time(e1))
+            tck.append(e1.elapsed_time(e2))
+            tsg.append(e2.elapsed_time(e3))
+        used = float(((Hn.to(torch.float64) // every) + 1).sum().item()) * (1 + 2 * rows) * 8.0
+        variants["checkpoints"] = {"every": every, "replay_ms": float(np.median(trp[1:])),
+                                   "replay_with_checkpoints_ms": float(np.median(tck[1:])),
+                                   "all_segments_ms": float(np.median(tsg[1:])), "segments": n_seg,
+                                   "checkpoint_bytes_written": used, "checkpoint_buffer_bytes": ck.numel() * 8.0,
+                                   "modes_not_ok": int((st != 0).sum().item()), "batch": B}
+        del Hh, Hn, ck
         # parameter derivatives: C_l and dC_l/d(h, omega_b, omega_cdm, ln A_s, n_s,
         # tau_reio) for the batch (five-point frozen-step stencil, rel 1e-4;
         # host table builds of the perturbed cosmologies included)
@@ -370,7 +405,7 @@ def main():
               f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
               f"{variants['lensing']}, spectra adjoint {variants['spectra_adjoint']['ms_per_batch']:.1f} ms, "
               f"sources adjoint {variants['sources_adjoint']['ms_per_cosmology']:.2f} ms per cosmology, "
-              f"jacobian {variants['jacobian']['s_per_batch']:.2f} s",
+              f"checkpoints {variants['checkpoints']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s",
               file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic flops / measured duration)

@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-#define CMB_ABI_VERSION 3
+#define CMB_ABI_VERSION 4
 
 /* call-level return codes */
 enum {
@@ -225,6 +225,38 @@ int cmb_perturb_record(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo,
 int cmb_perturb_replay(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, const double *d_hist,
                        const int32_t *d_hist_n, int hist_cap, double *d_S, int32_t *d_status, int32_t *d_nsteps,
                        void *hip_stream);
+
+/* Trajectory checkpoints of the ESDIRK integration (section 3 and the
+ * integrator's adjoint option in App. A.2: reverse-mode differentiation
+ * through the integrator needs the forward states again, the memory cost the
+ * paper notes; checkpoints every few steps bound it to one segment of steps
+ * plus the checkpoints, each segment recomputed from its own).
+ * cmb_perturb_checkpoint is cmb_perturb_record (replay = 0) or
+ * cmb_perturb_replay (replay != 0) that also writes, per mode, the record
+ *   d_ck[n_cosmo][n_k][ck_cap][1 + 2 N]  (N = cmb_state_rows):
+ *   ln a, the N state rows, and the N rows of the stage derivative the next
+ *   step starts from (the last stage of the step just taken),
+ * slot j after j * every accepted steps (slot 0 the start); slots past a
+ * mode's last step are left unwritten.  Sources, status and counts as the
+ * record or replay call.
+ * cmb_perturb_segment replays, for every mode, only the accepted steps
+ * seg * every + 1 .. (seg + 1) * every of d_hist, starting from checkpoint
+ * slot seg, and writes only the source entries of the output times those
+ * steps reach (segment 0 also the zeros before the start, the last segment
+ * the outputs after an abort): run over every segment into one d_S it
+ * reproduces cmb_perturb_replay's sources bit for bit, whatever the order.
+ * A mode whose history ends at or before step seg * every is left alone
+ * (status 0, count 0); status CMB_K_MAX_STEPS when the history ends inside
+ * the segment before a = 1.  d_ck must come from cmb_perturb_checkpoint
+ * with the same tables, history, every and ck_cap.
+ * Needs every >= 1, ck_cap >= (hist_cap - 1) / every + 1 and
+ * 0 <= seg < ck_cap (else CMB_E_INVALID); otherwise errors as cmb_perturb. */
+int cmb_perturb_checkpoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int replay, double *d_hist,
+                           int32_t *d_hist_n, int hist_cap, int every, double *d_ck, int ck_cap, double *d_S,
+                           int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
+int cmb_perturb_segment(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, const double *d_hist,
+                        const int32_t *d_hist_n, int hist_cap, int every, const double *d_ck, int ck_cap, int seg,
+                        double *d_S, int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
 
 /* Spectra and their derivatives with respect to theta = (h, omega_b,
  * omega_cdm, ln A_s, n_s, tau_reio) for a batch of cosmologies sharing one k

@@ -388,10 +388,12 @@ def jacobian(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, re
 
 
 def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None, y0=None, want_y: bool = False,
-                rtol: float | None = None, atol: float | None = None, acc_cap: int = 0, want_diag: bool = False):
+                rtol: float | None = None, atol: float | None = None, acc_cap: int = 0, want_diag: bool = False,
+                fixed=None):
     """One mode with full control (tests): custom start, output times,
     initial state, tolerances; optionally the dense-output states and the
-    accepted step sequence."""
+    accepted step sequence.  fixed = [start, h_1, h_2, ...] replays those
+    steps without error control (the start overrides lna0)."""
     prec = dict(t.prec)
     if prec_over:
         prec.update(prec_over)
@@ -409,11 +411,12 @@ def perturb_one(t, k: float, lna0: float, lna_out, prec_over: dict | None = None
     ns = ctypes.c_int(0)
     na = ctypes.c_int(0)
     D = np.zeros((n_out, 4))
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.float64)
     b = _Bound(t)
     st = lib().oracle_perturb(ctypes.byref(b.tab), ctypes.byref(p), float(k), float(lna0), n_out, _dp(lna_out), _dp(S),
                               _dp(Y) if want_y else None, _dp(y0a) if y0a is not None else None, ctypes.byref(ns),
                               ctypes.byref(na), _dp(acc) if acc_cap else None, acc_cap, _dp(D) if want_diag else None,
-                              None, None, 0)
+                              None, _dp(fx) if fx is not None else None, 0 if fx is None else len(fx) - 1)
     out = {"S": S, "status": st, "nsteps": ns.value, "naccept": na.value, "N": N}
     if want_diag:
         out["diag"] = D  # h', eta', alpha, alpha' per output time

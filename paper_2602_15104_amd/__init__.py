@@ -44,7 +44,8 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_tables_export", "cmb_ctx_create", "cmb_ctx_destroy", "cmb_solve_workspace_bytes", "cmb_perturb",
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
-           "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_jacobian",
+           "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_perturb_checkpoint",
+           "cmb_perturb_segment", "cmb_jacobian",
            "cmb_spectra_adjoint", "cmb_state_rows", "cmb_sources_adjoint",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena"]
@@ -129,6 +130,10 @@ def _declare(lib):
                                        _vp]
     lib.cmb_perturb_replay.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                        _vp]
+    lib.cmb_perturb_checkpoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                           ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.cmb_perturb_segment.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                        _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
     lib.cmb_spectra_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
     lib.cmb_state_rows.argtypes = [_vp]
     lib.cmb_sources_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp]
@@ -338,6 +343,24 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_perturb_replay(self._h, hs, len(tabs), _ptr(hist), _ptr(hist_n), int(hist.shape[-1]),
                                        _ptr(S), _ptr(status), _ptr(nsteps), _stream(stream)), "cmb_perturb_replay")
+
+    def perturb_checkpoint(self, tabs, hist, hist_n, every, ck, S, status, nsteps=None, replay=False, stream=None):
+        """Record (replay=False) or replay the step histories and write the
+        trajectory checkpoints ck [n][n_k][ck_cap][1 + 2 N] every `every`
+        accepted steps (cmb_perturb_checkpoint)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_checkpoint(self._h, hs, len(tabs), 1 if replay else 0, _ptr(hist), _ptr(hist_n),
+                                           int(hist.shape[-1]), int(every), _ptr(ck), int(ck.shape[-2]), _ptr(S),
+                                           _ptr(status), _ptr(nsteps), _stream(stream)), "cmb_perturb_checkpoint")
+
+    def perturb_segment(self, tabs, hist, hist_n, every, ck, seg, S, status, nsteps=None, stream=None):
+        """Replay segment seg (accepted steps seg*every+1 .. (seg+1)*every) of
+        every mode from its checkpoint, writing only that segment's outputs
+        into S (cmb_perturb_segment)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_perturb_segment(self._h, hs, len(tabs), _ptr(hist), _ptr(hist_n), int(hist.shape[-1]),
+                                        int(every), _ptr(ck), int(ck.shape[-2]), int(seg), _ptr(S), _ptr(status),
+                                        _ptr(nsteps), _stream(stream)), "cmb_perturb_segment")
 
     def spectra_adjoint(self, tabs, ell_max, Delta, gCl, gS, stream=None):
         """dL/dS from dL/dC_l through the transposed quadrature and projection."""

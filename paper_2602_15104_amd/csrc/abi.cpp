@@ -810,11 +810,18 @@ static int upload_devtabs(cmb_ctx *c, const std::vector<cmbhip::DevTab> &v, cons
     return CMB_OK;
 }
 
+// trajectory checkpoints of a history launch: every ck_every accepted steps
+// into (seg < 0) or, for segment seg, out of ck [n][n_k][ck_cap][1 + 2 N]
+struct Ckpt {
+    double *ck = nullptr;
+    int every = 0, cap = 0, seg = -1;
+};
+
 // K1 over tabs with step histories: cosmology i records into (replay = false)
 // or replays (replay = true) hist + base[i] n_k cap, hist_n + base[i] n_k
 static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const std::vector<int> &base,
                         double *d_hist, int32_t *d_hist_n, int cap, bool replay, double *d_S, int32_t *d_status,
-                        int32_t *d_nsteps, hipStream_t s) {
+                        int32_t *d_nsteps, hipStream_t s, const Ckpt &ck = Ckpt()) {
     Batch b;
     int rc = check_batch(tabs, n, b);
     if (rc) return rc;
@@ -826,6 +833,12 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
         set_error("step history capacity below max_steps + 1");
         return CMB_E_INVALID;
     }
+    const size_t ck_rec = ck.ck ? (size_t)ck.cap * (1 + 2 * (size_t)cmbhip::state_rows(b.prec)) : 0;
+    if (ck.ck && (ck.every < 1 || ck.cap < (cap - 1) / ck.every + 1 || ck.seg >= ck.cap || (ck.seg >= 0 && !replay))) {
+        set_error("checkpoints: need every >= 1, ck_cap >= (hist_cap - 1) / every + 1, 0 <= seg < ck_cap, and a "
+                  "segment only from a replay");
+        return CMB_E_INVALID;
+    }
     rc = upload(c, tabs, n, s);
     if (rc) return rc;
     std::vector<cmbhip::DevTab> v(c->h_tabs);
@@ -833,6 +846,17 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
         double *h = d_hist + (size_t)base[i] * b.n_k * cap;
         int *hn = d_hist_n + (size_t)base[i] * b.n_k;
         v[i].hist_cap = cap;
+        if (ck.ck) {
+            double *ci = ck.ck + (size_t)base[i] * b.n_k * ck_rec;
+            v[i].ck_every = ck.every;
+            v[i].ck_cap = ck.cap;
+            if (ck.seg >= 0) {
+                v[i].ck_in = ci;
+                v[i].ck_seg = ck.seg;
+            } else {
+                v[i].ck_out = ci;
+            }
+        }
         if (replay) {
             v[i].hist_in = h;
             v[i].hist_in_n = hn;
@@ -886,6 +910,55 @@ int cmb_perturb_replay(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, c
     for (int i = 0; i < n_cosmo; ++i) base[i] = i;
     int rc = perturb_hist(c, tabs, n_cosmo, base, const_cast<double *>(d_hist), const_cast<int32_t *>(d_hist_n),
                           hist_cap, true, d_S, d_status, d_nsteps, (hipStream_t)stream);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_perturb_checkpoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int replay, double *d_hist,
+                           int32_t *d_hist_n, int hist_cap, int every, double *d_ck, int ck_cap, double *d_S,
+                           int32_t *d_status, int32_t *d_nsteps, void *stream) {
+    if (!c || !d_S || !d_status || !d_hist || !d_hist_n || !d_ck || n_cosmo < 1) {
+        set_error("cmb_perturb_checkpoint: NULL argument");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    std::vector<int> base(n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) base[i] = i;
+    Ckpt ck;
+    ck.ck = d_ck;
+    ck.every = every;
+    ck.cap = ck_cap;
+    int rc = perturb_hist(c, tabs, n_cosmo, base, d_hist, d_hist_n, hist_cap, replay != 0, d_S, d_status, d_nsteps,
+                          (hipStream_t)stream, ck);
+    if (rc == CMB_OK) set_error("");
+    return rc;
+}
+
+int cmb_perturb_segment(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, const double *d_hist,
+                        const int32_t *d_hist_n, int hist_cap, int every, const double *d_ck, int ck_cap, int seg,
+                        double *d_S, int32_t *d_status, int32_t *d_nsteps, void *stream) {
+    if (!c || !d_S || !d_status || !d_hist || !d_hist_n || !d_ck || n_cosmo < 1) {
+        set_error("cmb_perturb_segment: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (seg < 0) {
+        set_error("cmb_perturb_segment: seg < 0");
+        return CMB_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    std::vector<int> base(n_cosmo);
+    for (int i = 0; i < n_cosmo; ++i) base[i] = i;
+    Ckpt ck;
+    ck.ck = const_cast<double *>(d_ck);
+    ck.every = every;
+    ck.cap = ck_cap;
+    ck.seg = seg;
+    int rc = perturb_hist(c, tabs, n_cosmo, base, const_cast<double *>(d_hist), const_cast<int32_t *>(d_hist_n),
+                          hist_cap, true, d_S, d_status, d_nsteps, (hipStream_t)stream, ck);
     if (rc == CMB_OK) set_error("");
     return rc;
 }

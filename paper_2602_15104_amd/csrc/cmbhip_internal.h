@@ -55,6 +55,15 @@ struct DevTab {
     double *hist_out;
     int *hist_out_n;
     int hist_cap, hist_pad;
+    // trajectory checkpoints [n_k][ck_cap][1 + 2 N] (ln a, the N state rows,
+    // the stage derivative the next step starts from) at the start and after
+    // every ck_every-th accepted step, written to ck_out; with ck_in (and
+    // hist_in), each mode replays only its accepted steps
+    // ck_seg ck_every + 1 .. (ck_seg + 1) ck_every from checkpoint ck_seg and
+    // writes only the outputs those steps reach; NULL when unused
+    double *ck_out;
+    const double *ck_in;
+    int ck_every, ck_cap, ck_seg, ck_pad;
     double L0, inv_dl;
     int n_tab, n_k, n_tau, pad;
     double tau0, R_nu;

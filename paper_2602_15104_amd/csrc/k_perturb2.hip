@@ -556,7 +556,28 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double *hin = (HIST && tb.hist_in) ? tb.hist_in + (size_t)ik * tb.hist_cap : nullptr;
     const int hin_n = hin ? min(tb.hist_in_n[ik], tb.hist_cap - 1) : 0;
     double *hout = (HIST && tb.hist_out) ? tb.hist_out + (size_t)ik * tb.hist_cap : nullptr;
-    const double t0 = hin ? hin[0] : tb.lna_start[ik];
+    // trajectory checkpoints: ckp receives (ln a, state rows, carried stage
+    // derivative) at the start and after every ck_every-th accepted step;
+    // cks, when set, is the checkpoint this mode's segment of the replay
+    // starts from (accepted steps na0 + 1 .. na_end)
+    const int ck_stride = 1 + 2 * L.N;
+    const double *cks = (HIST && hin && tb.ck_in)
+                            ? tb.ck_in + ((size_t)ik * tb.ck_cap + tb.ck_seg) * ck_stride
+                            : nullptr;
+    double *ckp = (HIST && !cks && tb.ck_out) ? tb.ck_out + (size_t)ik * tb.ck_cap * ck_stride : nullptr;
+    const int na0 = cks ? tb.ck_seg * tb.ck_every : 0;
+    const int na_end = cks ? min(hin_n, na0 + tb.ck_every) : hin_n;
+    if (cks && hin_n <= na0) {  // the mode ended before this segment: nothing to do
+        if (gl == 0 && items) {
+            tb.status[ik] = CMB_K_OK;
+            tb.nsteps[ik] = 0;
+        } else if (gl == 0) {
+            status[(size_t)c * n_k + ik] = CMB_K_OK;
+            nsteps[(size_t)c * n_k + ik] = 0;
+        }
+        return;
+    }
+    const double t0 = cks ? cks[0] : hin ? hin[0] : tb.lna_start[ik];
     const bool small = k < tb.k_split;
     const double rtol = small ? tb.rtol_small : tb.rtol_large;
     const double atol = small ? tb.atol_small : tb.atol_large;
@@ -630,6 +651,16 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         wsync();
     };
     full_rhs(w.y, w.K[0], s);
+    if (cks) {  // a segment continues from its checkpoint's state and derivative
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            if (row < N) {
+                w.y[r] = cks[1 + row];
+                w.K[0][r] = cks[1 + N + row];
+            }
+        }
+    }
 
     // sum over the group's lanes, the same bits in every lane (each step adds
     // two partial sums that every lane of the pair forms in the same order):
@@ -680,7 +711,9 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     };
 
     int jo = 0;
-    if (gl == 0) {
+    if (cks && na0 > 0) {  // outputs up to the checkpoint belong to earlier segments
+        while (jo < n_tau && lo[jo] <= t0) ++jo;
+    } else if (gl == 0) {
         while (jo < n_tau && lo[jo] < t0) {
             So[jo] = 0.0;
             So[n_tau + jo] = 0.0;
@@ -715,8 +748,23 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / 4.0;
     const double b3 = p.dcoeff / 4.0;
     double lEp = 0.0, lEpp = 0.0;  // logs of the previous two accepted error norms
-    int ns = 0, na = 0, st = CMB_K_OK;
+    int ns = 0, na = na0, st = CMB_K_OK;
+    bool seg_open = false;  // a segment stopped at its last step, before a = 1
     if (hout && gl == 0) hout[0] = t0;
+    auto put_ck = [&](int slot) {
+        if (slot >= tb.ck_cap) return;
+        double *q = ckp + (size_t)slot * ck_stride;
+        if (gl == 0) q[0] = t;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            if (row < N) {
+                q[1 + row] = w.y[r];
+                q[1 + N + row] = w.K[0][r];
+            }
+        }
+    };
+    if (ckp) put_ck(0);
 
     while (t < 0.0) {
         if (ns >= p.max_steps) {
@@ -725,8 +773,9 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         }
         bool last = false;
         if (hin) {
-            if (na >= hin_n) {
-                st = CMB_K_MAX_STEPS;
+            if (na >= na_end) {
+                seg_open = na_end < hin_n;
+                st = seg_open ? CMB_K_OK : CMB_K_MAX_STEPS;
                 break;
             }
             h = hin[1 + na];
@@ -1139,6 +1188,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 w.K[0][r] = w.K[5][r];
             }
             t = tn;
+            if (ckp && na % tb.ck_every == 0) put_ck(na / tb.ck_every);
             const double lE = log(fmax(E, 1e-10));
             fac = 0.9 * exp(-(b1 * lE + b2 * lEp + b3 * lEpp));
             fac = fmin(10.0, fmax(0.2, fac));
@@ -1177,7 +1227,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         }
     }
     if (gl == 0) {
-        for (; jo < n_tau; ++jo) {
+        for (; !seg_open && jo < n_tau; ++jo) {
             So[jo] = 0.0;
             So[n_tau + jo] = 0.0;
             So[2 * n_tau + jo] = 0.0;

@@ -41,7 +41,7 @@ def test_exports_match_header(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.abi_version() == 3
+    assert lib.abi_version() == 4
     c, p = lib.defaults()
     # App. A.2 defaults
     assert c["omega_b"] == 0.02237 and c["omega_cdm"] == 0.120 and c["h"] == 0.6736

@@ -871,6 +871,131 @@ def test_record_replay_bitwise(ctx):
     assert np.all(np.isfinite(S3.cpu().numpy()))
 
 
+def _ck_buffers(n, n_k, cap, every, rows):
+    import torch
+    n_slots = (cap - 1) // every + 1
+    return torch.full((n, n_k, n_slots, 1 + 2 * rows), float("nan"), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("massive", [False, True])
+def test_checkpoint_segments_bitwise(ctx, massive):
+    """Trajectory checkpoints every 16 accepted steps: recording with
+    checkpoints equals cmb_perturb bit for bit, a replay writes the same
+    checkpoints, and replaying every segment from its checkpoint (in reverse
+    order, into one buffer) rebuilds the replay's sources bit for bit, each
+    segment writing exactly the outputs its steps reach."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=20, n_tau=100, ell_max=40, k_max=0.1)
+    if massive:
+        wl = _massive(wl, 0.06, 3, 6)
+        cosmos = [wl.cosmo]
+    else:
+        cosmos = W.perturbed_cosmologies(2, seed=17)
+        for cc in cosmos:
+            cc["N_nu_massless"] = 3.0
+    _say("case checkpoint segments, massive =", massive)
+    tabs = [L.Tables(cc, wl.prec, wl.k, wl.n_tau) for cc in cosmos]
+    n, n_k, E = len(tabs), len(wl.k), 16
+    rows = tabs[0].state_rows()
+    cap = wl.prec["max_steps"] + 1
+    S = torch.empty((n, n_k, 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((n, n_k), dtype=torch.int32, device="cuda:0")
+    H = torch.empty((n, n_k, cap), dtype=torch.float64, device="cuda:0")
+    Hn = torch.empty_like(st)
+    ck = _ck_buffers(n, n_k, cap, E, rows)
+    ctx.perturb_checkpoint(tabs, H, Hn, E, ck, S, st)
+    S2 = torch.empty_like(S)
+    st2 = torch.empty_like(st)
+    ck2 = _ck_buffers(n, n_k, cap, E, rows)
+    ctx.perturb_checkpoint(tabs, H, Hn, E, ck2, S2, st2, replay=True)
+    torch.cuda.synchronize()
+    ref = run_gpu(ctx, tabs, 2)
+    hn = Hn.cpu().numpy()
+    ckh = ck.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0) and np.all(st2.cpu().numpy() == 0)
+    assert np.array_equal(S.cpu().numpy(), ref["S"]) and np.array_equal(S2.cpu().numpy(), ref["S"])
+    assert np.array_equal(ckh, ck2.cpu().numpy(), equal_nan=True)
+    n_seg = int(hn.max()) // E + 1
+    ex = [tb.export() for tb in tabs]
+    for i in range(n):
+        for ik in range(n_k):
+            used = hn[i, ik] // E + 1  # slots 0 .. hn // E are written, the rest untouched
+            assert np.all(np.isfinite(ckh[i, ik, :used])) and np.all(np.isnan(ckh[i, ik, used:]))
+            assert ckh[i, ik, 0, 0] == ex[i]["lna_start"][ik] and np.all(np.diff(ckh[i, ik, :used, 0]) > 0)
+    Sseg = torch.full_like(S, float("nan"))
+    ns = torch.empty_like(st)
+    for seg in reversed(range(n_seg)):
+        one = torch.full_like(S, float("nan"))
+        ctx.perturb_segment(tabs, H, Hn, E, ck, seg, one, st2, nsteps=ns)
+        ctx.perturb_segment(tabs, H, Hn, E, ck, seg, Sseg, st2)
+        torch.cuda.synchronize()
+        assert np.all(st2.cpu().numpy() == 0)
+        want_ns = np.clip(hn - seg * E, 0, E)
+        assert np.array_equal(ns.cpu().numpy(), want_ns), seg
+        o = one.cpu().numpy()
+        for i in range(n):
+            for ik in range(n_k):
+                if hn[i, ik] <= seg * E:
+                    assert np.all(np.isnan(o[i, ik]))
+                    continue
+                t_a = ckh[i, ik, seg, 0]
+                t_b = ckh[i, ik, seg + 1, 0] if (seg + 1) * E < hn[i, ik] else np.inf
+                lo = ex[i]["lna_src"]
+                inside = (lo <= t_b) & ((lo > t_a) if seg > 0 else True)
+                assert np.array_equal(o[i, ik][:, inside], ref["S"][i, ik][:, inside]), (seg, i, ik)
+                assert np.all(np.isnan(o[i, ik][:, ~inside])), (seg, i, ik)
+    assert np.array_equal(Sseg.cpu().numpy(), ref["S"])
+
+
+def test_checkpoint_states_parity(ctx):
+    """The checkpoints of a replay of the oracle's own recorded steps against
+    the oracle: ln a bit for bit (the oracle's accepted step ends), the state
+    rows to 1e-8 of each row's largest magnitude, and the carried stage
+    derivative against the oracle's right-hand side at its state to 1e-7
+    (the last stage's derivative is (Y - R)/(h gamma), whose rounding the
+    division by h gamma enlarges)."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=6, n_tau=60, ell_max=20, k_max=0.1)
+    wl.cosmo["N_nu_massless"] = 3.0
+    E = 8
+    t_or = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    _, st_o, _, hist, hn = O.perturb_hist(t_or)
+    assert np.all(st_o == 0)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    rows = tab.state_rows()
+    cap = hist.shape[1]
+    n_k = len(wl.k)
+    H = torch.tensor(hist[None], dtype=torch.float64, device="cuda:0")
+    Hn = torch.tensor(hn[None], dtype=torch.int32, device="cuda:0")
+    S = torch.empty((1, n_k, 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+    st = torch.empty((1, n_k), dtype=torch.int32, device="cuda:0")
+    ck = _ck_buffers(1, n_k, cap, E, rows)
+    ctx.perturb_checkpoint([tab], H, Hn, E, ck, S, st, replay=True)
+    torch.cuda.synchronize()
+    ckh = ck.cpu().numpy()[0]
+    assert np.all(st.cpu().numpy() == 0)
+    order = O.library_row_order(t_or.prec, 0)
+    assert len(order) == rows
+    ey = ek = 0.0
+    for ik in range(n_k):
+        k, lna0 = float(t_or.k[ik]), float(t_or.lna_i[ik])
+        acc = O.perturb_one(t_or, k, lna0, [], acc_cap=cap)["accepted_lna"]
+        assert len(acc) == hn[ik]
+        times = np.concatenate([[lna0], acc[E - 1::E]])
+        assert np.array_equal(ckh[ik, :len(times), 0], times), ik
+        Y = O.perturb_one(t_or, k, lna0, times, want_y=True)["y"]
+        F = np.array([O.rhs(t_or, k, float(tm), y) for tm, y in zip(times, Y)])
+        yg, fg = ckh[ik, :len(times), 1:1 + rows], ckh[ik, :len(times), 1 + rows:]
+        yo, fo = Y[:, order], F[:, order]
+        ey = max(ey, float(np.max(np.abs(yg - yo) / (np.max(np.abs(yo), axis=0) + 1e-300))))
+        ek = max(ek, float(np.max(np.abs(fg - fo) / (np.max(np.abs(fo), axis=0) + 1e-300))))
+    _say("checkpoint state err", ey, "stage derivative err", ek)
+    assert ey <= 1e-8 and ek <= 1e-7
+
+
 @pytest.mark.parametrize("order", [4, 2])
 def test_jacobian_parity(ctx, order):
     """cmb_jacobian against the oracle's frozen-step derivatives for two
@@ -1222,3 +1347,17 @@ def test_new_entry_points_reject_bad_arguments(ctx):
     assert e.value.name == "CMB_E_INVALID"
     with pytest.raises(L.CmbError):
         ctx.sources_adjoint([tab], S, None)
+    cap = wl.prec["max_steps"] + 1
+    Hf = torch.zeros((1, 8, cap), dtype=torch.float64, device=dev)
+    Hn = torch.zeros((1, 8), dtype=torch.int32, device=dev)
+    rows = tab.state_rows()
+    few = torch.zeros((1, 8, 2, 1 + 2 * rows), dtype=torch.float64, device=dev)  # too few checkpoint slots
+    ck = torch.zeros((1, 8, (cap - 1) // 64 + 1, 1 + 2 * rows), dtype=torch.float64, device=dev)
+    for every, buf in ((0, ck), (64, few)):
+        with pytest.raises(L.CmbError) as e:
+            ctx.perturb_checkpoint([tab], Hf, Hn, every, buf, S, st)
+        assert e.value.name == "CMB_E_INVALID"
+    for seg in (-1, ck.shape[-2]):
+        with pytest.raises(L.CmbError) as e:
+            ctx.perturb_segment([tab], Hf, Hn, 64, ck, seg, S, st)
+        assert e.value.name == "CMB_E_INVALID"

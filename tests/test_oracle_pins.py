@@ -925,6 +925,30 @@ def test_replay_reproduces_run(jac_case):
     assert np.array_equal(S2, S) and np.all(ns2 == hn)
 
 
+def test_restart_from_step_end_continues_run(jac_case):
+    """A trajectory checkpoint is the state at the end of an accepted step:
+    restarting there (the state as start, the remaining recorded steps
+    replayed) continues the run bit for bit after the restart (the oracle
+    forms every stage derivative as the right-hand side at the stage value,
+    so the derivative it recomputes at the restart is the one it would have
+    carried), and writes nothing before it."""
+    wl = jac_case
+    t = O.build_tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    S, st, ns, hist, hn = O.perturb_hist(t)
+    lo = np.asarray(t.lna_src)
+    for ik in (3, 15):
+        k, lna0 = float(t.k[ik]), float(t.lna_i[ik])
+        acc = O.perturb_one(t, k, lna0, [], acc_cap=hist.shape[1])["accepted_lna"]
+        for j in (max(1, int(hn[ik]) // 3), 2 * int(hn[ik]) // 3):
+            tc = float(acc[j - 1])
+            yc = O.perturb_one(t, k, lna0, [tc], want_y=True)["y"][0]
+            r = O.perturb_one(t, k, tc, lo, y0=yc, fixed=np.concatenate([[tc], hist[ik, 1 + j:1 + hn[ik]]]))
+            assert r["status"] == 0 and r["naccept"] == hn[ik] - j
+            after = lo > tc
+            assert np.all(r["S"][:, ~after] == 0.0)
+            assert np.array_equal(r["S"][:, after], S[ik][:, after]), (ik, j)
+
+
 def test_jacobian_stencils_consistent(jac_case):
     """Frozen steps make the discrete map smooth: the five-point derivative at
     rel 1e-4 and at 2e-4 agree to 1e-6 of each row (measured <= 1.6e-7), and
