@@ -249,8 +249,9 @@ int cmb_perturb_replay(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo,
  * (status 0, count 0); status CMB_K_MAX_STEPS when the history ends inside
  * the segment before a = 1.  d_ck must come from cmb_perturb_checkpoint
  * with the same tables, history, every and ck_cap.
- * Needs every >= 1, ck_cap >= (hist_cap - 1) / every + 1 and
- * 0 <= seg < ck_cap (else CMB_E_INVALID); otherwise errors as cmb_perturb. */
+ * Needs every >= 1, ck_cap >= (hist_cap - 1) / every + 1,
+ * 0 <= seg < ck_cap and seg * every < hist_cap (else CMB_E_INVALID);
+ * otherwise errors as cmb_perturb. */
 int cmb_perturb_checkpoint(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int replay, double *d_hist,
                            int32_t *d_hist_n, int hist_cap, int every, double *d_ck, int ck_cap, double *d_S,
                            int32_t *d_status, int32_t *d_nsteps, void *hip_stream);

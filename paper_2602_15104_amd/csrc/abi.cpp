@@ -834,9 +834,12 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
         return CMB_E_INVALID;
     }
     const size_t ck_rec = ck.ck ? (size_t)ck.cap * (1 + 2 * (size_t)cmbhip::state_rows(b.prec)) : 0;
-    if (ck.ck && (ck.every < 1 || ck.cap < (cap - 1) / ck.every + 1 || ck.seg >= ck.cap || (ck.seg >= 0 && !replay))) {
-        set_error("checkpoints: need every >= 1, ck_cap >= (hist_cap - 1) / every + 1, 0 <= seg < ck_cap, and a "
-                  "segment only from a replay");
+    if (ck.ck && (ck.every < 1 || ck.cap < (cap - 1) / ck.every + 1 || ck.seg >= ck.cap || (ck.seg >= 0 && !replay) ||
+                  (long long)ck.seg * ck.every >= cap)) {
+        // (the last condition also keeps seg * every, the segment's first step
+        // index in the kernel, inside int)
+        set_error("checkpoints: need every >= 1, ck_cap >= (hist_cap - 1) / every + 1, 0 <= seg < ck_cap, "
+                  "seg * every < hist_cap, and a segment only from a replay");
         return CMB_E_INVALID;
     }
     rc = upload(c, tabs, n, s);

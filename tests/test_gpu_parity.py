@@ -1361,3 +1361,8 @@ def test_new_entry_points_reject_bad_arguments(ctx):
         with pytest.raises(L.CmbError) as e:
             ctx.perturb_segment([tab], Hf, Hn, 64, ck, seg, S, st)
         assert e.value.name == "CMB_E_INVALID"
+    roomy = torch.zeros((1, 8, 1000, 1 + 2 * rows), dtype=torch.float64, device=dev)
+    for every, seg in ((64, cap // 64 + 1), (1 << 30, 4)):  # past the history; past int range
+        with pytest.raises(L.CmbError) as e:
+            ctx.perturb_segment([tab], Hf, Hn, every, roomy, seg, S, st)
+        assert e.value.name == "CMB_E_INVALID"
