@@ -163,7 +163,9 @@ int cmb_perturb_pk(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, dou
  *   d_Delta: device, [n_cosmo][2][ell_max-1][n_k] doubles (Delta_T, Delta_E
  *            for ell = 2..ell_max, k fastest); the E plane is written as 0
  *            when the tables have no polarisation hierarchy.
- * Bessel functions by recurrence on the GPU; ell_max in [2, 10000].
+ * Bessel functions by recurrence on the GPU; ell_max in [2, 10000]
+ * (else CMB_E_INVALID) and n_tau <= 4096 (else CMB_E_UNSUPPORTED: each
+ * 256-lane workgroup holds at most 16 output times per lane).
  */
 int cmb_los(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
             double *d_Delta, void *hip_stream);

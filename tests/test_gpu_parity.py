@@ -140,6 +140,51 @@ def test_los_cl_from_same_sources(ctx):
     np.testing.assert_allclose(C.cpu().numpy()[0][:, 2:], Co[:, 2:], rtol=1e-12, atol=0)
 
 
+def test_los_cl_maximum_sizes(ctx):
+    """K2 + K3 at the largest sizes the projection accepts: l_max = 10000 and
+    4096 output times, on seeded sources, for five k from 1e-4 to 0.8 Mpc^-1
+    (k chi up to 11000: the upward-recurrence seeding for x > l_max + 32, and
+    Miller's seeding with the cut below it).  Delta against the oracle's
+    projection to 1e-9 of each k's largest value, C_l against the oracle's
+    quadrature of the same Delta to 1e-12; 4097 output times are refused
+    (CMB_E_UNSUPPORTED)."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.config0()
+    wl.prec["ell_pol"] = 6  # a polarisation hierarchy, so that K2 writes the E plane
+    k = np.array([1e-4, 3e-3, 0.05, 0.3, 0.8])
+    n_tau, lmax = 4096, 10000
+    _say("case los maximum sizes: l_max", lmax, "n_tau", n_tau, "k", k)
+    tab = L.Tables(wl.cosmo, wl.prec, k, n_tau)
+    t_or = O.build_tables(wl.cosmo, wl.prec, k, n_tau)
+    rng = np.random.Generator(np.random.PCG64(9))
+    S = rng.standard_normal((1, len(k), 3, n_tau))
+    D = torch.empty((1, 2, lmax - 1, len(k)), dtype=torch.float64, device="cuda:0")
+    C = torch.empty((1, 3, lmax + 1), dtype=torch.float64, device="cuda:0")
+    ctx.los([tab], lmax, torch.tensor(S, device="cuda:0"), D)
+    ctx.cl([tab], lmax, D, C)
+    torch.cuda.synchronize()
+    DT, DE = O.los(t_or, S[0], lmax, True)
+    Dg = D.cpu().numpy()[0]
+    worst = 0.0
+    for ik in range(len(k)):
+        for plane, ref in ((0, DT), (1, DE)):
+            den = np.max(np.abs(ref[:, ik]))
+            e = np.max(np.abs(Dg[plane][:, ik] - ref[:, ik])) / den
+            worst = max(worst, e)
+            assert e <= 1e-9, (plane, ik, e)
+    Co = O.cl(k, Dg[0], Dg[1], lmax, True, wl.cosmo["A_s"], wl.cosmo["n_s"])
+    np.testing.assert_allclose(C.cpu().numpy()[0][:, 2:], Co[:, 2:], rtol=1e-12, atol=0)
+    _say("max-size projection err", worst)
+    big = L.Tables(wl.cosmo, wl.prec, k[:2], n_tau + 1)
+    Sb = torch.zeros((1, 2, 3, n_tau + 1), dtype=torch.float64, device="cuda:0")
+    Db = torch.empty((1, 2, lmax - 1, 2), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(L.CmbError) as e:
+        ctx.los([big], lmax, Sb, Db)
+    assert e.value.name == "CMB_E_UNSUPPORTED"
+
+
 def test_spike_source_closed_form_gpu(ctx):
     """A unit-weight spike of S_T0 at one output time: Delta_l(k) = j_l(k chi*)
     and, with n_s = 1, l(l+1) C_l/(2 pi A_s) = 1 up to k-quadrature error."""
