@@ -427,6 +427,41 @@ def test_config2_full_size(ctx):
         assert np.max(np.abs(g["nsteps"][0] - nso)) <= 2
 
 
+@pytest.mark.parametrize("ell", [60, 110])
+def test_hierarchy_size_limits(ctx, ell):
+    """Massless hierarchies at the cooperative kernel's edges: l_gamma = l_pol
+    = l_nu = 60 gives N = 187 rows, the widest group (64 lanes of five rows,
+    one mode per wavefront); 110 gives N = 337, beyond any group, which
+    cmb_perturb hands to the lane-per-mode kernel (step histories, built into
+    the cooperative kernel only, are refused).  Four modes up to k = 0.05,
+    sources to 1e-8 and C_l to 1e-6 of the oracle's."""
+    import torch
+    import oracle as O
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=4, n_tau=60, ell_max=40, k_max=0.05)
+    wl.cosmo["N_nu_massless"] = 3.0
+    wl.prec.update(ell_gamma=ell, ell_pol=ell, ell_nu=ell)
+    _say("case hierarchy l =", ell)
+    tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
+    assert tab.state_rows() == 3 * ell + 7
+    g = run_gpu(ctx, [tab], wl.ell_max)
+    r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True)
+    assert np.all(g["status"] == 0) and np.all(r["status"] == 0)
+    e = src_err(g["S"][0], r["S"])
+    tt, te, ee = cl_err(g["Cl"][0], r["Cl"])
+    _say("source err", e, "cl err", tt, te, ee, "steps", g["nsteps"][0], r["nsteps"])
+    assert e <= 1e-8
+    assert tt <= 1e-6 and te <= 1e-6 and ee <= 1e-6
+    if ell == 110:
+        n_k = len(wl.k)
+        S = torch.empty((1, n_k, 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+        st = torch.empty((1, n_k), dtype=torch.int32, device="cuda:0")
+        H = torch.empty((1, n_k, wl.prec["max_steps"] + 1), dtype=torch.float64, device="cuda:0")
+        with pytest.raises(L.CmbError) as ex:
+            ctx.perturb_record([tab], S, st, H, st)
+        assert ex.value.name == "CMB_E_UNSUPPORTED"
+
+
 def test_lane_per_mode_variant_parity(ctx):
     """The lane-per-mode perturbation kernel (CMBHIP_K1=lane) gives the same
     sources as the oracle and as the default cooperative kernel."""
