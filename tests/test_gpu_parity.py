@@ -1386,6 +1386,37 @@ def test_autograd_cl_of_params(ctx):
             assert abs(g[i, p] - ref) <= 1e-6 * scale, (i, p)
 
 
+def test_batch_consistency_errors(ctx):
+    """An empty batch, and batches whose cosmologies differ in n_k, n_tau or
+    the hierarchy, are CMB_E_INVALID at every batched entry point of the path
+    (K1, K2, K3 and the whole solve), and nothing is written: the outputs keep
+    their sentinels."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.small_case(n_k=8, n_tau=40, ell_max=20)
+    a = L.Tables(wl.cosmo, wl.prec, wl.k, 40)
+    other_k = L.Tables(wl.cosmo, wl.prec, wl.k[:7], 40)
+    other_tau = L.Tables(wl.cosmo, wl.prec, wl.k, 41)
+    pr = dict(wl.prec)
+    pr["ell_gamma"] += 1
+    other_h = L.Tables(wl.cosmo, pr, wl.k, 40)
+    dev = "cuda:0"
+    S = torch.full((2, 8, 3, 41), float("nan"), dtype=torch.float64, device=dev)
+    st = torch.full((2, 8), -7, dtype=torch.int32, device=dev)
+    D = torch.full((2, 2, 19, 8), float("nan"), dtype=torch.float64, device=dev)
+    C = torch.full((2, 3, 21), float("nan"), dtype=torch.float64, device=dev)
+    for tabs in ([], [a, other_k], [a, other_tau], [a, other_h]):
+        calls = (lambda: ctx.perturb(tabs, S, st), lambda: ctx.los(tabs, 20, S, D),
+                 lambda: ctx.cl(tabs, 20, D, C), lambda: ctx.solve(tabs, 20, C, st, S=S, Delta=D))
+        for call in calls:
+            with pytest.raises(L.CmbError) as e:
+                call()
+            assert e.value.name == "CMB_E_INVALID", (len(tabs), e.value)
+    torch.cuda.synchronize()
+    assert torch.isnan(S).all() and torch.isnan(D).all() and torch.isnan(C).all()
+    assert (st == -7).all()
+
+
 def test_new_entry_points_reject_bad_arguments(ctx):
     """Argument errors of the lensing, derivative and variant entry points
     come back as CmbError (CMB_E_INVALID) without touching the device."""
