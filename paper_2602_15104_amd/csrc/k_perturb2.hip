@@ -84,6 +84,7 @@ struct Bk {  // background and per-stage constants at one ln a
     double invHc, kH, k2H, T, R, trunc, cH1, cH2, cE;
     double am, pn4;  // massive nu: a m/T and pref/a^4 (rho = pn4 sum W eps)
 };
+static_assert(sizeof(Bk) == 23 * sizeof(double), "Bk is a record of 23 doubles");
 
 // massive-neutrino node energy and dln f0/dln q for f0 = 1/(e^q + 1)
 __device__ inline double eps_of(double q, double am) { return sqrt(fma(q, q, am * am)); }
@@ -308,6 +309,7 @@ constexpr int PADR = 8;  // spare records before row 0 and after the last row
 struct Slab {
     double *base;  // record of row r at base + (r + PADR) * STR
     double *AX;    // exchange area
+    double *BK;    // the current step's stage backgrounds, NBK doubles each
     __device__ double *rec(int row) const { return base + (row + PADR) * STR; }
     __device__ double &ry(int row) const { return base[(row + PADR) * STR + F_RY]; }
 };
@@ -315,8 +317,14 @@ struct Slab {
 // exchange area per mode: couplings (4) and the 4 x 4 top-row affine maps of
 // every chain, rounded to an even count (16-byte alignment of the next slab)
 __host__ __device__ constexpr int ax_doubles(int nch) { return (4 + 16 * nch + 1) & ~1; }
-// doubles of LDS per mode for NP rows
-__host__ __device__ constexpr int slab_doubles(int NP, int nch) { return (NP + 2 * PADR) * STR + ax_doubles(nch); }
+// one stage's background record (a Bk, padded to an even count)
+constexpr int NBK = 24;
+static_assert(NBK * sizeof(double) >= sizeof(Bk), "a stage record holds a Bk");
+// doubles of LDS per mode for NP rows: records, exchange area, and the
+// backgrounds of the five implicit stages
+__host__ __device__ constexpr int slab_doubles(int NP, int nch) {
+    return (NP + 2 * PADR) * STR + ax_doubles(nch) + 5 * NBK;
+}
 
 // Time-independent multipliers of a generic chain row (fifth row of its chain
 // onward): a = CA v, c = CC v, d = CD trunc - T (photon chains) or CD trunc,
@@ -519,6 +527,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         double *base = lds + (size_t)grp * slab_doubles(NP, L.nch);
         m.base = base;
         m.AX = base + (NP + 2 * PADR) * STR;
+        m.BK = m.AX + ax_doubles(L.nch);
         // every record, pads included, starts from zero; then the multipliers
         for (int i = gl; i < (NP + 2 * PADR) * STR; i += G) base[i] = 0.0;
         wsync();
@@ -785,9 +794,18 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             last = true;
         }
         const double g = h * GAMMA;
+        // the backgrounds of the step's five implicit stages, evaluated at once
+        // on five lanes of the group (instead of one stage after the other on
+        // every lane) and read back from LDS stage by stage
+        for (int si = 1 + gl; si < 6; si += G) {
+            const double ts = (si == 5) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
+            Bk b;
+            bk_at<MNU>(tb, p, k, ts, b);
+            __builtin_memcpy(m.BK + (si - 1) * NBK, &b, sizeof(Bk));
+        }
+        wsync();
         for (int si = 1; si < 6; ++si) {
-            double ts = (si == 5) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
-            bk_at<MNU>(tb, p, k, ts, s);
+            __builtin_memcpy(&s, m.BK + (si - 1) * NBK, sizeof(Bk));
             // stage weights h a_sj for j < s (zero otherwise): fixed-length sums keep
             // every register index static
             double hA[5];
