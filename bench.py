@@ -141,6 +141,52 @@ def cpu_baseline(wl, every: int = 1):
                       + (f", scaled x{scale:.0f}" if every > 1 else "")}
 
 
+def config2_sweep(ctx, batches):
+    """Config 2 (config 1 plus one 0.06 eV neutrino: 12 momentum nodes with
+    l <= 17, N = 295 rows, 600 modes): K1, K2, K3 of one batch timed with
+    HIP events (median of the timed repeats after one untimed) and the
+    spectra/s they give, per batch size."""
+    import cmb_workloads as W
+    import paper_2602_15104_amd as L
+    import torch
+    wl = W.config2()
+    rows = []
+    for B in batches:
+        cosmos = W.perturbed_cosmologies(B, seed=20260215)
+        for c in cosmos:
+            for key in ("N_nu_massless", "Neff", "N_nu_massive", "m_nu_massive"):
+                if key in wl.cosmo:
+                    c[key] = wl.cosmo[key]
+        t0 = time.perf_counter()
+        tabs = [L.Tables(c, wl.prec, wl.k, wl.n_tau) for c in cosmos]
+        t_tab = (time.perf_counter() - t0) / B
+        n_k = len(wl.k)
+        S = torch.empty((B, n_k, 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
+        st = torch.empty((B, n_k), dtype=torch.int32, device="cuda:0")
+        D = torch.empty((B, 2, wl.ell_max - 1, n_k), dtype=torch.float64, device="cuda:0")
+        C = torch.empty((B, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        res = []
+        for r in range(3):
+            ev[0].record()
+            ctx.perturb(tabs, S, st)
+            ev[1].record()
+            ctx.los(tabs, wl.ell_max, S, D)
+            ev[2].record()
+            ctx.cl(tabs, wl.ell_max, D, C)
+            ev[3].record()
+            torch.cuda.synchronize()
+            res.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+        k1, k2, k3 = (float(v) for v in np.median(np.array(res[1:]), axis=0))
+        rows.append({"batch": B, "spectra_per_s": 1000.0 * B / (k1 + k2 + k3), "perturb_ms": k1, "los_ms": k2,
+                     "cl_ms": k3, "host_table_ms_per_cosmology": 1000.0 * t_tab,
+                     "modes_not_ok": int((st != 0).sum().item())})
+        print(f"[bench] config 2, batch {B}: {rows[-1]['spectra_per_s']:.1f} spectra/s", file=sys.stderr, flush=True)
+        del S, st, D, C, tabs
+    return {"workload": "config 1 + one 0.06 eV neutrino (12 momentum nodes, l <= 17), N = 295 rows, 600 modes, "
+                        "2000 output times, l <= 2500", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +200,8 @@ def main():
                     help="Poisson serving workload: requests replayed (0 = skip)")
     ap.add_argument("--serving-plain-requests", type=int, default=128,
                     help="the same arrivals served one request at a time (0 = skip)")
+    ap.add_argument("--config2", type=str, default="",
+                    help="also time config 2 (massive neutrino) at these comma-separated batch sizes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -463,6 +511,8 @@ def main():
             out["serving_plain"] = serve(sub, wl.prec, wl.n_tau, max_batch=1, n_streams=1)
             print(f"[bench] serving one-at-a-time p50 {out['serving_plain']['p50_ms']:.1f} ms", file=sys.stderr,
                   flush=True)
+    if args.config2:
+        out["config2"] = config2_sweep(ctx, [int(b) for b in args.config2.split(",")])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
