@@ -18,8 +18,9 @@
  *   - adiabatic superhorizon initial conditions, leading order in k tau
  *     (Ma & Bertschinger 1995, eqs. 96 and 97), normalised to eta -> 1;
  *   - an ESDIRK time stepper: the six-stage, order-4, L-stable, stiffly
- *     accurate scheme of Kennedy & Carpenter (ESDIRK4(3)6L[2]SA) with its
- *     order-3 embedded estimate; every implicit stage is one linear solve of
+ *     accurate implicit part of Kennedy & Carpenter's additive scheme
+ *     ARK4(3)6L[2]SA (Appl. Numer. Math. 44, 2003) with its order-3 embedded
+ *     estimate; every implicit stage is one linear solve of
  *     (I - h gamma A) Y = R because the system is linear, done here on the
  *     dense matrix A (built column by column from f) by Gaussian elimination
  *     with partial pivoting and two steps of iterative refinement;
@@ -388,7 +389,7 @@ static int lu_solve(int N, const double *M, double *r, double *LU, int *piv, dou
 }
 
 /* ------------------------------------------------------------------------- */
-/* ESDIRK4(3)6L[2]SA (Kennedy & Carpenter), gamma = 1/4                        */
+/* ESDIRK: implicit part of ARK4(3)6L[2]SA (Kennedy & Carpenter 2003), gamma = 1/4 */
 /* ------------------------------------------------------------------------- */
 static const double RK_c[6] = {0.0, 0.5, 83.0 / 250.0, 31.0 / 50.0, 17.0 / 20.0, 1.0};
 static const double RK_A[6][6] = {

@@ -1,7 +1,7 @@
 // K1 (cooperative variant): synchronous-gauge perturbations and CMB sources,
 // one group of G lanes per (cosmology, k) mode.
 //
-// Same method as k_perturb.hip (ESDIRK4(3)6L[2]SA, RMS norm, PID control,
+// Same method as k_perturb.hip (the ESDIRK of ARK4(3)6L[2]SA, RMS norm, PID control,
 // Hermite dense output, source functions of App. B.4 of arXiv 2602.15104;
 // equations of App. B.3 and App. C), mapped differently onto the hardware:
 //
