@@ -43,6 +43,17 @@ def k1_flops_per_step(N: int, n_chains: int = 3) -> float:
 
 
 K1_FLOPS_PER_OUTPUT = 250.0  # Hermite interpolation of 12 rows + source formulas
+
+
+def k1_flops_per_step_scope(N: int) -> float:
+    """The algorithmic work per ESDIRK step that the hot path's scope sets for
+    the structured stage solve of a banded hierarchy (bandwidth b = 3, s = 6
+    stages): per implicit stage the right-hand side A y (12 N), assembling
+    I - h gamma A (7 N), the banded LU (18 N), three triangular solves (36 N),
+    the rank-2 Woodbury correction (6 N) and the stage combination (12 N),
+    about 90 N; six stages plus the error estimate, 560 N per step.  The
+    roofline fraction of the perturbation kernel is quoted on this count."""
+    return 560.0 * N
 K2_FLOPS_PER_TRIPLE = 13.0   # recurrence (3) + T projection (8) + E projection (2)
 K2_FLOPS_PER_SEED_STEP = 3.0
 
@@ -85,6 +96,42 @@ def k1_traffic(batch: int):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, OSError, ValueError):
         return None
+
+
+def k_fp64_measured(batch: int):
+    """FP64 operations per launch of each kernel from the committed rocprofv3
+    counter summary (VALU FP64 instruction counters times the active lanes
+    per instruction), or None when that summary was taken on other kernel
+    sources or another batch size."""
+    path = os.path.join(ROOT, "profiles", "fp64_config1_b32_counters.md")
+    if batch != 32 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ": " in line and not line.startswith(("|", " ", "#", "-")):
+            k, v = line.strip().split(": ", 1)
+            kv[k] = v
+    try:
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in kv["source_files"].split()))
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        out = {}
+        for k in ("perturb", "los"):
+            if f"{k}_fp64_flops_per_launch" in kv:
+                out[k] = {"flops_per_launch": float(kv[f"{k}_fp64_flops_per_launch"]), "what": kv.get("what", "")}
+        return out or None
+    except (KeyError, OSError, ValueError):
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serve(reqs, prec, n_tau, max_batch, n_streams, n_workers=8):
@@ -136,6 +183,7 @@ def cpu_baseline(wl, every: int = 1):
     sec_per_spectrum = dt * scale
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / sec_per_spectrum, "unit": "spectra/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
             "sample": f"one fiducial spectrum: {len(idx)} of {len(wl.k)} modes, all {wl.n_tau} output times, "
                       f"l<=2500 (tables, perturbations, projection, quadrature); {dt:.1f} s measured"
                       + (f", scaled x{scale:.0f}" if every > 1 else "")}
@@ -456,9 +504,13 @@ def main():
               f"checkpoints {variants['checkpoints']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s",
               file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (algorithmic flops / measured duration)
+    # roofline of the dominant kernel (algorithmic flops / measured duration):
+    # the perturbation kernel on the scope's count of 560 N per step (the
+    # reported fraction), and beside it on the count of what this kernel's
+    # continuant solve executes (fewer operations for the same solution)
     exs = [t.export() for t in tabs]
-    f_k1 = float(np.sum(nsteps)) * k1_flops_per_step(N) + B * n_k * n_tau * K1_FLOPS_PER_OUTPUT
+    f_k1 = float(np.sum(nsteps)) * k1_flops_per_step_scope(N)
+    f_k1_exec = float(np.sum(nsteps)) * k1_flops_per_step(N) + B * n_k * n_tau * K1_FLOPS_PER_OUTPUT
     f_k2 = sum(k2_flops(e["k"], e["chi_src"], lmax) for e in exs)
     f_k3 = 12.0 * B * (lmax - 1) * n_k
     avg = {k: float(np.mean(v)) for k, v in kt.items()}
@@ -467,6 +519,17 @@ def main():
     achieved = flops[dom] / (avg[dom] * 1e-3) / 1e12
     per_kernel = {k: {"ms": avg[k], "tflops": flops[k] / (avg[k] * 1e-3) / 1e12,
                       "frac_fp64_peak": flops[k] / (avg[k] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS} for k in avg}
+    per_kernel["perturb"]["count"] = "560 N flops per ESDIRK step (banded LU + Woodbury stage solve), N = %d" % N
+    per_kernel["perturb"]["tflops_executed_count"] = f_k1_exec / (avg["perturb"] * 1e-3) / 1e12
+    per_kernel["perturb"]["frac_executed_count"] = per_kernel["perturb"]["tflops_executed_count"] / FP64_PEAK_TFLOPS
+    per_kernel["perturb"]["executed_count"] = ("%.0f flops per step (continuant stage solve as executed) + %.0f per "
+                                               "output time" % (k1_flops_per_step(N), K1_FLOPS_PER_OUTPUT))
+    fp64_meas = k_fp64_measured(B)
+    if fp64_meas:
+        for k, v in fp64_meas.items():
+            if k in per_kernel:
+                per_kernel[k]["tflops_counters"] = v["flops_per_launch"] / (avg[k] * 1e-3) / 1e12
+                per_kernel[k]["counters"] = v["what"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -495,7 +558,10 @@ def main():
         "variants": variants,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": k1_traffic(B) if dom == "perturb" else None},
+                     "traffic": k1_traffic(B) if dom == "perturb" else None,
+                     "count": per_kernel[dom].get("count", "algorithmic flops of the kernel"),
+                     "frac_executed_count": per_kernel[dom].get("frac_executed_count"),
+                     "achieved_counters": per_kernel[dom].get("tflops_counters")},
     }
     if args.serving_requests > 0:
         reqs = W.serving_requests(args.serving_requests, rate_hz=50.0, seed=20260215)
@@ -506,6 +572,13 @@ def main():
                                       "config-1 hierarchy; latency = arrival to spectra on the host, incl. host tables")
         print(f"[bench] serving p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)
+        # capacity: the same requests arriving 40 times faster (2000/s), so the
+        # runtime is saturated and throughput is what it can serve
+        fast = [dict(r, arrival_s=r["arrival_s"] / 40.0) for r in reqs]
+        out["serving_saturated"] = serve(fast, wl.prec, wl.n_tau, max_batch=64, n_streams=2)
+        out["serving_saturated"]["workload"] = "the same 512 requests, arrivals compressed 40x (2000/s offered)"
+        print(f"[bench] serving saturated: {out['serving_saturated']['throughput_per_s']:.1f} requests/s, "
+              f"p50 {out['serving_saturated']['p50_ms']:.1f} ms", file=sys.stderr, flush=True)
         if args.serving_plain_requests > 0:
             sub = reqs[:args.serving_plain_requests]
             out["serving_plain"] = serve(sub, wl.prec, wl.n_tau, max_batch=1, n_streams=1)

@@ -88,7 +88,10 @@ K_TRANSITION = 0.45 / 170.0  # Mpc^-1, log->linear transition of the step law
 
 
 def log_grid(k_min: float, k_max: float, n: int) -> np.ndarray:
-    """n points spaced uniformly in log k, both ends included."""
+    """n points spaced uniformly in log k, both ends included (n = 1: k_min
+    alone)."""
+    if n == 1:
+        return np.array([float(k_min)])
     i = np.arange(n, dtype=np.float64)
     return k_min * (k_max / k_min) ** (i / (n - 1))
 
@@ -175,6 +178,33 @@ def config2() -> Workload:
     c["m_nu_massive"] = 0.06
     return Workload("config2_mnu_l2500", c, prec_for(24, 24, 24, n_q=12, ell_ncdm=17, max_steps=4096), step_law_grid(1e-5, 0.5, 600),
                     2000, 2500, True, "config1 + 1 massive nu 0.06 eV, 12 q x ell<=17, 600 k, 2000 tau")
+
+
+def tight(wl: Workload, rtol: float = 1e-10, max_steps: int = 400000) -> Workload:
+    """The same workload at a much tighter tolerance: rtol for both k ranges,
+    each atol scaled by the same factor as its rtol (so atol/rtol keeps the
+    paper's ratio), and room for the many more steps."""
+    w = copy.deepcopy(wl)
+    p = w.prec
+    p["atol_small"] = p["atol_small"] * rtol / p["rtol_small"]
+    p["atol_large"] = p["atol_large"] * rtol / p["rtol_large"]
+    p["rtol_small"] = p["rtol_large"] = rtol
+    p["max_steps"] = max_steps
+    w.name = wl.name + f"_rtol{rtol:g}"
+    return w
+
+
+# config-1 modes of the tight-tolerance cross-check (spread over the grid,
+# both tolerance ranges, the largest k included)
+CONFIG1_SUBSET = (0, 50, 100, 150, 200, 250, 300, 399)
+
+
+def config1_subset(idx=CONFIG1_SUBSET) -> Workload:
+    """Config 1 physics on a subset of its k grid."""
+    w = config1()
+    w.k = np.ascontiguousarray(w.k[list(idx)])
+    w.name = w.name + f"_subset{len(idx)}"
+    return w
 
 
 def small_case(n_k: int = 12, n_tau: int = 120, ell_max: int = 60, polarization: bool = True,

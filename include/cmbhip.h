@@ -123,8 +123,11 @@ int cmb_tables_export(const cmb_tables *t, cmb_table_view *out);
 /* ---------------------------------------------------------------- device */
 /* A context binds one HIP device and owns the device workspace (table
  * copies, integrator scratch), grown on demand up to hbm_budget_bytes
- * (0 = 16 GiB).  One context per host thread.  Errors: CMB_E_DEVICE,
- * CMB_E_INVALID. */
+ * (0 = 16 GiB).  One context per host thread.  Calls on one context may name
+ * different streams: each call's device work is queued after the device work
+ * of the context's previous call (its stream waits for an event the previous
+ * call recorded), because calls reuse and regrow the context's buffers; work
+ * on one stream is ordered as usual.  Errors: CMB_E_DEVICE, CMB_E_INVALID. */
 typedef struct cmb_ctx cmb_ctx;
 int cmb_ctx_create(int device, size_t hbm_budget_bytes, cmb_ctx **out);
 void cmb_ctx_destroy(cmb_ctx *ctx);
@@ -142,6 +145,8 @@ size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo);
  *   d_nsteps: device, [n_cosmo][n_k] int32 attempted steps (may be NULL).
  * Asynchronous on hip_stream (a hipStream_t; NULL = default stream).  Buffers
  * are caller-owned and must stay valid until the stream reaches this work.
+ * Hierarchies of more than 320 state rows (cmb_state_rows) or more than 16
+ * momentum nodes: CMB_E_UNSUPPORTED, outputs untouched.
  */
 int cmb_perturb(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
                 int32_t *d_nsteps, void *hip_stream);

@@ -126,6 +126,11 @@ struct cmb_ctx {
     std::vector<unsigned long long> resident;
     cmbhip::DevTab *d_tabs = nullptr;
     std::vector<cmbhip::DevTab> h_tabs;
+    // completion of the last call's device work and the stream it ran on: a
+    // call on another stream waits for it before it touches the buffers above
+    hipEvent_t done_ev = nullptr;
+    hipStream_t done_stream = nullptr;
+    bool done_live = false;
     std::mutex mu;
 };
 
@@ -304,6 +309,18 @@ int cmb_ctx_create(int device, size_t budget, cmb_ctx **out) {
     if (!c) return CMB_E_INVALID;
     c->device = device;
     c->budget = budget ? budget : (size_t)16 << 30;
+    {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            delete c;
+            set_error(std::string("cmb_ctx_create: ") + hipGetErrorString(e));
+            return CMB_E_DEVICE;
+        }
+    }
     *out = c;
     set_error("");
     return CMB_OK;
@@ -319,6 +336,7 @@ void cmb_ctx_destroy(cmb_ctx *c) {
         hipFree(p);
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->kt_stage) hipHostFree(c->kt_stage);
+    if (c->done_ev) hipEventDestroy(c->done_ev);
     hipSetDevice(prev);
     delete c;
 }
@@ -407,6 +425,12 @@ int upload(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, hipStream_t s
     std::vector<unsigned long long> key(n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) key[i] = tabs[i]->t.uid;
     if (key == c->resident) return CMB_OK;
+    // the cache names no tables until this upload has been queued: a failure
+    // below (the buffer regrown, staging reallocated) must not leave it
+    // pointing at freed or half-written memory
+    c->resident.clear();
+    c->d_tabs = nullptr;
+    c->h_tabs.clear();
     size_t bytes = align256(sizeof(cmbhip::DevTab) * n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) bytes += table_bytes(tabs[i]->t);
     int rc = grow(c, &c->tab_buf, &c->tab_cap, bytes, s);
@@ -453,6 +477,27 @@ struct DeviceGuard {
     }
 };
 
+// Calls on one context may name different streams, and later calls reuse,
+// overwrite or regrow the context's buffers (tables, staging, scratch).  So
+// every call first makes its stream wait for the previous call's device work
+// (an event recorded at that call's end on its stream), and records the event
+// on its own stream when it returns.  Construct after taking the context lock
+// with the context's device current; rc != CMB_OK means the wait could not
+// be queued.
+struct StreamOrder {
+    cmb_ctx *c;
+    hipStream_t s;
+    int rc = CMB_OK;
+    StreamOrder(cmb_ctx *c_, void *stream) : c(c_), s((hipStream_t)stream) {
+        if (c->done_live && c->done_stream != s) rc = herr(hipStreamWaitEvent(s, c->done_ev, 0), "hipStreamWaitEvent");
+    }
+    ~StreamOrder() {
+        if (rc != CMB_OK) return;
+        c->done_live = hipEventRecord(c->done_ev, s) == hipSuccess;
+        c->done_stream = s;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -462,7 +507,7 @@ size_t cmb_solve_workspace_bytes(const cmb_tables *const *tabs, int n_cosmo) {
     if (check_batch(tabs, n_cosmo, b)) return 0;
     size_t bytes = align256(sizeof(cmbhip::DevTab) * n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) bytes += table_bytes(tabs[i]->t);
-    bytes += cmbhip::perturb_ws_doubles(n_cosmo, b.n_k, b.prec) * sizeof(double);
+    bytes += align256(sizeof(int32_t) * (size_t)n_cosmo * b.n_k);  // step counts when the caller passes none
     return bytes;
 }
 
@@ -478,42 +523,24 @@ int perturb_impl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
-    const char *variant = std::getenv("CMBHIP_K1");
-    bool lane_variant = variant && std::string(variant) == "lane" && !d_Pk && !d_Dm;
-    if (b.prec.nq > 0 && (lane_variant || !cmbhip::perturb2_supported(b.prec))) {
-        set_error("massive neutrinos are built into the cooperative perturbation kernel only");
+    if (!cmbhip::perturb2_supported(b.prec)) {
+        set_error("hierarchy of " + std::to_string(cmbhip::state_rows(b.prec)) +
+                  " state rows: the perturbation kernel holds at most 320 (five rows on each of 64 lanes) "
+                  "and 16 momentum nodes");
         return CMB_E_UNSUPPORTED;
     }
-    if ((d_Pk || d_Dm) && !cmbhip::perturb2_supported(b.prec)) {
-        set_error("the matter power spectrum is built into the cooperative perturbation kernel only");
-        return CMB_E_UNSUPPORTED;
-    }
-    if (!lane_variant && cmbhip::perturb2_supported(b.prec)) {
-        int32_t *ns2 = d_nsteps;
-        if (!ns2) {
-            rc = grow(c, &c->st_buf, &c->st_cap, sizeof(int32_t) * (size_t)n_cosmo * b.n_k, s);
-            if (rc) return rc;
-            ns2 = (int32_t *)c->st_buf;
-        }
-        rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, d_Pk, d_Dm,
-                                     stream);
-        if (rc == CMB_OK) set_error("");
-        return rc;
-    }
-    size_t need = cmbhip::perturb_ws_doubles(n_cosmo, b.n_k, b.prec) * sizeof(double);
-    rc = grow(c, &c->ws_buf, &c->ws_cap, need, s);
-    if (rc) return rc;
-    int32_t *ns = d_nsteps;
-    if (!ns) {
+    int32_t *ns2 = d_nsteps;
+    if (!ns2) {
         rc = grow(c, &c->st_buf, &c->st_cap, sizeof(int32_t) * (size_t)n_cosmo * b.n_k, s);
         if (rc) return rc;
-        ns = (int32_t *)c->st_buf;
+        ns2 = (int32_t *)c->st_buf;
     }
-    rc = cmbhip::launch_perturb(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, (double *)c->ws_buf, d_S, d_status, ns,
-                                stream);
+    rc = cmbhip::launch_perturb2(c->d_tabs, n_cosmo, b.n_k, b.n_tau, b.prec, d_S, d_status, ns2, d_Pk, d_Dm, stream);
     if (rc == CMB_OK) set_error("");
     return rc;
 }
@@ -569,6 +596,8 @@ int cmb_los(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max,
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     rc = upload(c, tabs, n_cosmo, (hipStream_t)stream);
     if (rc) return rc;
     rc = cmbhip::launch_los(c->d_tabs, n_cosmo, b.n_k, b.n_tau, ell_max, b.polar, b.s_pol, d_S, d_Delta, stream);
@@ -592,6 +621,8 @@ int cmb_cl(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     rc = upload(c, tabs, n_cosmo, (hipStream_t)stream);
     if (rc) return rc;
     rc = cmbhip::launch_cl(c->d_tabs, n_cosmo, b.n_k, ell_max, d_Delta, d_Cl, stream);
@@ -616,6 +647,9 @@ int cmb_solve(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_ma
     if (!d_S) {
         std::lock_guard<std::mutex> lk(c->mu);
         DeviceGuard g(c->device);
+        if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+        StreamOrder so(c, stream);
+        if (so.rc) return so.rc;
         rc = grow(c, &c->s_buf, &c->s_cap, sizeof(double) * (size_t)n_cosmo * b.n_k * 3 * b.n_tau, s);
         if (rc) return rc;
         d_S = (double *)c->s_buf;
@@ -623,6 +657,9 @@ int cmb_solve(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_ma
     if (!d_Delta) {
         std::lock_guard<std::mutex> lk(c->mu);
         DeviceGuard g(c->device);
+        if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+        StreamOrder so(c, stream);
+        if (so.rc) return so.rc;
         rc = grow(c, &c->d_buf, &c->d_cap, sizeof(double) * (size_t)n_cosmo * 2 * (ell_max - 1) * b.n_k, s);
         if (rc) return rc;
         d_Delta = (double *)c->d_buf;
@@ -826,7 +863,7 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
     int rc = check_batch(tabs, n, b);
     if (rc) return rc;
     if (!cmbhip::perturb2_supported(b.prec)) {
-        set_error("step histories are built into the cooperative perturbation kernel only");
+        set_error("hierarchy larger than the perturbation kernel holds (320 state rows, 16 momentum nodes)");
         return CMB_E_UNSUPPORTED;
     }
     if (cap < tabs[0]->t.prec.max_steps + 1) {
@@ -891,6 +928,8 @@ int cmb_perturb_record(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, d
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     std::vector<int> base(n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) base[i] = i;
     int rc = perturb_hist(c, tabs, n_cosmo, base, d_hist, d_hist_n, hist_cap, false, d_S, d_status, d_nsteps,
@@ -909,6 +948,8 @@ int cmb_perturb_replay(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, c
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     std::vector<int> base(n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) base[i] = i;
     int rc = perturb_hist(c, tabs, n_cosmo, base, const_cast<double *>(d_hist), const_cast<int32_t *>(d_hist_n),
@@ -927,6 +968,8 @@ int cmb_perturb_checkpoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosm
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     std::vector<int> base(n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) base[i] = i;
     Ckpt ck;
@@ -953,6 +996,8 @@ int cmb_perturb_segment(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     std::vector<int> base(n_cosmo);
     for (int i = 0; i < n_cosmo; ++i) base[i] = i;
     Ckpt ck;
@@ -1049,6 +1094,8 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     const int cap = tabs[0]->t.prec.max_steps + 1;
     const int n3 = 3 * (ell_max + 1), nl = ell_max - 1;
@@ -1143,6 +1190,8 @@ int cmb_sources_adjoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
@@ -1171,6 +1220,8 @@ int cmb_spectra_adjoint(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
@@ -1195,6 +1246,8 @@ int cmb_lensed_cl(cmb_ctx *c, int n_cosmo, int L, const double *d_Cl, const doub
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     int rc = ensure_lens_tables(c, L, n_mu, s);
     if (rc) return rc;
@@ -1219,6 +1272,8 @@ int cmb_bessel3_table(cmb_ctx *c, int ell_max, double *h_xs, double *h_x5, doubl
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, nullptr);
+    if (so.rc) return so.rc;
     hipStream_t s = nullptr;
     int rc = ensure_bessel3(c, ell_max, s);
     if (rc) return rc;
@@ -1254,6 +1309,8 @@ int cmb_los_bessel3(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = ensure_bessel3(c, ell_max, s);
     if (rc) return rc;
@@ -1296,6 +1353,8 @@ int cmb_lensing_potential(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;
@@ -1371,6 +1430,8 @@ int cmb_spectra_on_grid(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
     hipStream_t s = (hipStream_t)stream;
     rc = upload(c, tabs, n_cosmo, s);
     if (rc) return rc;

@@ -90,9 +90,6 @@ void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x);
 DevPrec dev_prec(const cmb_prec &p, int nq);
 
 // kernel launchers (hipStream_t passed as void*)
-int launch_perturb(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_ws,
-                   double *d_S, int *d_status, int *d_nsteps, void *stream);
-size_t perturb_ws_doubles(int n_cosmo, int n_k, const DevPrec &p);
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
                     int *d_status, int *d_nsteps, double *d_Pk, double *d_Dm, void *stream, bool hist = false);
 bool perturb2_supported(const DevPrec &p);

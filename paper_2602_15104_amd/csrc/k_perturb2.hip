@@ -1,9 +1,10 @@
-// K1 (cooperative variant): synchronous-gauge perturbations and CMB sources,
-// one group of G lanes per (cosmology, k) mode.
+// K1: synchronous-gauge perturbations and CMB sources, one group of G lanes
+// per (cosmology, k) mode.
 //
-// Same method as k_perturb.hip (the ESDIRK of ARK4(3)6L[2]SA, RMS norm, PID control,
-// Hermite dense output, source functions of App. B.4 of arXiv 2602.15104;
-// equations of App. B.3 and App. C), mapped differently onto the hardware:
+// The method: the ESDIRK of ARK4(3)6L[2]SA (Kennedy & Carpenter 2003), RMS
+// error norm, PID step control, Hermite dense output and the source
+// functions of App. B.4 of arXiv 2602.15104, for the equations of App. B.3 and
+// App. C.  The mapping onto the hardware:
 //
 //  * a mode's state rows are spread over a group of G lanes (G = 16 for the
 //    79-row TT/TE/EE hierarchy, R = 5 rows per lane, in full launches; 64

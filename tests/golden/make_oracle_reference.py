@@ -1,6 +1,7 @@
 """Write the oracle spectra used by the GPU parity tests at full size.
 
     python tests/golden/make_oracle_reference.py [config1] [config2] [config1_transfer] [config1_jacobian]
+                                                 [tight_config0] [tight_config1]
 
 Calls only the CPU oracle (package ``oracle``) and the seeded workload
 generator; re-run it whenever the oracle's arithmetic changes.  Outputs, for
@@ -15,6 +16,12 @@ plus, for config 2, the per-mode step counts (oracle_config2_nsteps.npy), and
   tests/golden/oracle_config1_jacobian.npy  dC_l/d(h, omega_b, omega_cdm, ln A_s,
                                       n_s, tau_reio) [6][3][2501] for config 1
                                       (five-point stencil, rel 1e-4, frozen steps)
+  tests/golden/oracle_tight_config0.npz, oracle_tight_config1_subset.npz
+                                      the tight-tolerance cross-check: config 0
+                                      in full and config 1 on eight of its modes,
+                                      both at rtol 1e-10 (atol scaled alike):
+                                      S, Cl, nsteps, and the same at the paper's
+                                      tolerances for the discretisation report
 """
 import os
 import sys
@@ -29,8 +36,26 @@ import cmb_workloads as W  # noqa: E402
 import oracle as O  # noqa: E402
 
 
+def tight(name):
+    wl = W.config0() if name == "config0" else W.config1_subset()
+    wt = W.tight(wl)
+    t0 = time.time()
+    r = O.solve(wt.cosmo, wt.prec, wt.k, wt.n_tau, wt.ell_max, wt.polarization)
+    assert np.all(r["status"] == 0)
+    p = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, wl.polarization)
+    assert np.all(p["status"] == 0)
+    out = os.path.join(HERE, f"oracle_tight_{'config1_subset' if name != 'config0' else name}.npz")
+    np.savez_compressed(out, k=wt.k, S=r["S"], Cl=r["Cl"], nsteps=np.asarray(r["nsteps"], dtype=np.int32),
+                        S_paper=p["S"], Cl_paper=p["Cl"])
+    print(f"wrote {os.path.basename(out)} in {time.time() - t0:.1f} s; steps {np.min(r['nsteps'])}.."
+          f"{np.max(r['nsteps'])} (paper tolerances {np.max(p['nsteps'])})", flush=True)
+
+
 def main(which):
     for name in which:
+        if name.startswith("tight_"):
+            tight(name[len("tight_"):])
+            continue
         if name.endswith("_jacobian"):
             wl = getattr(W, name.replace("_jacobian", ""))()
             t0 = time.time()

@@ -70,6 +70,19 @@ def test_serving_matches_alone(ctx, max_batch, n_streams):
         assert np.array_equal(Cl, ref), np.max(np.abs(Cl - ref))
         assert 0.0 <= tm["submit"] <= tm["tables_ready"] <= tm["launched"] <= tm["done"]
         assert 1 <= tm["batch_size"] <= max_batch
+    # the mix really happened: requests shared a batch, and batches on
+    # different streams were on the device at the same time (one batch per
+    # launch time; a batch launched before an earlier one finished overlaps it)
+    times = [tm for _, _, tm in got]
+    sizes = [tm["batch_size"] for tm in times]
+    batches = sorted({(tm["launched"], tm["done"]) for tm in times})
+    overlaps = sum(1 for i in range(1, len(batches)) if batches[i][0] < max(d for _, d in batches[:i]))
+    _say("batch sizes", sizes, "batches", len(batches), "overlapping launches", overlaps)
+    if max_batch == 1:
+        assert max(sizes) == 1 and overlaps == 0
+    else:
+        assert max(sizes) > 1
+        assert overlaps >= 1
 
 
 def test_serving_rejects_other_hierarchy():
