@@ -28,46 +28,9 @@ size_t table_doubles(const Tables &t) {
 }
 
 void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x) {
-    size_t o = 0;
-    auto put = [&](const std::vector<double> &v) {
-        std::memcpy(hp + o, v.data(), v.size() * sizeof(double));
-        const double *r = dp + o;
-        o += v.size();
-        return r;
-    };
-    std::memset(&x, 0, sizeof(x));
-    x.poly = put(t.poly);
-    x.k = put(t.k);
-    x.lna_start = put(t.lna_start);
-    x.lna_src = put(t.lna_src);
-    x.chi_src = put(t.chi_src);
-    x.w_src = put(t.w_src);
-    x.q = put(t.q);
-    x.W = put(t.W);
-    x.lens_w = put(t.lens_w);
-    x.chi_star = t.chi_star;
-    x.pref_ncdm = t.pref_ncdm;
-    x.m_over_T = t.m_over_T;
-    x.L0 = t.L0;
-    x.inv_dl = 1.0 / t.dl;
-    x.n_tab = t.n_tab;
-    x.n_k = (int)t.k.size();
-    x.n_tau = (int)t.lna_src.size();
-    x.tau0 = t.tau0;
-    x.R_nu = t.R_nu;
-    x.rt_g0 = t.rt_g0;
-    x.rt_ur0 = t.rt_ur0;
-    x.rt_c0 = t.rt_c0;
-    x.rt_b0 = t.rt_b0;
-    x.rt_L = t.rt_L;
-    x.A_s = t.cosmo.A_s;
-    x.n_s = t.cosmo.n_s;
-    x.k_pivot = t.prec.k_pivot;
-    x.rtol_small = t.prec.rtol_small;
-    x.rtol_large = t.prec.rtol_large;
-    x.atol_small = t.prec.atol_small;
-    x.atol_large = t.prec.atol_large;
-    x.k_split = t.prec.k_split;
+    describe_table(t, dp, x, [&](const double *src, size_t n, const double *dst) {
+        if (n) std::memcpy(hp + (dst - dp), src, n * sizeof(double));
+    });
 }
 
 DevPrec dev_prec(const cmb_prec &p, int nq) {
@@ -376,12 +339,9 @@ int grow(cmb_ctx *c, void **buf, size_t *cap, size_t need, hipStream_t s) {
     return CMB_OK;
 }
 
-struct Batch {
-    int n_k = 0, n_tau = 0;
-    cmbhip::DevPrec prec{};
-    int polar = 0;
-    double s_pol = 1.0;
-};
+}  // namespace
+
+namespace cmbhip {
 
 int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
     if (!tabs || n_cosmo < 1) {
@@ -415,6 +375,15 @@ int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b) {
     b.s_pol = p.scale_pol;
     return CMB_OK;
 }
+
+const Tables &tables_of(const cmb_tables *t) { return t->t; }
+
+}  // namespace cmbhip
+
+namespace {
+
+using cmbhip::Batch;
+using cmbhip::check_batch;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

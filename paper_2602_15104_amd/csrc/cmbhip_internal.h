@@ -86,8 +86,67 @@ struct DevPrec {
 // into host staging hp whose device copy will sit at dp (fills the DevTab)
 size_t table_doubles(const Tables &t);
 void pack_table(const Tables &t, double *hp, const double *dp, DevTab &x);
+
+// The descriptor of table t whose arrays sit one after another from device
+// address dp, in the order of the calls put(host array, doubles, device
+// address) that this makes (table_doubles(t) doubles in all).
+template <class Put>
+void describe_table(const Tables &t, const double *dp, DevTab &x, Put put) {
+    size_t o = 0;
+    auto at = [&](const std::vector<double> &v) {
+        const double *r = dp + o;
+        put(v.data(), v.size(), r);
+        o += v.size();
+        return r;
+    };
+    x = DevTab{};
+    x.poly = at(t.poly);
+    x.k = at(t.k);
+    x.lna_start = at(t.lna_start);
+    x.lna_src = at(t.lna_src);
+    x.chi_src = at(t.chi_src);
+    x.w_src = at(t.w_src);
+    x.q = at(t.q);
+    x.W = at(t.W);
+    x.lens_w = at(t.lens_w);
+    x.chi_star = t.chi_star;
+    x.pref_ncdm = t.pref_ncdm;
+    x.m_over_T = t.m_over_T;
+    x.L0 = t.L0;
+    x.inv_dl = 1.0 / t.dl;
+    x.n_tab = t.n_tab;
+    x.n_k = (int)t.k.size();
+    x.n_tau = (int)t.lna_src.size();
+    x.tau0 = t.tau0;
+    x.R_nu = t.R_nu;
+    x.rt_g0 = t.rt_g0;
+    x.rt_ur0 = t.rt_ur0;
+    x.rt_c0 = t.rt_c0;
+    x.rt_b0 = t.rt_b0;
+    x.rt_L = t.rt_L;
+    x.A_s = t.cosmo.A_s;
+    x.n_s = t.cosmo.n_s;
+    x.k_pivot = t.prec.k_pivot;
+    x.rtol_small = t.prec.rtol_small;
+    x.rtol_large = t.prec.rtol_large;
+    x.atol_small = t.prec.atol_small;
+    x.atol_large = t.prec.atol_large;
+    x.k_split = t.prec.k_split;
+}
 // launch options of a hierarchy (nq: momentum nodes actually present)
 DevPrec dev_prec(const cmb_prec &p, int nq);
+
+// What the cosmologies of one call share; check_batch validates a batch
+// (non-empty, no NULL table, equal n_k, n_tau and static options) and fills
+// it, or sets the error text and returns CMB_E_INVALID.
+struct Batch {
+    int n_k = 0, n_tau = 0;
+    DevPrec prec{};
+    int polar = 0;
+    double s_pol = 1.0;
+};
+int check_batch(const cmb_tables *const *tabs, int n_cosmo, Batch &b);
+const Tables &tables_of(const cmb_tables *t);
 
 // kernel launchers (hipStream_t passed as void*)
 int launch_perturb2(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
