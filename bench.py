@@ -30,15 +30,16 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64: 256 CU x 2.4 GHz x 128 flop/cycle
 
 
 def k1_flops_per_step(N: int, n_chains: int = 3) -> float:
-    """Algorithmic arithmetic of one ESDIRK step (five implicit stages) of the
-    structured stage solve, N state rows (exp, sqrt, reciprocal = 1 flop):
-      stage right-hand sides  sum_s 2 s N              = 30 N
+    """Arithmetic the perturbation kernel executes in one ESDIRK step (five
+    implicit stages) of its continuant stage solve, N state rows (exp, sqrt,
+    reciprocal = 1 flop):
+      stage right-hand sides  sum_s 2 s N  (s = 1..5)   = 30 N
       per stage and row: continuant sweep up 6, pivot reciprocals and
       downward coefficients 5, downward sweep 2, K = (Y - R)/g 2  = 75 N
-      error estimate and norm                          = 19 N
+      error estimate and norm                            = 19 N
       per stage: top rows of each chain ~184, coupling solve ~150,
-      background ~60                                   = 5 (184 n_chains + 210)
-      step control                                     = 10"""
+      background ~60                                     = 5 (184 n_chains + 210)
+      step control                                       = 10"""
     return 124.0 * N + 5.0 * (184.0 * n_chains + 210.0) + 10.0
 
 

@@ -33,8 +33,12 @@ namespace cmbhip {
 
 namespace {
 
-__device__ constexpr double Kc[6] = {0.0, 0.5, 83.0 / 250.0, 31.0 / 50.0, 17.0 / 20.0, 1.0};
-__device__ constexpr double Ka[6][6] = {
+// ESDIRK: the implicit part of Kennedy & Carpenter's ARK4(3)6L[2]SA (2003):
+// six stages, explicit first stage, gamma = 1/4, stiffly accurate (the last
+// row is the order-4 solution), Ke = b - bhat with bhat the order-3 weights.
+constexpr int NSTG = 6;
+__device__ constexpr double Kc[NSTG] = {0.0, 0.5, 83.0 / 250.0, 31.0 / 50.0, 17.0 / 20.0, 1.0};
+__device__ constexpr double Ka[NSTG][NSTG] = {
     {0, 0, 0, 0, 0, 0},
     {0.25, 0.25, 0, 0, 0, 0},
     {8611.0 / 62500.0, -1743.0 / 31250.0, 0.25, 0, 0, 0},
@@ -42,11 +46,12 @@ __device__ constexpr double Ka[6][6] = {
     {15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0, 2285395.0 / 8070912.0,
      0.25, 0},
     {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, 0.25}};
-__device__ constexpr double Ke[6] = {
+__device__ constexpr double Ke[NSTG] = {
     82889.0 / 524892.0 - 4586570599.0 / 29645900160.0, 0.0, 15625.0 / 83664.0 - 178811875.0 / 945068544.0,
     69875.0 / 102672.0 - 814220225.0 / 1159782912.0, -2260.0 / 8211.0 + 3700637.0 / 11593932.0,
     0.25 - 61727.0 / 225920.0};
 constexpr double GAMMA = 0.25;
+constexpr double ERR_ORDER = 4.0;  // order of the error estimate (step control)
 
 // 1/b: hardware reciprocal refined by two Newton steps (relative error at the
 // level of rounding), shorter on the dependent path than IEEE division.
@@ -294,24 +299,32 @@ __device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p, 
     return r;
 }
 
-// LDS slab of one mode
-// Per-row record in LDS (STR doubles, 16-byte aligned so that neighbouring
-// fields pair into 128-bit accesses): stage rhs / solution, the
-// time-independent multipliers of the row, the scaled continuants of the
-// upward sweep and the coefficients of the downward one.
-constexpr int STR = 10;
-constexpr int F_RY = 0, F_CC = 1, F_CP = 2, F_CA = 3, F_M = 4, F_MN = 5, F_U = 6, F_V = 7, F_CD = 8, F_X = 9;
+// LDS of a workgroup: the rows' time-independent multipliers, one table that
+// every mode of the wavefront reads (they depend on the hierarchy only), then
+// one slab per mode.  A mode's slab holds a record of STR doubles per row
+// (16-byte aligned, so neighbouring fields pair into 128-bit accesses): the
+// stage rhs / solution, the scaled continuants M_j, M_{j+1} and S_j of the
+// upward sweep; after the pivots are formed, the U_j and V_j of the downward
+// recurrence replace S_j and M_{j+1} in place.
+constexpr int STR = 4;
+constexpr int F_RY = 0, F_M = 1, F_MN = 2, F_U = 3;
+constexpr int F_V = F_MN;  // V_j, written over M_{j+1} once the pivots are formed
+// the multipliers table: SST doubles per row (CC and CP adjacent)
+constexpr int SST = 4;
+constexpr int S_CC = 0, S_CP = 1, S_CA = 2, S_CD = 3;
 // record fields free between steps, one per output time of a batch of dense
 // outputs (the next step's stages rewrite them before reading them)
-constexpr int OUT_SLOTS = 6;
-__device__ inline int out_slot(int b) { return b == 0 ? F_RY : (b < 5 ? F_M + (b - 1) : F_X); }
+constexpr int OUT_SLOTS = STR;
+__device__ inline int out_slot(int b) { return b; }
 constexpr int PADR = 8;  // spare records before row 0 and after the last row
 
 struct Slab {
     double *base;  // record of row r at base + (r + PADR) * STR
+    const double *st;  // multipliers of row r at st + (r + PADR) * SST (shared by the wavefront's modes)
     double *AX;    // exchange area
     double *BK;    // the current step's stage backgrounds, NBK doubles each
     __device__ double *rec(int row) const { return base + (row + PADR) * STR; }
+    __device__ const double *sta(int row) const { return st + (row + PADR) * SST; }
     __device__ double &ry(int row) const { return base[(row + PADR) * STR + F_RY]; }
 };
 
@@ -322,10 +335,12 @@ __host__ __device__ constexpr int ax_doubles(int nch) { return (4 + 16 * nch + 1
 constexpr int NBK = 24;
 static_assert(NBK * sizeof(double) >= sizeof(Bk), "a stage record holds a Bk");
 // doubles of LDS per mode for NP rows: records, exchange area, and the
-// backgrounds of the five implicit stages
+// backgrounds of the implicit stages
 __host__ __device__ constexpr int slab_doubles(int NP, int nch) {
-    return (NP + 2 * PADR) * STR + ax_doubles(nch) + 5 * NBK;
+    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NSTG - 1) * NBK;
 }
+// doubles of the shared multipliers table for NP rows
+__host__ __device__ constexpr int stat_doubles(int NP) { return (NP + 2 * PADR) * SST; }
 
 // Time-independent multipliers of a generic chain row (fifth row of its chain
 // onward): a = CA v, c = CC v, d = CD trunc - T (photon chains) or CD trunc,
@@ -465,7 +480,7 @@ __device__ void aux_from_rows(const Slab &m, const Lay &L, const Bk &s, const De
 
 template <int R>
 struct Rows {
-    double y[R], yn[R], K[6][R], rr[R];
+    double y[R], yn[R], K[NSTG][R], rr[R];
 };
 
 // f = A y for this lane's rows; y already in the records (all rows), couplings in AX[0..2].
@@ -525,23 +540,27 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int NP = G * R;
     Slab m;
     {
-        double *base = lds + (size_t)grp * slab_doubles(NP, L.nch);
+        double *stat = lds;
+        double *base = lds + stat_doubles(NP) + (size_t)grp * slab_doubles(NP, L.nch);
         m.base = base;
+        m.st = stat;
         m.AX = base + (NP + 2 * PADR) * STR;
         m.BK = m.AX + ax_doubles(L.nch);
-        // every record, pads included, starts from zero; then the multipliers
+        // every record, pads included, starts from zero, and so does the
+        // multipliers table (every group writes the same values into it)
         for (int i = gl; i < (NP + 2 * PADR) * STR; i += G) base[i] = 0.0;
+        for (int i = gl; i < stat_doubles(NP); i += G) stat[i] = 0.0;
         wsync();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
             double ca, cc, cd, cp;
             row_static(row, L, ca, cc, cd, cp);
-            double *q = m.rec(row);
-            q[F_CA] = ca;
-            q[F_CC] = cc;
-            q[F_CD] = cd;
-            q[F_CP] = cp;
+            double *q = stat + (row + PADR) * SST;
+            q[S_CA] = ca;
+            q[S_CC] = cc;
+            q[S_CD] = cd;
+            q[S_CP] = cp;
         }
         wsync();
     }
@@ -612,7 +631,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     for (int r = 0; r < R; ++r) {
         w.y[r] = w.yn[r] = w.rr[r] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) w.K[j][r] = 0.0;
+        for (int j = 0; j < NSTG; ++j) w.K[j][r] = 0.0;
     }
     Bk s;
     bk_at<MNU>(tb, p, k, t0, s);
@@ -645,7 +664,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         }
     }
     // f0 = A y0
-    auto full_rhs = [&](const double *yv, double *f, const Bk &bs) {
+    auto full_rhs = [&](const double *yv, double *f, const Bk &bs) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) m.ry(gl * R + r) = yv[r];
         wsync();
@@ -676,7 +695,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     // two partial sums that every lane of the pair forms in the same order):
     // DPP permutes inside a 16-lane row (swap neighbours, swap pairs, mirror
     // the half row, mirror the row), lane shuffles only for groups above 16
-    auto group_sum = [&](double v, int w) {
+    auto group_sum = [&](double v, int w) __attribute__((always_inline)) {
         v += dpp_f64<0xB1>(v);  // quad_perm [1, 0, 3, 2]
         v += dpp_f64<0x4E>(v);  // quad_perm [2, 3, 0, 1]
         if (w >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
@@ -688,8 +707,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     // the rows' terms are summed in the order of the narrow groups of Gn
     // lanes with RN rows each, so a mode takes the same steps, bit for bit,
     // in either shape (and so alone or in any batch).
-    auto rms = [&](const double *v, const double *y1, const double *y2) {
-        auto term = [&](int r) {
+    auto rms = [&](const double *v, const double *y1, const double *y2) __attribute__((always_inline)) {
+        auto term = [&](int r) __attribute__((always_inline)) {
             double yy = fabs(y1[r]);
             if (y2) yy = fmax(yy, fabs(y2[r]));
             return v[r] * rcp(fma(rtol, yy, atol));
@@ -704,14 +723,36 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 }
             }
             acc = group_sum(acc, G);
+        } else if constexpr (R == 2 * RN) {
+            // groups of G = Gn / 2 lanes with twice the rows: lane g holds the
+            // rows of narrow lanes 2g and 2g + 1, whose partial sums it forms
+            // in their order and adds (the narrow tree's first level); the
+            // narrow tree's later levels pair lanes g ^ 1, g ^ 2 and the two
+            // halves of the group (its mirrored quads hold equal values)
+            double a2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                if (gl * R + r < N) {
+                    const double q = term(r);
+                    acc = fma(q, q, acc);
+                }
+                if (gl * R + RN + r < N) {
+                    const double q = term(RN + r);
+                    a2 = fma(q, q, a2);
+                }
+            }
+            acc += a2;
+            if (G >= 2) acc += dpp_f64<0xB1>(acc);   // quad_perm [1, 0, 3, 2]
+            if (G >= 4) acc += dpp_f64<0x4E>(acc);   // quad_perm [2, 3, 0, 1]
+            if (G >= 8) acc += dpp_f64<0x141>(acc);  // row_half_mirror
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) m.rec(gl * R + r)[F_X] = term(r);
+            for (int r = 0; r < R; ++r) m.rec(gl * R + r)[F_M] = term(r);
             wsync();
             if (gl < Gn)
                 for (int r = 0; r < RN; ++r)
                     if (RN * gl + r < N) {
-                        const double q = m.rec(RN * gl + r)[F_X];
+                        const double q = m.rec(RN * gl + r)[F_M];
                         acc = fma(q, q, acc);
                     }
             acc = group_sum(acc, Gn);  // lanes from Gn on carry values nobody uses
@@ -751,17 +792,17 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         for (int r = 0; r < R; ++r) f1[r] -= w.K[0][r];
         double d2 = rms(f1, w.y, nullptr) / h0;
         double dm = fmax(d1, d2);
-        double hh = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+        double hh = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / (ERR_ORDER + 1.0));
         h = fmin(100.0 * h0, hh);
     }
-    const double b1 = (p.pcoeff + p.icoeff + p.dcoeff) / 4.0;
-    const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / 4.0;
-    const double b3 = p.dcoeff / 4.0;
+    const double b1 = (p.pcoeff + p.icoeff + p.dcoeff) / ERR_ORDER;
+    const double b2 = -(p.pcoeff + 2.0 * p.dcoeff) / ERR_ORDER;
+    const double b3 = p.dcoeff / ERR_ORDER;
     double lEp = 0.0, lEpp = 0.0;  // logs of the previous two accepted error norms
     int ns = 0, na = na0, st = CMB_K_OK;
     bool seg_open = false;  // a segment stopped at its last step, before a = 1
     if (hout && gl == 0) hout[0] = t0;
-    auto put_ck = [&](int slot) {
+    auto put_ck = [&](int slot) __attribute__((always_inline)) {
         if (slot >= tb.ck_cap) return;
         double *q = ckp + (size_t)slot * ck_stride;
         if (gl == 0) q[0] = t;
@@ -795,30 +836,31 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             last = true;
         }
         const double g = h * GAMMA;
-        // the backgrounds of the step's five implicit stages, evaluated at once
-        // on five lanes of the group (instead of one stage after the other on
-        // every lane) and read back from LDS stage by stage
-        for (int si = 1 + gl; si < 6; si += G) {
-            const double ts = (si == 5) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
+        // the backgrounds of the step's implicit stages, evaluated at once on
+        // as many lanes of the group (instead of one stage after the other on
+        // every lane) and read back from LDS stage by stage; the stage at the
+        // step's end lands on it exactly
+        for (int si = 1 + gl; si < NSTG; si += G) {
+            const double ts = (Kc[si] == 1.0) ? (last ? 0.0 : t + h) : t + Kc[si] * h;
             Bk b;
             bk_at<MNU>(tb, p, k, ts, b);
             __builtin_memcpy(m.BK + (si - 1) * NBK, &b, sizeof(Bk));
         }
         wsync();
-        for (int si = 1; si < 6; ++si) {
+        for (int si = 1; si < NSTG; ++si) {
             __builtin_memcpy(&s, m.BK + (si - 1) * NBK, sizeof(Bk));
             // stage weights h a_sj for j < s (zero otherwise): fixed-length sums keep
             // every register index static
-            double hA[5];
+            double hA[NSTG - 1];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
+            for (int j = 0; j < NSTG - 1; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
             const double gkH = g * s.kH, gT_ph = g * s.T, gtr = g * s.trunc;
             // (A) stage right-hand sides, row-parallel
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double acc = w.y[r];
 #pragma unroll
-                for (int j = 0; j < 5; ++j) acc += hA[j] * w.K[j][r];
+                for (int j = 0; j < NSTG - 1; ++j) acc += hA[j] * w.K[j][r];
                 w.rr[r] = acc;
                 m.ry(gl * R + r) = acc;
             }
@@ -844,18 +886,19 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 if (cn >= 5) {
                     const double bq = (1.0 + gT) * iu;
                     double *rl = m.rec(cb + cn - 1);
-                    double M1 = fma(-gtr, rl[F_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
+                    double M1 = fma(-gtr, m.sta(cb + cn - 1)[S_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
                     rl[F_M] = M1;
                     rl[F_MN] = M2;
                     rl[F_U] = S1 * iu;
                     // prefetched (RY, CC) and CP of the next block, rows j0 .. j0-3
                     double pr[4], pc[4], pp[4];
                     const double *pb = m.rec(cb + cn - 5);  // row j0 - 3 of the first block
+                    const double *ps = m.sta(cb + cn - 5);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         pr[q] = pb[(3 - q) * STR + F_RY];
-                        pc[q] = pb[(3 - q) * STR + F_CC];
-                        pp[q] = pb[(3 - q) * STR + F_CP];
+                        pc[q] = ps[(3 - q) * SST + S_CC];
+                        pp[q] = ps[(3 - q) * SST + S_CP];
                     }
                     // one block: rows j0 .. j0-3 from (cr, cc, cp) while the next
                     // block's values load into (nr, nc, np); two blocks per trip with
@@ -864,11 +907,12 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                                         double(&nr)[4], double(&nc)[4], double(&np)[4], int j0) {
                         double *cbk = m.rec(j0 - 3 + cb);
                         const double *nb = cbk - 4 * STR;
+                        const double *ns = m.sta(j0 - 3 + cb) - 4 * SST;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             nr[q] = nb[(3 - q) * STR + F_RY];
-                            nc[q] = nb[(3 - q) * STR + F_CC];
-                            np[q] = nb[(3 - q) * STR + F_CP];
+                            nc[q] = ns[(3 - q) * SST + S_CC];
+                            np[q] = ns[(3 - q) * SST + S_CP];
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
@@ -909,7 +953,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     const double *r4 = m.rec(cb + 4);
                     Q1 = r4[F_M];
                     Q2 = r4[F_MN];
-                    bq1 = -r4[F_CA];
+                    bq1 = -m.sta(cb + 4)[S_CA];
                     Z0 = r4[F_U];
                 }
                 double Qs[5], z0[4], zH[4], zE[4], zP[4], al[4];
@@ -970,11 +1014,11 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double *q = m.rec(gl * R + r);
-                const double ca = q[F_CA], fm = q[F_M], fu = q[F_U], fmn = q[F_MN], fv = q[F_V];
+                const double ca = m.sta(gl * R + r)[S_CA], fm = q[F_M], fu = q[F_U], fmn = q[F_MN];
                 const double iM = rcp(fm);
                 const bool gen = ca != 0.0;
                 q[F_U] = gen ? fu * iM : fu;
-                q[F_V] = gen ? -ca * fmn * iM : fv;
+                q[F_V] = gen ? -ca * fmn * iM : fmn;
             }
             // (C) couplings: 3x3 (2x2 without polarisation) system, one lane
             if (gl == 0) {
@@ -1107,9 +1151,9 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 double y = row < N ? m.ry(row) : 0.0;
                 double kv = (y - w.rr[r]) * ig;
 #pragma unroll
-                for (int j = 1; j < 6; ++j)
+                for (int j = 1; j < NSTG; ++j)
                     if (si == j) w.K[j][r] = kv;
-                if (si == 5) w.yn[r] = y;
+                if (si == NSTG - 1) w.yn[r] = y;
             }
             wsync();
         }
@@ -1119,7 +1163,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         for (int r = 0; r < R; ++r) {
             double e = 0.0;
 #pragma unroll
-            for (int j = 0; j < 6; ++j) e += Ke[j] * w.K[j][r];
+            for (int j = 0; j < NSTG; ++j) e += Ke[j] * w.K[j][r];
             ev[r] = h * e;
         }
         double E = rms(ev, w.y, w.yn);
@@ -1152,7 +1196,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         m.rec(gl * R + r)[fld] =
-                            h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[5][r];
+                            h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * w.yn[r] + h11 * hh * w.K[NSTG - 1][r];
                 }
                 wsync();
                 if (gl < nb) {
@@ -1204,7 +1248,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 w.y[r] = w.yn[r];
-                w.K[0][r] = w.K[5][r];
+                w.K[0][r] = w.K[NSTG - 1][r];
             }
             t = tn;
             if (ckp && na % tb.ck_every == 0) put_ck(na / tb.ck_every);
@@ -1214,7 +1258,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             lEpp = lEp;
             lEp = lE;
         } else {
-            fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -0.25)));
+            fac = fmin(0.9, fmax(0.2, 0.9 * pow(E, -1.0 / ERR_ORDER)));
         }
         h *= fac;
         if (!hin && t < 0.0 && h < 1e-12) {
@@ -1392,11 +1436,24 @@ static void wide_shape(const DevPrec &p, long n_sys, int &R, int &G) {
     }
 }
 
+// Many modes: groups of half the narrow width with twice the rows, so that a
+// wavefront carries eight modes and the serial chain sweeps and coupling
+// solves serve twice as many modes per instruction (the error norm keeps the
+// narrow groups' order).  Massless hierarchies whose narrow groups are 16
+// lanes of five rows, in launches of at least kDenseModes modes.
+constexpr long kDenseModes = 8192;
+static void dense_shape(const DevPrec &p, long n_sys, int &R, int &G) {
+    if (R != 5 || G != 16 || p.nq > 0 || n_sys < kDenseModes) return;
+    R = 10;
+    G = 8;
+}
+
 bool perturb2_supported(const DevPrec &p) {
     int R, G;
     group_shape(p, R, G);
     const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
-    return G <= 64 && (64 / G) * slab_doubles(G * R, nch) * sizeof(double) <= 65536 && p.nq <= kMaxQ;
+    return G <= 64 && (stat_doubles(G * R) + (64 / G) * slab_doubles(G * R, nch)) * sizeof(double) <= 65536 &&
+           p.nq <= kMaxQ;
 }
 
 static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, double *d_S,
@@ -1412,17 +1469,20 @@ static int launch_perturb2_any(const DevTab *d_tabs, int n_cosmo, int n_k, int n
     if (n_sys <= 0) return CMB_OK;
     const int Gn = G;  // the narrow group, whose error-norm order every shape keeps
     wide_shape(p, n_sys, R, G);
+    dense_shape(p, n_sys, R, G);
     int spw = 64 / G;
     dim3 grid((unsigned)((n_sys + spw - 1) / spw)), block(64);
     const int nch = (p.lp > 0 ? 3 : 2) + p.nq;
-    size_t lds = (size_t)spw * slab_doubles(G * R, nch) * sizeof(double);
+    size_t lds = ((size_t)stat_doubles(G * R) + (size_t)spw * slab_doubles(G * R, nch)) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     const bool mnu = p.nq > 0;
 #define CMB_K1_LAUNCH(R_, M_, H_, RN_)                                                                  \
     hipLaunchKernelGGL((perturb2_kernel<R_, M_, H_, RN_>), grid, block, lds, s, d_tabs, n_cosmo, n_k, n_tau, p, G, \
                        Gn, d_S, d_status, d_nsteps, d_items, n_items, d_Pk, d_Dm)
 #define CMB_K1_LAUNCH3(R_, M_, H_) CMB_K1_LAUNCH(R_, M_, H_, R_)
-    if (G != Gn && R == 2) {  // wide groups (massless hierarchies) in the order of narrow groups of five rows
+    if (G != Gn && R == 10) {  // dense groups (massless) in the order of narrow groups of five rows
+        if (hist) CMB_K1_LAUNCH(10, false, true, 5); else CMB_K1_LAUNCH(10, false, false, 5);
+    } else if (G != Gn && R == 2) {  // wide groups (massless hierarchies) in the order of narrow groups of five rows
         if (hist) CMB_K1_LAUNCH(2, false, true, 5); else CMB_K1_LAUNCH(2, false, false, 5);
     } else if (G != Gn) {
         if (hist) CMB_K1_LAUNCH(3, false, true, 5); else CMB_K1_LAUNCH(3, false, false, 5);

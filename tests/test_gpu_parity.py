@@ -239,24 +239,70 @@ def test_batch_invariance_and_determinism(ctx):
 
 def test_launch_shape_invariance(ctx):
     """Config-1 hierarchy (79 rows) on 40 modes to k = 0.2, one cosmology in
-    three launch shapes: alone (a whole wavefront per mode), among 30
-    cosmologies (1200 modes: 32-lane groups) and among 60 (2400 modes: 16-lane
-    groups); sources, step counts and C_ell are the same bits in all three."""
+    four launch shapes: alone (a whole wavefront per mode), among 30
+    cosmologies (1200 modes: 32-lane groups), among 60 (2400 modes: 16-lane
+    groups) and among 210 (8400 modes: 8-lane groups of ten rows, eight modes
+    per wavefront); sources, step counts and C_ell are the same bits in all."""
     import paper_2602_15104_amd as L
     wl = W.config1()
     k = W.log_grid(1e-4, 0.2, 40)
-    cosmos = W.perturbed_cosmologies(60, seed=19)
+    cosmos = W.perturbed_cosmologies(210, seed=19)
     for cc in cosmos:
         cc["N_nu_massless"] = 3.0
     tabs = [L.Tables(cc, wl.prec, k, 200) for cc in cosmos]
     a = run_gpu(ctx, [tabs[11]], 300)
     b = run_gpu(ctx, tabs[:30], 300)
-    c = run_gpu(ctx, tabs, 300)
-    assert np.all(a["status"] == 0) and np.all(b["status"] == 0) and np.all(c["status"] == 0)
-    for o in (b, c):
+    c = run_gpu(ctx, tabs[:60], 300)
+    d = run_gpu(ctx, tabs, 300)
+    for o in (a, b, c, d):
+        assert np.all(o["status"] == 0)
+    for o in (b, c, d):
         assert np.array_equal(a["nsteps"][0], o["nsteps"][11])
         assert np.array_equal(a["S"][0], o["S"][11])
         assert np.array_equal(a["Cl"][0], o["Cl"][11])
+    # a cosmology late in the dense launch too (another wavefront, other slots)
+    e = run_gpu(ctx, [tabs[197]], 300)
+    assert np.array_equal(e["S"][0], d["S"][197]) and np.array_equal(e["nsteps"][0], d["nsteps"][197])
+
+
+def test_dense_shape_record_replay(ctx):
+    """Step histories in the dense launch shape (8-lane groups, 8400 modes):
+    the recorded history and sources of one cosmology equal its solo record
+    (a whole wavefront per mode) bit for bit, and replaying the dense
+    histories reproduces the sources."""
+    import torch
+    import paper_2602_15104_amd as L
+    wl = W.config1()
+    k = W.log_grid(1e-4, 0.2, 40)
+    cosmos = W.perturbed_cosmologies(210, seed=23)
+    for cc in cosmos:
+        cc["N_nu_massless"] = 3.0
+    tabs = [L.Tables(cc, wl.prec, k, 200) for cc in cosmos]
+    cap = wl.prec["max_steps"] + 1
+
+    def record(tb):
+        n = len(tb)
+        S = torch.empty((n, len(k), 3, 200), dtype=torch.float64, device="cuda:0")
+        st = torch.empty((n, len(k)), dtype=torch.int32, device="cuda:0")
+        H = torch.empty((n, len(k), cap), dtype=torch.float64, device="cuda:0")
+        Hn = torch.empty((n, len(k)), dtype=torch.int32, device="cuda:0")
+        ctx.perturb_record(tb, S, st, H, Hn)
+        torch.cuda.synchronize()
+        return S, st, H, Hn
+
+    S, st, H, Hn = record(tabs)
+    S1, st1, H1, Hn1 = record([tabs[5]])
+    assert torch.all(st == 0) and torch.all(st1 == 0)
+    assert torch.equal(Hn[5], Hn1[0])
+    for i in range(len(k)):
+        n = int(Hn1[0, i].item())
+        assert torch.equal(H[5, i, :n + 1], H1[0, i, :n + 1]), i
+    assert torch.equal(S[5], S1[0])
+    S2 = torch.empty_like(S)
+    st2 = torch.empty_like(st)
+    ctx.perturb_replay(tabs, H, Hn, S2, st2)
+    torch.cuda.synchronize()
+    assert torch.all(st2 == 0) and torch.equal(S2, S)
 
 
 def test_batched_parity_box_cosmologies(ctx):
