@@ -64,6 +64,12 @@ struct DevTab {
     double *ck_out;
     const double *ck_in;
     int ck_every, ck_cap, ck_seg, ck_pad;
+    // step trajectory of a replay (for the reverse sweep): per accepted step
+    // of the replayed steps (a segment's, counted from its first), the record
+    // [t_n, h, t_{n+1}, y_n (N), K_0 .. K_{s-1} (s N)] in traj_out
+    // [n_k][traj_cap][traj_rec(N)]; NULL when unused
+    double *traj_out;
+    int traj_cap, traj_pad;
     double L0, inv_dl;
     int n_tab, n_k, n_tau, pad;
     double tau0, R_nu;
@@ -73,6 +79,11 @@ struct DevTab {
     double chi_star;
     double rtol_small, rtol_large, atol_small, atol_large, k_split;
 };
+
+// doubles of one step-trajectory record for N state rows (the ESDIRK's six
+// stage derivatives)
+constexpr int kTrajStages = 6;
+constexpr int traj_rec(int N) { return 3 + (1 + kTrajStages) * N; }
 
 // Static options shared by one launch.
 struct DevPrec {

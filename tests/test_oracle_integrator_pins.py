@@ -166,7 +166,7 @@ def test_kernel_tableau_is_the_oracle_tableau():
     """The perturbation kernel types the same rationals separately; they must
     be the same numbers (error weights b - bh included)."""
     c, A, bh = _oracle_tableau()
-    src = open(os.path.join(ROOT, "paper_2602_15104_amd", "csrc", "k_perturb2.hip")).read()
+    src = open(os.path.join(ROOT, "paper_2602_15104_amd", "csrc", "k1_common.h")).read()
     kc = _elements(_initializer(src, "Kc"))
     kA = _elements(_initializer(src, "Ka"))
     ke = _elements(_initializer(src, "Ke"))
