@@ -191,6 +191,35 @@ int cmb_cl(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max
 int cmb_solve(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_S, double *d_Delta,
               double *d_Cl, int32_t *d_status, int32_t *d_nsteps, void *hip_stream);
 
+/* ------------------------------------------------------ no allocation */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the whole
+ * path of cmb_solve with every intermediate -- table copies, sources,
+ * transfer functions, step counts when d_nsteps is NULL -- in a fixed device
+ * array of CMB_NOALLOC_SCRATCH_MB MiB that the library holds on each device
+ * it runs on, from that device's first call until the process ends.  The
+ * call allocates nothing: no hipMalloc, hipFree or pinned staging; it needs
+ * no context and runs on the current device.
+ *   tabs, n_cosmo: as cmb_solve (cosmologies sharing n_k, n_tau and the
+ *     static options); their host arrays are copied into the scratch array
+ *     on hip_stream, so the tables must stay alive until the stream has
+ *     reached this work;
+ *   d_Cl [n_cosmo][3][ell_max+1], d_status [n_cosmo][n_k], d_nsteps
+ *     [n_cosmo][n_k] (may be NULL): device, caller-owned, as cmb_solve.
+ * Asynchronous on hip_stream.  Every call on one device shares that device's
+ * array and leaves the last call's intermediates in it: calls that overlap
+ * on one device (other streams, other host threads) race, calls on one
+ * stream are ordered.  Errors: CMB_E_INVALID as cmb_solve; CMB_E_NOMEM when
+ * the batch's tables, sources and transfer functions exceed the array
+ * (cmb_noalloc_scratch_bytes; one config-1 cosmology -- 400 modes, 2000
+ * output times, l <= 2500 -- needs 36 MiB); CMB_E_UNSUPPORTED and
+ * CMB_E_DEVICE as cmb_solve.  On an error nothing is launched and the
+ * outputs are untouched. */
+#define CMB_NOALLOC_SCRATCH_MB 160
+size_t cmb_noalloc_scratch_bytes(void);
+int cmb_solve_noalloc(const cmb_tables *const *tabs, int n_cosmo, int ell_max, double *d_Cl, int32_t *d_status,
+                      int32_t *d_nsteps, void *hip_stream);
+
 /* ------------------------------------------------------- transfer k-grid */
 /* Transfer k-grid of App. A.2 (eq. k_transfer_spacing):
  *   k_{n+1} = k_n + k_period linstep k_n / (k_n + linstep/logstep),

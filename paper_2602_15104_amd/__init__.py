@@ -48,7 +48,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_perturb_segment", "cmb_jacobian",
            "cmb_spectra_adjoint", "cmb_state_rows", "cmb_sources_adjoint",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
-           "cmb_server_destroy", "cmb_server_selftest_arena"]
+           "cmb_server_destroy", "cmb_server_selftest_arena", "cmb_solve_noalloc", "cmb_noalloc_scratch_bytes"]
 
 
 class CmbError(RuntimeError):
@@ -142,6 +142,9 @@ def _declare(lib):
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.cmb_solve_noalloc.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
+    lib.cmb_noalloc_scratch_bytes.argtypes = []
+    lib.cmb_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.cmb_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(CServerOpts), ctypes.POINTER(_vp)]
     lib.cmb_server_submit.argtypes = [_vp, ctypes.POINTER(CCosmo), ctypes.POINTER(CPrec), _dp, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
@@ -417,6 +420,18 @@ class Context:
 
 def workspace_bytes(tabs) -> int:
     return int(_lib.cmb_solve_workspace_bytes(_handles(tabs), len(tabs)))
+
+
+def solve_noalloc(tabs, ell_max, Cl, status, nsteps=None, stream=None):
+    """cmb_solve_noalloc: the whole path on the current device with every
+    intermediate in the library's fixed device array (no allocation)."""
+    hs = _handles(tabs)
+    _check(_lib.cmb_solve_noalloc(hs, len(tabs), int(ell_max), _ptr(Cl), _ptr(status), _ptr(nsteps),
+                                  _stream(stream)), "cmb_solve_noalloc")
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(_lib.cmb_noalloc_scratch_bytes())
 
 
 def alloc_outputs(tabs, ell_max: int, device: str = "cuda:0", keep_S: bool = True, keep_Delta: bool = True):
