@@ -497,12 +497,35 @@ def main():
                                 "cosmologies_integrated": B * 17, "batch": B,
                                 "modes_not_ok": int((Js != 0).sum().item())}
         del Jc, Jj, Js
+        # the discrete adjoint: C_l and dL/dtheta of L = sum gC C_l for seeded
+        # gC (record with checkpoints, spectrum-side reverse mode, segment
+        # replays and the reverse ESDIRK sweep, table tangents; host table
+        # builds of the perturbed cosmologies included)
+        gen = torch.Generator(device="cpu").manual_seed(61)
+        gC = torch.randn((B, 3, lmax + 1), generator=gen, dtype=torch.float64).to(dev)
+        Gc = torch.empty((B, 3, lmax + 1), dtype=torch.float64, device=dev)
+        Gg = torch.empty((B, 6), dtype=torch.float64, device=dev)
+        Gs = torch.empty((B, n_k), dtype=torch.int32, device=dev)
+        tgs = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            tg0 = time.perf_counter()
+            ctx.gradient(tabs, lmax, gC, Gc, Gg, Gs, rel=1e-4)
+            torch.cuda.synchronize()
+            tgs.append(time.perf_counter() - tg0)
+        tg = min(tgs)
+        variants["gradient"] = {"s_per_batch": tg, "gradients_per_s": B / tg, "rel": 1e-4, "batch": B,
+                                "jacobian_over_adjoint_time": tj / tg, "modes_not_ok": int((Gs != 0).sum().item()),
+                                "what": "cmb_gradient: record + checkpoints, spectrum-side adjoint, per 64-step "
+                                        "segment a replay and the reverse ESDIRK sweep, table tangents"}
+        del gC, Gc, Gg, Gs
         print(f"[bench] variants: transfer grid {variants['transfer_grid']['ms_per_batch']:.1f} ms, "
               f"perturb+pk {variants['perturb_pk']['ms_per_batch']:.1f} ms, "
               f"los three-region {variants['los_bessel3']['ms_per_batch']:.1f} ms, lensing "
               f"{variants['lensing']}, spectra adjoint {variants['spectra_adjoint']['ms_per_batch']:.1f} ms, "
               f"sources adjoint {variants['sources_adjoint']['ms_per_cosmology']:.2f} ms per cosmology, "
-              f"checkpoints {variants['checkpoints']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s",
+              f"checkpoints {variants['checkpoints']}, jacobian {variants['jacobian']['s_per_batch']:.2f} s, "
+              f"adjoint gradient {variants['gradient']['s_per_batch']:.2f} s",
               file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (algorithmic flops / measured duration):

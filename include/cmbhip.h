@@ -312,6 +312,47 @@ int cmb_perturb_segment(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo
 int cmb_jacobian(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, double rel, int order,
                  double *d_Cl, double *d_J, int32_t *d_status, void *hip_stream);
 
+/* Gradient of a scalar L of the spectra with respect to theta = (h, omega_b,
+ * omega_cdm, ln A_s, n_s, tau_reio), by the discrete adjoint of the whole
+ * path (section 3; App. A.2, the integrator's reverse-mode adjoint with
+ * recursive checkpoints): given dL/dC_l, the spectra and dL/dtheta for a
+ * batch of cosmologies (each with tau_reio given), in one call:
+ *   1. the base run, recording each mode's accepted steps and a checkpoint
+ *      (state and carried stage derivative) every 64 of them; projection and
+ *      k quadrature to C_l;
+ *   2. dL/dS by the transposes of the k quadrature and the projection
+ *      (cmb_spectra_adjoint);
+ *   3. segment by segment, last first: a replay of the segment's steps from
+ *      its checkpoint that keeps every step's stages, then the reverse
+ *      sweep over them: per step, the transposed dense output forced by the
+ *      transposed source functions at the output times inside it, and per
+ *      implicit stage (last to first) the transposed stage solve
+ *      (I - h gamma A)^T, the transposed A and the stage weights.  The
+ *      steps are frozen (the derivative of the recorded discrete map);
+ *   4. the tables' dependence on h, omega_b, omega_cdm and tau_reio as
+ *      central differences of the tables at theta_p (1 +- rel), built on
+ *      host threads: contracted with the sweep's stage adjoints (the stage
+ *      matrices, the sources at fixed state, the initial conditions) and,
+ *      for the projection's geometry, as the spectra of the base sources
+ *      under the perturbed tables;
+ *   5. dL/d ln A_s = sum dL/dC_l C_l, and dL/dn_s from the k quadrature
+ *      weighted by ln(k/k_pivot).
+ *   d_gCl:   device [n_cosmo][3][ell_max+1] dL/dC_l (TT, TE, EE; l < 2 ignored);
+ *   d_Cl:    device [n_cosmo][3][ell_max+1] the spectra (output, as cmb_solve);
+ *   d_grad:  device [n_cosmo][6] dL/dtheta (output);
+ *   d_status: device [n_cosmo][n_k] the base run's per-mode status, or a
+ *            failing segment replay's;
+ *   d_dLdy0: device [n_cosmo][n_k][cmb_state_rows] dL/dy at each mode's start
+ *            state (before the initial conditions' own dependence on theta),
+ *            or NULL.
+ * 0 < rel <= 0.01.  Massless neutrinos only (CMB_E_UNSUPPORTED otherwise).
+ * Workspace from the context: about 250 MB per cosmology of config-1 size
+ * (400 modes, 2000 output times, l <= 2500).  Synchronises hip_stream before
+ * returning (the perturbed tables are temporary).  Errors: CMB_E_INVALID,
+ * CMB_E_UNSUPPORTED, CMB_E_DEVICE, CMB_E_NOMEM. */
+int cmb_gradient(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_gCl,
+                 double rel, double *d_Cl, double *d_grad, int32_t *d_status, double *d_dLdy0, void *hip_stream);
+
 /* Reverse mode of the spectrum side (the first two steps of the discrete
  * adjoint): given dL/dC_l for a scalar L of the spectra, the gradient with
  * respect to the sources, dL/dS, through the transposes of the k quadrature

@@ -45,7 +45,7 @@ EXPORTS = ["cmb_abi_version", "cmb_defaults", "cmb_last_error", "cmb_tables_buil
            "cmb_los", "cmb_cl", "cmb_solve", "cmb_perturb_pk", "cmb_transfer_kgrid", "cmb_spectra_on_grid",
            "cmb_bessel3_table", "cmb_los_bessel3", "cmb_perturb_matter", "cmb_lensing_potential",
            "cmb_lensed_cl", "cmb_perturb_record", "cmb_perturb_replay", "cmb_perturb_checkpoint",
-           "cmb_perturb_segment", "cmb_jacobian",
+           "cmb_perturb_segment", "cmb_jacobian", "cmb_gradient",
            "cmb_spectra_adjoint", "cmb_state_rows", "cmb_sources_adjoint",
            "cmb_server_create", "cmb_server_submit", "cmb_server_wait",
            "cmb_server_destroy", "cmb_server_selftest_arena", "cmb_solve_noalloc", "cmb_noalloc_scratch_bytes"]
@@ -139,6 +139,8 @@ def _declare(lib):
     lib.cmb_sources_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_jacobian.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                  _vp, _vp, _vp, _vp]
+    lib.cmb_gradient.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double, _vp, _vp,
+                                 _vp, _vp, _vp]
     lib.cmb_los_bessel3.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_cl.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
     lib.cmb_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -383,6 +385,13 @@ class Context:
         hs = _handles(tabs)
         _check(_lib.cmb_jacobian(self._h, hs, len(tabs), int(ell_max), float(rel), int(order), _ptr(Cl), _ptr(J),
                                  _ptr(status), _stream(stream)), "cmb_jacobian")
+
+    def gradient(self, tabs, ell_max, gCl, Cl, grad, status, rel=1e-4, dLdy0=None, stream=None):
+        """C_l and dL/d(h, omega_b, omega_cdm, ln A_s, n_s, tau_reio) for
+        L = sum dL/dC_l C_l by the discrete adjoint (cmb_gradient)."""
+        hs = _handles(tabs)
+        _check(_lib.cmb_gradient(self._h, hs, len(tabs), int(ell_max), _ptr(gCl), float(rel), _ptr(Cl), _ptr(grad),
+                                 _ptr(status), _ptr(dLdy0), _stream(stream)), "cmb_gradient")
 
     def lensed_cl(self, Cl, Clpp, ell_max, Cll, n_mu=None, stream=None):
         """Lensed TT, TE, EE, BB [n][4][ell_max+1] from unlensed Cl[n][3][L+1]

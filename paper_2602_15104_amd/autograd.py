@@ -9,13 +9,14 @@ spectra_from_sources(context, tabs, ell_max, S) -> C_l [n][3][ell_max+1]
 
 cl_of_params(context, theta, base_cosmo, prec, k, n_tau, ell_max) -> C_l
     differentiable in theta [n][6] = (h, omega_b, omega_cdm, ln A_s, n_s,
-    tau_reio): the forward pass builds each row's tables and calls
-    cmb_jacobian, which returns C_l and dC_l/dtheta together; the backward
-    pass contracts the incoming dL/dC_l with the stored dC_l/dtheta.
+    tau_reio): the forward pass builds each row's tables and runs the path
+    (cmb_solve); the backward pass hands the incoming dL/dC_l to
+    cmb_gradient, the discrete adjoint of the path (reverse ESDIRK sweep over
+    checkpointed segments), which returns dL/dtheta.
 
 Argument marshalling only: projection, quadrature, their transposes, the
-perturbation replays and the finite-difference stencil run in the library's
-kernels (the library must be loaded; there is no fallback).
+perturbation runs, the reverse sweep and the gradient's assembly run in the
+library's kernels (the library must be loaded; there is no fallback).
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import math
 
 import torch
 
-from . import Tables
+from . import Tables, solve_batch
 
 #: the parameters of cl_of_params, in the column order of theta
 PARAMS = ("h", "omega_b", "omega_cdm", "ln_A_s", "n_s", "tau_reio")
@@ -71,38 +72,39 @@ def spectra_from_sources(context, tabs, ell_max: int, S: torch.Tensor) -> torch.
 
 class _ClOfParams(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, theta, context, base_cosmo, prec, k, n_tau, ell_max, rel, order, device):
+    def forward(fctx, theta, context, base_cosmo, prec, k, n_tau, ell_max, rel, device):
         th = theta.detach().to("cpu", torch.float64)
         if th.dim() != 2 or th.shape[1] != 6:
             raise ValueError("theta must be [n][6] = (h, omega_b, omega_cdm, ln A_s, n_s, tau_reio)")
         n = int(th.shape[0])
         tabs = [Tables(_cosmo_at(base_cosmo, th[i].tolist()), prec, k, n_tau) for i in range(n)]
-        Cl = torch.empty((n, 3, ell_max + 1), dtype=torch.float64, device=device)
-        J = torch.empty((n, 6, 3, ell_max + 1), dtype=torch.float64, device=device)
-        status = torch.empty((n, len(tabs[0].k)), dtype=torch.int32, device=device)
-        stream = torch.cuda.current_stream(device).cuda_stream
-        context.jacobian(tabs, ell_max, Cl, J, status, rel=rel, order=order, stream=stream)
-        if int(status.abs().max().item()) != 0:
-            raise RuntimeError("cmb_jacobian: a perturbation mode failed (per-mode status is nonzero)")
-        fctx.save_for_backward(J)
-        fctx.theta_meta = (theta.dtype, theta.device)
-        return Cl
+        out = solve_batch(context, tabs, ell_max, keep_S=False, keep_Delta=False,
+                          stream=torch.cuda.current_stream(device).cuda_stream)
+        if int(out["status"].abs().max().item()) != 0:
+            raise RuntimeError("cmb_solve: a perturbation mode failed (per-mode status is nonzero)")
+        fctx.meta = (context, tabs, ell_max, rel, device, theta.dtype, theta.device)
+        return out["Cl"]
 
     @staticmethod
     def backward(fctx, gCl):
-        (J,) = fctx.saved_tensors
-        dtype, dev = fctx.theta_meta
-        # vector-Jacobian product: dL/dtheta_p = sum over (type, l) of dL/dC_l dC_l/dtheta_p
-        g = (J * gCl.to(J.device, torch.float64).unsqueeze(1)).sum(dim=(2, 3))
-        return g.to(dev, dtype), None, None, None, None, None, None, None, None, None
+        context, tabs, ell_max, rel, device, dtype, dev = fctx.meta
+        n, n_k = len(tabs), len(tabs[0].k)
+        g = gCl.to(device, torch.float64).contiguous()
+        Cl = torch.empty((n, 3, ell_max + 1), dtype=torch.float64, device=device)
+        grad = torch.empty((n, 6), dtype=torch.float64, device=device)
+        status = torch.empty((n, n_k), dtype=torch.int32, device=device)
+        context.gradient(tabs, ell_max, g, Cl, grad, status, rel=rel,
+                         stream=torch.cuda.current_stream(device).cuda_stream)
+        if int(status.abs().max().item()) != 0:
+            raise RuntimeError("cmb_gradient: a perturbation mode failed (per-mode status is nonzero)")
+        return grad.to(dev, dtype), None, None, None, None, None, None, None, None
 
 
 def cl_of_params(context, theta: torch.Tensor, base_cosmo: dict, prec: dict, k, n_tau: int, ell_max: int,
-                 rel: float = 1e-4, order: int = 4, device: str = "cuda:0") -> torch.Tensor:
-    """C_l [n][3][ell_max+1] at theta [n][6]; backward gives dL/dtheta
-    through cmb_jacobian's derivatives (frozen-step five-point differences
-    for h, omega_b, omega_cdm, tau_reio; exact for ln A_s and n_s).
-    base_cosmo supplies every other parameter; theta's tau_reio replaces any
-    z_reio in it."""
-    return _ClOfParams.apply(theta, context, base_cosmo, prec, k, int(n_tau), int(ell_max), float(rel), int(order),
-                             device)
+                 rel: float = 1e-4, device: str = "cuda:0") -> torch.Tensor:
+    """C_l [n][3][ell_max+1] at theta [n][6]; backward gives dL/dtheta by
+    cmb_gradient (the discrete adjoint of the frozen-step path; the tables'
+    dependence on h, omega_b, omega_cdm and tau_reio by central differences
+    at relative step rel; ln A_s and n_s exact).  base_cosmo supplies every
+    other parameter; theta's tau_reio replaces any z_reio in it."""
+    return _ClOfParams.apply(theta, context, base_cosmo, prec, k, int(n_tau), int(ell_max), float(rel), device)

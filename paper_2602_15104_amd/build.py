@@ -20,7 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["k_perturb2.hip", "k_los.hip", "k_cl.hip", "k_interp.hip", "k_los3.hip", "k_lens.hip", "noalloc.hip"]
+HIP_SOURCES = ["k_perturb2.hip", "k_los.hip", "k_cl.hip", "k_interp.hip", "k_los3.hip", "k_lens.hip", "noalloc.hip",
+               "k_adjoint.hip"]
 CPP_SOURCES = ["tables.cpp", "abi.cpp", "server.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

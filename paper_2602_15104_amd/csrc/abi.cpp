@@ -886,6 +886,85 @@ static int perturb_hist(cmb_ctx *c, const cmb_tables *const *tabs, int n, const 
     return cmbhip::launch_perturb2(dt, n, b.n_k, b.n_tau, b.prec, d_S, d_status, ns, nullptr, nullptr, s, true);
 }
 
+// trajectory checkpoint spacing of the reverse sweep (accepted steps per segment)
+constexpr int kGradEvery = 64;
+
+// Tables at theta_p (1 + mult[m] rel) for the four table parameters p = h,
+// omega_b, omega_cdm, tau_reio, one per base cosmology and (p, m), built on
+// up to 16 worker threads in parameter order, so that the device can start on
+// the parameters already built.  wait(p) blocks until every table of p is
+// built and returns the first failing build's code.  The destructor joins the
+// workers (the tables live as long as the object).
+class PerturbedTables {
+  public:
+    PerturbedTables(const cmb_tables *const *tabs, int nb, int n_k, int n_tau, double rel, const double *mult, int nm)
+        : tabs_(tabs), nb_(nb), nm_(nm), n_k_(n_k), n_tau_(n_tau), rel_(rel), mult_(mult, mult + nm), pert_(4), brc_((size_t)4 * nm * nb, CMB_OK),
+          built_(4, 0) {
+        for (int p = 0; p < 4; ++p) pert_[p].resize((size_t)nm * nb);
+        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        try {
+            for (unsigned i = 0; i < nth; ++i) th_.emplace_back([this] { work(); });
+        } catch (const std::exception &) {
+            // no thread could start: build every table here (started workers
+            // share the jobs and are joined in the destructor)
+            if (th_.empty()) work();
+        }
+    }
+    ~PerturbedTables() {
+        for (auto &x : th_) x.join();
+    }
+    PerturbedTables(const PerturbedTables &) = delete;
+    PerturbedTables &operator=(const PerturbedTables &) = delete;
+
+    int wait(int p) {
+        std::unique_lock<std::mutex> bl(mu_);
+        cv_.wait(bl, [&] { return built_[p] == nm_ * nb_; });
+        for (int j = 0; j < nm_ * nb_; ++j)
+            if (brc_[(size_t)p * nm_ * nb_ + j] != CMB_OK) return brc_[(size_t)p * nm_ * nb_ + j];
+        return CMB_OK;
+    }
+    const cmb_tables *get(int p, int m, int cb) const { return pert_[p][(size_t)m * nb_ + cb].get(); }
+    static double value(const cmb_cosmo &c, int p) {
+        return p == 0 ? c.h : p == 1 ? c.omega_b : p == 2 ? c.omega_cdm : c.tau_reio;
+    }
+
+  private:
+    void work() {
+        const size_t n_jobs = (size_t)4 * nm_ * nb_;
+        for (size_t q; (q = next_.fetch_add(1)) < n_jobs;) {
+            const int p = (int)(q / ((size_t)nm_ * nb_)), j = (int)(q % ((size_t)nm_ * nb_)), m = j / nb_,
+                      cb = j % nb_;
+            const cmbhip::Tables &t0 = tabs_[cb]->t;
+            cmb_cosmo cc = t0.cosmo;
+            double *v = p == 0 ? &cc.h : p == 1 ? &cc.omega_b : p == 2 ? &cc.omega_cdm : &cc.tau_reio;
+            *v *= 1.0 + mult_[m] * rel_;
+            std::unique_ptr<cmb_tables> t(new (std::nothrow) cmb_tables);
+            int r = t ? CMB_OK : CMB_E_NOMEM;
+            try {
+                if (r == CMB_OK) r = cmbhip::build_tables(cc, t0.prec, t0.k.data(), n_k_, n_tau_, t->t);
+            } catch (const std::exception &) {
+                r = CMB_E_INVALID;
+            }
+            if (r == CMB_OK) t->t.uid = cmbhip::g_uid.fetch_add(1);
+            brc_[(size_t)p * nm_ * nb_ + j] = r;
+            pert_[p][j] = std::move(t);
+            std::lock_guard<std::mutex> bl(mu_);
+            if (++built_[p] == nm_ * nb_) cv_.notify_all();
+        }
+    }
+    const cmb_tables *const *tabs_;
+    int nb_, nm_, n_k_, n_tau_;
+    double rel_;
+    std::vector<double> mult_;
+    std::vector<std::vector<std::unique_ptr<cmb_tables>>> pert_;
+    std::vector<int> brc_;
+    std::vector<int> built_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::atomic<size_t> next_{0};
+    std::vector<std::thread> th_;  // last member: joined before the others go
+};
+
 extern "C" {
 
 int cmb_perturb_record(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, double *d_S, int32_t *d_status,
@@ -1005,61 +1084,10 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     const int nb = n_cosmo, nm = order == 4 ? 4 : 2, n_k = b.n_k, n_tau = b.n_tau;
     const double mult[4] = {1.0, -1.0, 2.0, -2.0};
     const int slot[4] = {0, 1, 2, 5};  // h, omega_b, omega_cdm, tau_reio in (h, wb, wc, ln A_s, n_s, tau)
-    // perturbed tables on host threads, pert[p][m nb + cb], built in parameter
-    // order while the device records the base steps and replays the
-    // parameters already built (each replay waits only for its own tables)
-    std::vector<std::vector<std::unique_ptr<cmb_tables>>> pert(4);
-    for (int p = 0; p < 4; ++p) pert[p].resize(nm * nb);
-    std::vector<int> brc(4 * nm * nb, CMB_OK);
-    std::vector<int> built(4, 0);
-    std::mutex bmu;
-    std::condition_variable bcv;
-    std::atomic<size_t> next{0};
-    const size_t n_jobs = (size_t)4 * nm * nb;
-    auto work = [&]() {
-        for (size_t q; (q = next.fetch_add(1)) < n_jobs;) {
-            const int p = (int)(q / ((size_t)nm * nb)), j = (int)(q % ((size_t)nm * nb)), m = j / nb, cb = j % nb;
-            const cmbhip::Tables &t0 = tabs[cb]->t;
-            cmb_cosmo cc = t0.cosmo;
-            double *v = p == 0 ? &cc.h : p == 1 ? &cc.omega_b : p == 2 ? &cc.omega_cdm : &cc.tau_reio;
-            *v *= 1.0 + mult[m] * rel;
-            std::unique_ptr<cmb_tables> t(new (std::nothrow) cmb_tables);
-            int r = t ? CMB_OK : CMB_E_NOMEM;
-            try {
-                if (r == CMB_OK) r = cmbhip::build_tables(cc, t0.prec, t0.k.data(), n_k, n_tau, t->t);
-            } catch (const std::exception &) {
-                r = CMB_E_INVALID;
-            }
-            if (r == CMB_OK) t->t.uid = cmbhip::g_uid.fetch_add(1);
-            brc[(size_t)p * nm * nb + j] = r;
-            pert[p][j] = std::move(t);
-            std::lock_guard<std::mutex> bl(bmu);
-            if (++built[p] == nm * nb) bcv.notify_all();
-        }
-    };
-    struct Joiner {  // every worker is joined on every return path
-        std::vector<std::thread> th;
-        ~Joiner() {
-            for (auto &x : th) x.join();
-        }
-    } workers;
-    {
-        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        try {
-            for (unsigned i = 0; i < nth; ++i) workers.th.emplace_back(work);
-        } catch (const std::exception &) {
-            // no thread could start: build every table here (started workers
-            // share the jobs and are joined on return)
-            if (workers.th.empty()) work();
-        }
-    }
-    auto wait_built = [&](int p) {
-        std::unique_lock<std::mutex> bl(bmu);
-        bcv.wait(bl, [&] { return built[p] == nm * nb; });
-        for (int j = 0; j < nm * nb; ++j)
-            if (brc[(size_t)p * nm * nb + j] != CMB_OK) return brc[(size_t)p * nm * nb + j];
-        return (int)CMB_OK;
-    };
+    // perturbed tables on host threads, built in parameter order while the
+    // device records the base steps and replays the parameters already built
+    // (each replay waits only for its own tables)
+    PerturbedTables pt(tabs, nb, n_k, n_tau, rel, mult, nm);
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
@@ -1099,14 +1127,14 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
     if (rc) return rc;
     // the four table parameters: replays of the base steps at the stencil points
     for (int p = 0; p < 4; ++p) {
-        rc = wait_built(p);
+        rc = pt.wait(p);
         if (rc) {
             set_error("cmb_jacobian: a perturbed table build failed");
             hipStreamSynchronize(s);  // launches already queued use tables freed on return
             return rc;
         }
         std::vector<const cmb_tables *> run(n_run);
-        for (size_t j = 0; j < n_run; ++j) run[j] = pert[p][j].get();
+        for (size_t j = 0; j < n_run; ++j) run[j] = pt.get(p, (int)(j / nb), (int)(j % nb));
         rc = perturb_hist(c, run.data(), (int)n_run, base, hist, hn, cap, true, S, rst, nullptr, s);
         if (rc) return rc;
         rc = cmbhip::launch_los(c->d_tabs, (int)n_run, n_k, n_tau, ell_max, b.polar, b.s_pol, S, D, s);
@@ -1115,9 +1143,7 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
         if (rc) return rc;
         std::vector<double> e(nb);
         for (int cb = 0; cb < nb; ++cb) {
-            const cmb_cosmo &cc = tabs[cb]->t.cosmo;
-            const double v = p == 0 ? cc.h : p == 1 ? cc.omega_b : p == 2 ? cc.omega_cdm : cc.tau_reio;
-            e[cb] = rel * v;
+            e[cb] = rel * PerturbedTables::value(tabs[cb]->t.cosmo, p);
         }
         cmbhip::DevTab *unused = nullptr;
         double *d_e = nullptr;
@@ -1129,6 +1155,182 @@ int cmb_jacobian(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell
         if (rc) return rc;
     }
     hipError_t e = hipStreamSynchronize(s);  // the perturbed tables are freed on return
+    if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
+    set_error("");
+    return CMB_OK;
+}
+
+int cmb_gradient(cmb_ctx *c, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_gCl, double rel,
+                 double *d_Cl, double *d_grad, int32_t *d_status, double *d_dLdy0, void *stream) {
+    if (!c || !tabs || !d_gCl || !d_Cl || !d_grad || !d_status || n_cosmo < 1) {
+        set_error("cmb_gradient: NULL argument");
+        return CMB_E_INVALID;
+    }
+    if (ell_max < 2 || ell_max > 10000 || !(rel > 0.0 && rel <= 0.01)) {
+        set_error("cmb_gradient: need 2 <= ell_max <= 10000 and 0 < rel <= 0.01");
+        return CMB_E_INVALID;
+    }
+    Batch b;
+    int rc = check_batch(tabs, n_cosmo, b);
+    if (rc) return rc;
+    for (int i = 0; i < n_cosmo; ++i)
+        if (!std::isfinite(tabs[i]->t.cosmo.tau_reio)) {
+            set_error("cmb_gradient: every cosmology needs tau_reio (not z_reio)");
+            return CMB_E_INVALID;
+        }
+    if (b.n_tau > cmbhip::los_max_tau()) {
+        set_error("n_tau above the line-of-sight kernel's limit");
+        return CMB_E_UNSUPPORTED;
+    }
+    if (!cmbhip::perturb2_supported(b.prec) || !cmbhip::adjoint_supported(b.prec)) {
+        set_error("cmb_gradient: the reverse sweep takes massless neutrinos only and a hierarchy of at most 320 rows");
+        return CMB_E_UNSUPPORTED;
+    }
+    const int nb = n_cosmo, n_k = b.n_k, n_tau = b.n_tau, N = cmbhip::state_rows(b.prec);
+    const double mult[2] = {1.0, -1.0};
+    // the tables at theta_p (1 +- rel) build on host threads while the device
+    // records the base run and takes the spectrum side's reverse mode
+    PerturbedTables pt(tabs, nb, n_k, n_tau, rel, mult, 2);
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!g.ok) return herr(hipErrorInvalidDevice, "hipSetDevice");
+    StreamOrder so(c, stream);
+    if (so.rc) return so.rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int cap = tabs[0]->t.prec.max_steps + 1, every = kGradEvery, ck_cap = (cap - 1) / every + 1;
+    const int n3 = 3 * (ell_max + 1), nl = ell_max - 1;
+    const size_t nm = (size_t)nb * n_k, nS = nm * 3 * n_tau, nD = (size_t)nb * 2 * nl * n_k;
+    const size_t ck_rec = (size_t)ck_cap * (1 + 2 * (size_t)N), tr_rec = (size_t)every * cmbhip::traj_rec(N);
+    // workspace: hist | hist_n | checkpoints | trajectories | segment sources |
+    // dL/dS | projection adjoint | n_s spectra | perturbed spectra | lambda |
+    // per-mode sums | replay status | replay counts
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t o_h = take(sizeof(double) * nm * cap), o_hn = take(sizeof(int32_t) * nm),
+                 o_ck = take(sizeof(double) * nm * ck_rec), o_tr = take(sizeof(double) * nm * tr_rec),
+                 o_s2 = take(sizeof(double) * nS), o_gs = take(sizeof(double) * nS), o_gw = take(sizeof(double) * nD),
+                 o_cn = take(sizeof(double) * (size_t)nb * n3), o_cp = take(sizeof(double) * 8 * (size_t)nb * n3),
+                 o_lm = take(sizeof(double) * nm * 2 * N), o_ad = take(sizeof(double) * nm * 4),
+                 o_rs = take(sizeof(int32_t) * nm), o_ns = take(sizeof(int32_t) * nm);
+    rc = grow(c, &c->ws_buf, &c->ws_cap, off, s);
+    if (rc) return rc;
+    rc = grow(c, &c->s_buf, &c->s_cap, sizeof(double) * nS, s);
+    if (rc) return rc;
+    rc = grow(c, &c->d_buf, &c->d_cap, sizeof(double) * nD, s);
+    if (rc) return rc;
+    char *w = (char *)c->ws_buf;
+    double *hist = (double *)(w + o_h), *ck = (double *)(w + o_ck), *traj = (double *)(w + o_tr);
+    double *S2 = (double *)(w + o_s2), *gS = (double *)(w + o_gs), *Gw = (double *)(w + o_gw);
+    double *Cns = (double *)(w + o_cn), *Cp = (double *)(w + o_cp), *lam = (double *)(w + o_lm);
+    double *adj = (double *)(w + o_ad);
+    int32_t *hn = (int32_t *)(w + o_hn), *rst = (int32_t *)(w + o_rs), *nsc = (int32_t *)(w + o_ns);
+    double *S = (double *)c->s_buf, *D = (double *)c->d_buf;
+    // (1) record the base run with trajectory checkpoints, project, C_l, the
+    // n_s-weighted quadrature and dL/dS
+    rc = upload(c, tabs, nb, s);
+    if (rc) return rc;
+    {
+        std::vector<cmbhip::DevTab> v(c->h_tabs);
+        for (int i = 0; i < nb; ++i) {
+            v[i].hist_out = hist + (size_t)i * n_k * cap;
+            v[i].hist_out_n = hn + (size_t)i * n_k;
+            v[i].hist_cap = cap;
+            v[i].ck_out = ck + (size_t)i * n_k * ck_rec;
+            v[i].ck_every = every;
+            v[i].ck_cap = ck_cap;
+        }
+        cmbhip::DevTab *dt = nullptr;
+        rc = upload_devtabs(c, v, {}, s, &dt, nullptr);
+        if (rc) return rc;
+        rc = cmbhip::launch_perturb2(dt, nb, n_k, n_tau, b.prec, S, d_status, nsc, nullptr, nullptr, s, true);
+        if (rc) return rc;
+    }
+    rc = cmbhip::launch_los(c->d_tabs, nb, n_k, n_tau, ell_max, b.polar, b.s_pol, S, D, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl(c->d_tabs, nb, n_k, ell_max, D, d_Cl, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_cl_ex(c->d_tabs, nb, n_k, ell_max, D, Cns, (long)n3, 1, s);
+    if (rc) return rc;
+    rc = cmbhip::launch_spectra_adjoint(c->d_tabs, nb, n_k, n_tau, ell_max, b.polar, b.s_pol, D, d_gCl, Gw, gS, s);
+    if (rc) return rc;
+    // (2) every table, base and perturbed, resident at once: base at 0 .. nb-1,
+    // then set q = 2 p + (0: +rel, 1: -rel) at nb + q nb
+    for (int p = 0; p < 4; ++p) {
+        rc = pt.wait(p);
+        if (rc) {
+            set_error("cmb_gradient: a perturbed table build failed");
+            hipStreamSynchronize(s);
+            return rc;
+        }
+    }
+    std::vector<const cmb_tables *> all((size_t)9 * nb);
+    for (int i = 0; i < nb; ++i) all[i] = tabs[i];
+    for (int q = 0; q < 8; ++q)
+        for (int i = 0; i < nb; ++i) all[(size_t)nb + (size_t)q * nb + i] = pt.get(q >> 1, q & 1, i);
+    rc = upload(c, all.data(), 9 * nb, s);
+    if (rc) return rc;
+    const cmbhip::DevTab *d_base = c->d_tabs, *d_pert = c->d_tabs + nb;
+    // (3) the projection's own dependence on the four table parameters: the
+    // base sources under each perturbed geometry
+    for (int q = 0; q < 8; ++q) {
+        rc = cmbhip::launch_los(d_pert + (size_t)q * nb, nb, n_k, n_tau, ell_max, b.polar, b.s_pol, S, D, s);
+        if (rc) return rc;
+        rc = cmbhip::launch_cl(d_pert + (size_t)q * nb, nb, n_k, ell_max, D, Cp + (size_t)q * nb * n3, s);
+        if (rc) return rc;
+    }
+    // (4) segments: as many as the longest recorded history needs
+    std::vector<int32_t> h_hn(nm);
+    hipError_t e = hipMemcpyAsync(h_hn.data(), hn, sizeof(int32_t) * nm, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return herr(e, "step counts to host");
+    int n_seg = 1;
+    for (int32_t x : h_hn) n_seg = std::max(n_seg, (int)((std::max(x, 0) + every - 1) / every));
+    std::vector<cmbhip::DevTab> v((size_t)n_seg * nb);
+    for (int sg = 0; sg < n_seg; ++sg)
+        for (int i = 0; i < nb; ++i) {
+            cmbhip::DevTab &x = v[(size_t)sg * nb + i];
+            x = c->h_tabs[i];
+            x.hist_in = hist + (size_t)i * n_k * cap;
+            x.hist_in_n = hn + (size_t)i * n_k;
+            x.hist_cap = cap;
+            x.ck_in = ck + (size_t)i * n_k * ck_rec;
+            x.ck_every = every;
+            x.ck_cap = ck_cap;
+            x.ck_seg = sg;
+            x.traj_out = traj + (size_t)i * n_k * tr_rec;
+            x.traj_cap = every;
+        }
+    std::vector<double> den((size_t)nb * 4);
+    for (int i = 0; i < nb; ++i)
+        for (int p = 0; p < 4; ++p) den[(size_t)i * 4 + p] = 2.0 * rel * PerturbedTables::value(tabs[i]->t.cosmo, p);
+    cmbhip::DevTab *dseg = nullptr;
+    double *d_den = nullptr;
+    rc = upload_devtabs(c, v, den, s, &dseg, &d_den);
+    if (rc) return rc;
+    // (5) the reverse sweep, last segment first: replay the segment from its
+    // checkpoint writing its step trajectories, then walk them backwards
+    for (int sg = n_seg - 1; sg >= 0; --sg) {
+        rc = cmbhip::launch_perturb2(dseg + (size_t)sg * nb, nb, n_k, n_tau, b.prec, S2, rst, nsc, nullptr, nullptr, s,
+                                     true);
+        if (rc) return rc;
+        rc = cmbhip::launch_merge_status(nb, n_k, 1, rst, d_status, s);
+        if (rc) return rc;
+        rc = cmbhip::launch_adjoint_segment(d_base, d_pert, d_den, nb, n_k, n_tau, b.prec, traj, every, hn, sg, every,
+                                            gS, lam, adj, sg == n_seg - 1, s);
+        if (rc) return rc;
+    }
+    rc = cmbhip::launch_grad_assemble(nb, n_k, ell_max, d_gCl, d_Cl, Cns, Cp, d_den, adj, d_grad, s);
+    if (rc) return rc;
+    if (d_dLdy0) {
+        e = hipMemcpy2DAsync(d_dLdy0, sizeof(double) * N, lam, sizeof(double) * 2 * N, sizeof(double) * N, nm,
+                             hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return herr(e, "dL/dy0 copy");
+    }
+    e = hipStreamSynchronize(s);  // the descriptors' staging and the perturbed tables go on return
     if (e != hipSuccess) return herr(e, "hipStreamSynchronize");
     set_error("");
     return CMB_OK;

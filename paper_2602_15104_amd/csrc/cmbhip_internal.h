@@ -179,6 +179,27 @@ int los_max_tau();
 int launch_sources_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, const DevPrec &p, const double *d_gS,
                            double *d_gY, void *stream);
 int state_rows(const DevPrec &p);
+// reverse sweep of K1 over segment seg (steps seg*every .. of each mode, in
+// reverse) from the step trajectories d_traj [n_cosmo][n_k][traj_cap]
+// [traj_rec(N)] of that segment's replay, forced by d_gS (the sources'
+// adjoint); carries (dL/dy, dL/dK_0) [n_cosmo][n_k][2N] in d_lam between
+// segments and sums dL/dtheta of (h, omega_b, omega_cdm, tau_reio) per mode
+// into d_grad [n_cosmo][n_k][4]; first != 0 for the first launch (the last
+// segment: nothing carried in).  d_ptabs holds 8 sets of n_cosmo tables,
+// set 2p at theta_p (1 + eps), set 2p + 1 at theta_p (1 - eps); d_pden
+// [n_cosmo][4] = 2 eps theta_p.  Massless neutrinos only.
+bool adjoint_supported(const DevPrec &p);
+int launch_adjoint_segment(const DevTab *d_tabs, const DevTab *d_ptabs, const double *d_pden, int n_cosmo, int n_k,
+                           int n_tau, const DevPrec &p, const double *d_traj, int traj_cap, const int *d_hist_n,
+                           int seg, int every, const double *d_gS, double *d_lam, double *d_grad, int first,
+                           void *stream);
+// dL/dtheta [n_cosmo][6] = (h, omega_b, omega_cdm, ln A_s, n_s, tau_reio) from
+// dL/dC_l, C_l, the n_s-weighted C_l, the spectra of the unperturbed sources
+// under the perturbed tables Cp [8][n_cosmo][3][ell_max+1] (sets as d_ptabs),
+// d_pden and the reverse sweep's per-mode sums
+int launch_grad_assemble(int n_cosmo, int n_k, int ell_max, const double *d_gCl, const double *d_Cl,
+                         const double *d_Cns, const double *d_Cp, const double *d_pden, const double *d_adj,
+                         double *d_grad, void *stream);
 int launch_spectra_adjoint(const DevTab *d_tabs, int n_cosmo, int n_k, int n_tau, int ell_max, int want_E,
                            double s_pol, const double *d_Delta, const double *d_gC, double *d_G, double *d_gS,
                            void *stream);

@@ -1,0 +1,693 @@
+// Reverse sweep of the perturbation kernel (K1): the discrete adjoint of its
+// ESDIRK integration with frozen steps, segment by segment from the step
+// trajectories a replay writes (App. A.2 integrator adjoint option; section 3
+// of arXiv 2602.15104).
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "k1_common.h"
+
+namespace cmbhip {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Reverse sweep: the discrete adjoint of the ESDIRK integration with frozen
+// steps (section 3 and the integrator's adjoint option, App. A.2), one group
+// of G lanes per mode as in the forward kernel.
+//
+// A step n maps (y_n, K_0) to y_{n+1} = Y_5 through the stages
+//   R_s = y_n + h sum_{j<s} a_sj K_j,  (I - g A_s) Y_s = R_s,  K_s = A_s Y_s,
+// g = h gamma, A_s = A(t_n + c_s h); K_0 is the previous step's K_5, and the
+// dense output y(t_o) = h00 y_n + h10 hh K_0 + h01 Y_5 + h11 hh K_5 gives the
+// sources.  Backwards, with ybar = dL/dy_n, Kbar_j = dL/dK_j:
+//   Ybar_s = [s = 5: dL/dy_{n+1}] + A_s^T Kbar_s,   Rbar_s = (I - g A_s)^-T Ybar_s,
+//   ybar += Rbar_s,  Kbar_j += h a_sj Rbar_s (j < s),
+// and the matrix A_s itself, through the tables and the background, carries
+// dL/dA_s = (Kbar_s + g Rbar_s) Y_s^T.  Its dependence on the parameters
+// theta_p is taken from central differences of A_s Y_s between the tables
+// built at theta_p (1 +- eps) (the host's table tangents), contracted with
+// (Kbar_s + g Rbar_s); so are the sources' own dependence at fixed state and
+// the initial conditions'.
+//
+// The transposed stage matrix has the forward one's structure: the chains'
+// tridiagonal blocks transposed (a row's sub-diagonal is the previous row's
+// super-diagonal), and the rank-three coupling A = B + u_H w_H^T + u_E w_E^T
+// + u_P w_P^T with the roles of u (how h', eta', Pi enter each row) and w
+// (how each row enters h', eta', Pi) exchanged.  It is solved as the forward
+// one is: each chain eliminated upwards from its highest multipole, its top
+// four rows as affine maps of the three coupling unknowns
+// zeta = (u_H.x, u_E.x, u_P.x), a 3 x 3 system for zeta, then substitution
+// downwards.  The elimination divides by pivots that are those of the
+// forward continuants (a transposed tridiagonal block has the same ones),
+// all >= 1.
+//
+// Per mode and launch: the steps of one segment, in reverse, read from the
+// step trajectory a segment replay of the forward kernel wrote; the running
+// adjoint (dL/dy, dL/dK_0) and the parameter accumulators carry from one
+// segment's launch to the previous one's in global memory.
+
+constexpr int NAF = 4;  // adjoint fields per row: right-hand side, solution, elimination U and V
+constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3;
+constexpr int NPAR = 4;  // parameters with table tangents: h, omega_b, omega_cdm, tau_reio
+
+// the transposed chain coefficients of a row: its diagonal, and the
+// off-diagonals of the transpose (the previous row's super-diagonal, the
+// next row's sub-diagonal); zero outside the row's chain
+__device__ inline void coef_t(int row, const Lay &L, const Bk &s, const DevPrec &p, const DevTab &tb, double &dd,
+                              double &sub, double &sup) {
+    const RowCo c = row_coef(row, L, s, p, tb);
+    dd = c.d;
+    sub = sup = 0.0;
+    Chain cs;
+    if (!chain_of(row, L, cs)) return;
+    if (row > cs.cb) sub = row_coef(row - 1, L, s, p, tb).c;
+    if (row + 1 < cs.cb + cs.cn) sup = row_coef(row + 1, L, s, p, tb).a;
+}
+
+// how a row enters the couplings: h' = w_H . y, eta' = w_E . y, Pi = w_P . y
+// (App. B.3, eqs. hprime and etaprime; Pi = 2 sigma_gamma + G_0 + G_2)
+__device__ inline void w_row(int row, const Lay &L, const Bk &s, const DevPrec &p, double &wH, double &wE, double &wP) {
+    wH = wE = wP = 0.0;
+    if (row == L.rETA) wH = s.cH1;
+    if (row == L.rDC) wH = s.cH2 * s.rc;
+    if (row == 0) wH = s.cH2 * s.rb;
+    if (row == L.rDG) wH = s.cH2 * s.rg;
+    if (row == L.bV) wH = s.cH2 * s.rur;
+    if (row == 1) wE = s.cE * s.rb;
+    if (row == 2) wE = s.cE * (4.0 / 3.0) * s.rg;
+    if (row == L.bV + 1) wE = s.cE * (4.0 / 3.0) * s.rur;
+    if (p.lp > 0) {
+        if (row == 3) wP = 2.0;
+        if (row == L.bG || row == L.bG + 2) wP = 1.0;
+    }
+}
+
+// doubles of LDS per mode of the reverse kernel: a forward slab, the adjoint
+// fields of every row and one vector of N rows (the forcing at an output)
+__host__ __device__ constexpr int adj_slab_doubles(int NP, int nch) {
+    return slab_doubles(NP, nch) + (NP + 2 * PADR) * NAF + NP;
+}
+
+template <int R>
+struct AdjRows {
+    double y[R], K[NSTG][R];  // the step's start state and stage derivatives (forward)
+    double yb[R], Kb[NSTG][R];  // dL/dy_n and dL/dK_j being accumulated
+    double Y5b[R];              // dL/dy_{n+1} (seed of the last stage)
+};
+
+template <int R>
+__global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ tabs, const DevTab *__restrict__ ptabs,
+                                                     const double *__restrict__ pden, int n_cosmo, int n_k, int n_tau,
+                                                     DevPrec p, int G, const double *__restrict__ traj, int traj_cap,
+                                                     const int *__restrict__ hist_n, int seg, int every,
+                                                     const double *__restrict__ gS, double *__restrict__ lam,
+                                                     double *__restrict__ grad, int first) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int gl = lane % G;
+    const int grp = lane / G;
+    const int spw = 64 / G;
+    const int n_sys = n_cosmo * n_k;
+    const int lin = blockIdx.x * spw + grp;
+    const Lay L = make_lay(p);
+    const int NP = G * R;
+    const int N = L.N;
+    const int TR = traj_rec(N);
+    Slab m;
+    double *af, *gv;
+    {
+        double *base = lds + (size_t)grp * adj_slab_doubles(NP, L.nch);
+        m.base = base;
+        m.st = nullptr;  // the multipliers table is not used here
+        m.AX = base + (NP + 2 * PADR) * STR;
+        m.BK = m.AX + ax_doubles(L.nch);
+        af = base + slab_doubles(NP, L.nch);
+        gv = af + (NP + 2 * PADR) * NAF;
+        for (int i = gl; i < adj_slab_doubles(NP, L.nch); i += G) base[i] = 0.0;
+        wsync();
+    }
+    if (lin >= n_sys) return;
+    const int c = lin % n_cosmo, ik = lin / n_cosmo;
+    const DevTab &tb = tabs[c];
+    const double k = tb.k[ik];
+    auto afr = [&](int row) { return af + (row + PADR) * NAF; };
+    auto group_sum = [&](double v) __attribute__((always_inline)) {
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        if (G >= 8) v += dpp_f64<0x141>(v);
+        if (G >= 16) v += dpp_f64<0x140>(v);
+        for (int o = 16; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+        return v;
+    };
+    const size_t mode = (size_t)c * n_k + ik;
+    double *lm = lam + mode * 2 * N;  // dL/dy and dL/dK_0 carried between segments
+    double *gr = grad + mode * NPAR;
+    const double *den = pden + (size_t)c * NPAR;  // 2 eps theta_p of each parameter
+    // tables at theta_p (1 + eps) (q = 2 p) and theta_p (1 - eps) (q = 2 p + 1),
+    // one set of n_cosmo per q
+    auto pt = [&](int q) -> const DevTab & { return ptabs[(size_t)q * n_cosmo + c]; };
+    double acc[NPAR] = {0.0, 0.0, 0.0, 0.0};  // this lane's share of dL/dtheta_p
+
+    AdjRows<R> w;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = gl * R + r;
+        const bool in = row < N && !first;
+        w.Y5b[r] = in ? lm[row] : 0.0;
+        w.Kb[NSTG - 1][r] = in ? lm[N + row] : 0.0;
+    }
+    const double *lo = tb.lna_src;
+    const bool final_seg = seg == 0;
+    int nst = hist_n[mode] - seg * every;  // this mode's steps in the segment
+    nst = nst < 0 ? 0 : (nst > every ? every : nst);
+
+    // Ybar -> A^T Ybar for this lane's rows, the vector in AF_B of every row
+    auto apply_t = [&](const Bk &s, double *out) __attribute__((always_inline)) {
+        double zH = 0.0, zE = 0.0, zP = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            if (row < N) {
+                const RowCo cc = row_coef(row, L, s, p, tb);
+                const double v = afr(row)[AF_B];
+                zH = fma(cc.uH, v, zH);
+                zE = fma(cc.uE, v, zE);
+                zP = fma(cc.uP, v, zP);
+            }
+        }
+        zH = group_sum(zH);
+        zE = group_sum(zE);
+        zP = group_sum(zP);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            double v = 0.0;
+            if (row < N) {
+                double dd, sub, sup, wH, wE, wP;
+                coef_t(row, L, s, p, tb, dd, sub, sup);
+                w_row(row, L, s, p, wH, wE, wP);
+                v = dd * afr(row)[AF_B];
+                if (sub != 0.0) v = fma(sub, afr(row - 1)[AF_B], v);
+                if (sup != 0.0) v = fma(sup, afr(row + 1)[AF_B], v);
+                if (row == 2) v = fma(-(4.0 / 3.0) * s.invHc, afr(L.rDG)[AF_B], v);  // delta_g' = -(4/3) theta_g / Hc ...
+                if (row == L.rDG) v = fma(0.25 * s.k2H, afr(2)[AF_B], v);          // theta_g' = ... + k^2 delta_g / (4 Hc)
+                v = fma(wH, zH, fma(wE, zE, fma(wP, zP, v)));
+            }
+            out[r] = v;
+        }
+    };
+
+    // x = (I - g A)^-T b: b in AF_B of every row, x into AF_X of every row
+    auto solve_t = [&](const Bk &s, double g) __attribute__((always_inline)) {
+        // (1) chains, one lane each: upward elimination x_j = U_j + V_j x_{j-1};
+        // the top four rows' U as affine maps of zeta (constant, H, E, P parts)
+        if (gl < L.nch) {
+            const Chain ch = chain_by_index(gl, L);
+            double U1 = 0.0, V1 = 0.0;  // of the row below
+            // top rows 0..3: affine U, and V (zero beyond a chain shorter than four rows)
+            double tU[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}, tV[4] = {0, 0, 0, 0};
+            for (int j = ch.cn - 1; j >= 0; --j) {
+                const int row = ch.cb + j;
+                double dd, sub, sup, wH, wE, wP;
+                coef_t(row, L, s, p, tb, dd, sub, sup);
+                double piv = 1.0 - g * dd;
+                double rhs = afr(row)[AF_B];
+                double xH = 0.0, xE = 0.0, xP = 0.0;  // coupling columns (top rows)
+                if (j < 4) {
+                    w_row(row, L, s, p, wH, wE, wP);
+                    xH = g * wH;
+                    xE = g * wE;
+                    xP = g * wP;
+                    if (row == 2) {
+                        // delta_g = b_dg + g w_H(dg) zeta_H + g k^2/(4 Hc) x_theta_g, eliminated
+                        // into the theta_g row through its link -(4/3)/Hc
+                        const double lk = g * (4.0 / 3.0) * s.invHc;
+                        double wHd, wEd, wPd;
+                        w_row(L.rDG, L, s, p, wHd, wEd, wPd);
+                        piv = fma(lk, g * 0.25 * s.k2H, piv);
+                        rhs = fma(-lk, afr(L.rDG)[AF_B], rhs);
+                        xH = fma(-lk, g * wHd, xH);
+                    }
+                }
+                // row j: piv x_j - g sub x_{j-1} - g sup x_{j+1} = rhs + x . zeta,
+                // with x_{j+1} = U1 + V1 x_j from below
+                const double p2 = fma(-g * sup, V1, piv);
+                const double ip = rcp(p2);
+                const double V = g * sub * ip;
+                if (j >= 4) {
+                    const double U = fma(g * sup, U1, rhs) * ip;
+                    afr(row)[AF_U] = U;
+                    afr(row)[AF_V] = V;
+                    U1 = U;
+                } else {
+                    // affine: the row below contributes only through its
+                    // constant part (generic rows) or its affine map (top rows)
+                    const double gs = g * sup;
+                    double a0 = rhs, aH = xH, aE = xE, aP = xP;
+                    if (j == 3) {
+                        a0 = fma(gs, U1, a0);
+                    } else {
+                        a0 = fma(gs, tU[j + 1][0], a0);
+                        aH = fma(gs, tU[j + 1][1], aH);
+                        aE = fma(gs, tU[j + 1][2], aE);
+                        aP = fma(gs, tU[j + 1][3], aP);
+                    }
+                    tU[j][0] = a0 * ip;
+                    tU[j][1] = aH * ip;
+                    tU[j][2] = aE * ip;
+                    tU[j][3] = aP * ip;
+                    tV[j] = V;
+                }
+                V1 = V;
+            }
+            // downwards through the top rows: x_j as affine maps of zeta
+            double x0 = tU[0][0], xh = tU[0][1], xe = tU[0][2], xp = tU[0][3];
+            for (int j = 0; j < 4; ++j) {
+                if (j > 0) {
+                    x0 = fma(tV[j], x0, tU[j][0]);
+                    xh = fma(tV[j], xh, tU[j][1]);
+                    xe = fma(tV[j], xe, tU[j][2]);
+                    xp = fma(tV[j], xp, tU[j][3]);
+                }
+                double *q = m.AX + 4 + 16 * gl + 4 * j;
+                q[0] = x0;
+                q[1] = xh;
+                q[2] = xe;
+                q[3] = xp;
+            }
+        }
+        wsync();
+        // (2) one lane: the coupling unknowns zeta = (u_H.x, u_E.x, u_P.x)
+        if (gl == 0) {
+            double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, d[3] = {0, 0, 0};
+            auto add = [&](int row, double x0, double xh, double xe, double xp) {
+                const RowCo cc = row_coef(row, L, s, p, tb);
+                const double u[3] = {cc.uH, cc.uE, cc.uP};
+                for (int i = 0; i < 3; ++i) {
+                    d[i] = fma(u[i], x0, d[i]);
+                    C[i][0] = fma(u[i], xh, C[i][0]);
+                    C[i][1] = fma(u[i], xe, C[i][1]);
+                    C[i][2] = fma(u[i], xp, C[i][2]);
+                }
+            };
+            for (int ch = 0; ch < L.nch; ++ch) {
+                const Chain cs = chain_by_index(ch, L);
+                for (int j = 0; j < 4 && j < cs.cn; ++j) {
+                    const double *q = m.AX + 4 + 16 * ch + 4 * j;
+                    add(cs.cb + j, q[0], q[1], q[2], q[3]);
+                }
+            }
+            double wH, wE, wP;
+            w_row(L.rDC, L, s, p, wH, wE, wP);
+            add(L.rDC, afr(L.rDC)[AF_B], g * wH, 0.0, 0.0);
+            w_row(L.rETA, L, s, p, wH, wE, wP);
+            add(L.rETA, afr(L.rETA)[AF_B], g * wH, 0.0, 0.0);
+            w_row(L.rDG, L, s, p, wH, wE, wP);
+            {
+                const double *q = m.AX + 4 + 4 * 2;  // theta_g, row 2 of the first chain
+                const double lk = g * 0.25 * s.k2H;
+                add(L.rDG, fma(lk, q[0], afr(L.rDG)[AF_B]), fma(lk, q[1], g * wH), lk * q[2], lk * q[3]);
+            }
+            // (I - C) zeta = d by the adjugate
+            const double a00 = 1.0 - C[0][0], a01 = -C[0][1], a02 = -C[0][2];
+            const double a10 = -C[1][0], a11 = 1.0 - C[1][1], a12 = -C[1][2];
+            const double a20 = -C[2][0], a21 = -C[2][1], a22 = 1.0 - C[2][2];
+            const double c00 = fma(a11, a22, -a12 * a21), c01 = fma(a12, a20, -a10 * a22);
+            const double c02 = fma(a10, a21, -a11 * a20), c10 = fma(a02, a21, -a01 * a22);
+            const double c11 = fma(a00, a22, -a02 * a20), c12 = fma(a01, a20, -a00 * a21);
+            const double c20 = fma(a01, a12, -a02 * a11), c21 = fma(a02, a10, -a00 * a12);
+            const double c22 = fma(a00, a11, -a01 * a10);
+            const double idet = 1.0 / fma(a00, c00, fma(a01, c01, a02 * c02));
+            const double zH = fma(c00, d[0], fma(c10, d[1], c20 * d[2])) * idet;
+            const double zE = fma(c01, d[0], fma(c11, d[1], c21 * d[2])) * idet;
+            const double zP = fma(c02, d[0], fma(c12, d[1], c22 * d[2])) * idet;
+            m.AX[0] = zH;
+            m.AX[1] = zE;
+            m.AX[2] = zP;
+            w_row(L.rDC, L, s, p, wH, wE, wP);
+            afr(L.rDC)[AF_X] = fma(g * wH, zH, afr(L.rDC)[AF_B]);
+            w_row(L.rETA, L, s, p, wH, wE, wP);
+            afr(L.rETA)[AF_X] = fma(g * wH, zH, afr(L.rETA)[AF_B]);
+            w_row(L.rDG, L, s, p, wH, wE, wP);
+            const double *q = m.AX + 4 + 4 * 2;
+            const double xtg = fma(q[1], zH, fma(q[2], zE, fma(q[3], zP, q[0])));
+            afr(L.rDG)[AF_X] = fma(g * 0.25 * s.k2H, xtg, fma(g * wH, zH, afr(L.rDG)[AF_B]));
+        }
+        wsync();
+        // (3) chains: the top rows from zeta, the others downwards
+        if (gl < L.nch) {
+            const Chain ch = chain_by_index(gl, L);
+            const double zH = m.AX[0], zE = m.AX[1], zP = m.AX[2];
+            double xp = 0.0;
+            for (int j = 0; j < ch.cn; ++j) {
+                const int row = ch.cb + j;
+                if (j < 4) {
+                    const double *q = m.AX + 4 + 16 * gl + 4 * j;
+                    xp = fma(q[1], zH, fma(q[2], zE, fma(q[3], zP, q[0])));
+                } else {
+                    xp = fma(afr(row)[AF_V], xp, afr(row)[AF_U]);
+                }
+                afr(row)[AF_X] = xp;
+            }
+        }
+        wsync();
+    };
+
+    // mu . (A(theta+) - A(theta-)) v / den for every parameter into acc: v in
+    // the RY records of every row, mu for this lane's rows
+    auto theta_rhs = [&](double tt, const double *mu) __attribute__((always_inline)) {
+        for (int q = 0; q < 2 * NPAR; ++q) {
+            Bk sp;
+            bk_at<false>(pt(q), p, k, tt, sp);
+            if (gl == 0) {
+                double H, E, P;
+                aux_from_rows(m, L, sp, p, pt(q), k, H, E, P);
+                m.AX[0] = H;
+                m.AX[1] = E;
+                m.AX[2] = P;
+            }
+            wsync();
+            double f[R];
+            rhs_rows<R>(m, L, sp, p, pt(q), gl, f);
+            double d = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (gl * R + r < N) d = fma(mu[r], f[r], d);
+            const double dq = (q & 1 ? -d : d) / den[q >> 1];
+#pragma unroll
+            for (int i = 0; i < NPAR; ++i)
+                if ((q >> 1) == i) acc[i] += dq;
+            wsync();
+        }
+    };
+
+    for (int n = nst - 1; n >= 0; --n) {
+        const double *qrec = traj + (mode * traj_cap + n) * TR;
+        const double t = qrec[0], h = qrec[1], tn = qrec[2], hh = tn - t;
+        const double g = h * GAMMA;
+        const bool start = final_seg && n == 0;  // the integration's first step
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            const bool in = row < N;
+            w.y[r] = in ? qrec[3 + row] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NSTG; ++j) w.K[j][r] = in ? qrec[3 + (1 + j) * N + row] : 0.0;
+            w.yb[r] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NSTG - 1; ++j) w.Kb[j][r] = 0.0;
+        }
+        // the output times of this step: (t_n, t_{n+1}], the first step also t_0
+        int o0 = 0, o1 = n_tau;
+        {
+            int lo_i = 0, hi_i = n_tau;  // first index with lo > t (>= t at the start)
+            while (lo_i < hi_i) {
+                const int mid = (lo_i + hi_i) >> 1;
+                if (start ? lo[mid] < t : lo[mid] <= t) lo_i = mid + 1; else hi_i = mid;
+            }
+            o0 = lo_i;
+            lo_i = o0;
+            hi_i = n_tau;  // first index with lo > tn
+            while (lo_i < hi_i) {
+                const int mid = (lo_i + hi_i) >> 1;
+                if (lo[mid] <= tn) lo_i = mid + 1; else hi_i = mid;
+            }
+            o1 = lo_i;
+        }
+        for (int o = o0; o < o1; ++o) {
+            const double th = hh > 0.0 ? (lo[o] - t) / hh : 1.0;
+            const double th2 = th * th, th3 = th2 * th;
+            const double h00 = 2.0 * th3 - 3.0 * th2 + 1.0, h10 = th3 - 2.0 * th2 + th;
+            const double h01 = -2.0 * th3 + 3.0 * th2, h11 = th3 - th2;
+            // dL/dy at this output (transposed sources) into gv, zero elsewhere
+#pragma unroll
+            for (int r = 0; r < R; ++r) gv[gl * R + r] = 0.0;
+            // the interpolated state into the RY records (for the sources' own
+            // parameter dependence); Y_5 = R_5 + g K_5
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double y5 = w.y[r];
+#pragma unroll
+                for (int j = 0; j < NSTG - 1; ++j) y5 = fma(h * Ka[NSTG - 1][j], w.K[j][r], y5);
+                y5 = fma(g, w.K[NSTG - 1][r], y5);
+                m.ry(gl * R + r) = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * y5 + h11 * hh * w.K[NSTG - 1][r];
+            }
+            wsync();
+            if (gl == 0) sources_adj_point<false>(tb, p, L, n_tau, ik, o, gS + mode * 3 * n_tau, gv);
+            wsync();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double G_ = gv[gl * R + r];
+                w.yb[r] = fma(h00, G_, w.yb[r]);
+                w.Kb[0][r] = fma(h10 * hh, G_, w.Kb[0][r]);
+                w.Y5b[r] = fma(h01, G_, w.Y5b[r]);
+                w.Kb[NSTG - 1][r] = fma(h11 * hh, G_, w.Kb[NSTG - 1][r]);
+            }
+            // the sources' own dependence on the parameters at this state: one
+            // perturbed table per lane
+            for (int q = gl; q < 2 * NPAR; q += G) {
+                Bk sp;
+                bk_at<false>(pt(q), p, k, lo[o], sp);
+                double S0, S1, S2;
+                auto yo = [&](int row) { return m.ry(row); };
+                source_values(sp, L, p, k, yo, 0.0, 0.0, 0.0, S0, S1, S2);
+                const double *gs = gS + mode * 3 * n_tau;
+                const double d = (gs[o] * S0 + gs[n_tau + o] * S1 + gs[2 * n_tau + o] * S2) / den[q >> 1];
+#pragma unroll
+                for (int i = 0; i < NPAR; ++i)
+                    if ((q >> 1) == i) acc[i] += (q & 1) ? -d : d;
+            }
+            wsync();
+        }
+        // stages, last to first
+        for (int si = NSTG - 1; si >= 1; --si) {
+            const double ts = (Kc[si] == 1.0) ? tn : t + Kc[si] * h;
+            Bk s;
+            bk_at<false>(tb, p, k, ts, s);
+            double Yb[R], Ys[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double rr = w.y[r];
+#pragma unroll
+                for (int j = 0; j < NSTG - 1; ++j)
+                    if (j < si) rr = fma(h * Ka[si][j], w.K[j][r], rr);
+                double ks = w.K[0][r];
+#pragma unroll
+                for (int j = 1; j < NSTG; ++j)
+                    if (si == j) ks = w.K[j][r];
+                Ys[r] = fma(g, ks, rr);
+                double kb = w.Kb[0][r];
+#pragma unroll
+                for (int j = 1; j < NSTG; ++j)
+                    if (si == j) kb = w.Kb[j][r];
+                afr(gl * R + r)[AF_B] = kb;
+            }
+            wsync();
+            double at[R];
+            apply_t(s, at);  // A_s^T Kbar_s
+            wsync();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Yb[r] = at[r] + (si == NSTG - 1 ? w.Y5b[r] : 0.0);
+                afr(gl * R + r)[AF_B] = Yb[r];
+            }
+            wsync();
+            solve_t(s, g);  // Rbar_s into AF_X
+            double mu[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double rb = gl * R + r < N ? afr(gl * R + r)[AF_X] : 0.0;
+                double kb = w.Kb[0][r];
+#pragma unroll
+                for (int j = 1; j < NSTG; ++j)
+                    if (si == j) kb = w.Kb[j][r];
+                mu[r] = fma(g, rb, kb);
+                w.yb[r] += rb;
+#pragma unroll
+                for (int j = 0; j < NSTG - 1; ++j)
+                    if (j < si) w.Kb[j][r] = fma(h * Ka[si][j], rb, w.Kb[j][r]);
+                m.ry(gl * R + r) = Ys[r];
+            }
+            wsync();
+            theta_rhs(ts, mu);  // the stage matrix's dependence on the parameters
+        }
+        if (start) {
+            // K_0 = A(t_0) y_0 at the start, and y_0 from the initial conditions
+            Bk s;
+            bk_at<false>(tb, p, k, t, s);
+            double at[R], mu[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                afr(gl * R + r)[AF_B] = w.Kb[0][r];
+                m.ry(gl * R + r) = w.y[r];
+                mu[r] = w.Kb[0][r];
+            }
+            wsync();
+            apply_t(s, at);
+            wsync();
+            theta_rhs(t, mu);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                w.yb[r] += at[r];
+                w.Kb[0][r] = 0.0;
+            }
+            for (int q = 0; q < 2 * NPAR; ++q) {
+                Bk sp;
+                bk_at<false>(pt(q), p, k, t, sp);
+                double d = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int row = gl * R + r;
+                    if (row < N) d = fma(w.yb[r], ic_row<false>(row, L, sp, pt(q), k), d);
+                }
+                const double dq = (q & 1 ? -d : d) / den[q >> 1];
+#pragma unroll
+                for (int i = 0; i < NPAR; ++i)
+                    if ((q >> 1) == i) acc[i] += dq;
+            }
+        }
+        // to the previous step: dL/dy_n seeds its last stage, dL/dK_0 its K_5
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w.Y5b[r] = w.yb[r];
+            w.Kb[NSTG - 1][r] = w.Kb[0][r];
+        }
+    }
+    // carry to the previous segment (or, after the first, dL/dy_0)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = gl * R + r;
+        if (row < N) {
+            lm[row] = w.Y5b[r];
+            lm[N + row] = w.Kb[NSTG - 1][r];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NPAR; ++q) {
+        const double v = group_sum(acc[q]);
+        if (gl == 0) gr[q] = (first ? 0.0 : gr[q]) + v;
+    }
+}
+
+
+// The gradient of L = sum dL/dC_l C_l per cosmology, assembled from its
+// parts (one workgroup per cosmology): the reverse sweep's per-mode sums for
+// (h, omega_b, omega_cdm, tau_reio); the projection's own dependence on them
+// from the spectra of the unperturbed sources under the perturbed tables'
+// geometry (central differences); ln A_s (C_l is proportional to A_s) and n_s
+// (the k quadrature weighted by ln(k / k_pivot)).
+constexpr int ASM_THREADS = 256;
+__global__ void __launch_bounds__(ASM_THREADS) grad_assemble_kernel(int n_cosmo, int n_k, int n3,
+                                                                   const double *__restrict__ gCl,
+                                                                   const double *__restrict__ Cl,
+                                                                   const double *__restrict__ Cns,
+                                                                   const double *__restrict__ Cp,
+                                                                   const double *__restrict__ pden,
+                                                                   const double *__restrict__ adj,
+                                                                   double *__restrict__ grad) {
+    __shared__ double red[ASM_THREADS / 64][2 + 2 * NPAR];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const double *g = gCl + (size_t)c * n3;
+    double v[2 + 2 * NPAR];
+    for (int i = 0; i < 2 + 2 * NPAR; ++i) v[i] = 0.0;
+    for (int j = tid; j < n3; j += ASM_THREADS) {
+        const double gj = g[j];
+        v[0] = fma(gj, Cl[(size_t)c * n3 + j], v[0]);
+        v[1] = fma(gj, Cns[(size_t)c * n3 + j], v[1]);
+        for (int i = 0; i < NPAR; ++i) {
+            const double dp = Cp[((size_t)(2 * i) * n_cosmo + c) * n3 + j] - Cp[((size_t)(2 * i + 1) * n_cosmo + c) * n3 + j];
+            v[2 + i] = fma(gj, dp, v[2 + i]);
+        }
+    }
+    for (int ik = tid; ik < n_k; ik += ASM_THREADS)
+        for (int i = 0; i < NPAR; ++i) v[2 + NPAR + i] += adj[((size_t)c * n_k + ik) * NPAR + i];
+    // wavefront sums, then one per wavefront through LDS (fixed order)
+    for (int i = 0; i < 2 + 2 * NPAR; ++i)
+        for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    if ((tid & 63) == 0)
+        for (int i = 0; i < 2 + 2 * NPAR; ++i) red[tid >> 6][i] = v[i];
+    __syncthreads();
+    if (tid == 0) {
+        double t[2 + 2 * NPAR];
+        for (int i = 0; i < 2 + 2 * NPAR; ++i) {
+            t[i] = 0.0;
+            for (int w = 0; w < ASM_THREADS / 64; ++w) t[i] += red[w][i];
+        }
+        // (h, omega_b, omega_cdm, ln A_s, n_s, tau_reio)
+        const int slot[NPAR] = {0, 1, 2, 5};
+        double *gr = grad + (size_t)c * 6;
+        gr[3] = t[0];
+        gr[4] = t[1];
+        for (int i = 0; i < NPAR; ++i) gr[slot[i]] = t[2 + NPAR + i] + t[2 + i] / pden[(size_t)c * NPAR + i];
+    }
+}
+
+template <int R>
+int launch_adj_r(const DevTab *d_tabs, const DevTab *d_ptabs, const double *d_pden, int n_cosmo, int n_k, int n_tau,
+                 const DevPrec &p, int G, const double *d_traj, int traj_cap, const int *d_hist_n, int seg, int every,
+                 const double *d_gS, double *d_lam, double *d_grad, int first, size_t lds, hipStream_t s) {
+    const int spw = 64 / G;
+    const long n_sys = (long)n_cosmo * n_k;
+    const long blocks = (n_sys + spw - 1) / spw;
+    hipLaunchKernelGGL(adjoint_kernel<R>, dim3((unsigned)blocks), dim3(64), lds, s, d_tabs, d_ptabs, d_pden, n_cosmo,
+                       n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg, every, d_gS, d_lam, d_grad, first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("reverse sweep launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+}  // namespace
+
+bool adjoint_supported(const DevPrec &p) {
+    if (p.nq > 0) return false;
+    int R, G;
+    group_shape(p, R, G);
+    const Lay L = make_lay(p);
+    if (G > 64 || (R != 2 && R != 5)) return false;
+    return (size_t)(64 / G) * adj_slab_doubles(G * R, L.nch) * sizeof(double) <= 65536;
+}
+
+int launch_adjoint_segment(const DevTab *d_tabs, const DevTab *d_ptabs, const double *d_pden, int n_cosmo, int n_k,
+                           int n_tau, const DevPrec &p, const double *d_traj, int traj_cap, const int *d_hist_n,
+                           int seg, int every, const double *d_gS, double *d_lam, double *d_grad, int first,
+                           void *stream) {
+    if (!adjoint_supported(p)) {
+        set_error("reverse sweep: massless neutrinos only, and a hierarchy whose records fit 64 KB of LDS per workgroup");
+        return CMB_E_UNSUPPORTED;
+    }
+    if (every < 1 || traj_cap < every || seg < 0 || n_cosmo < 1 || n_k < 1) {
+        set_error("reverse sweep: need every >= 1, traj_cap >= every, seg >= 0");
+        return CMB_E_INVALID;
+    }
+    int R, G;
+    group_shape(p, R, G);
+    const Lay L = make_lay(p);
+    const size_t lds = (size_t)(64 / G) * adj_slab_doubles(G * R, L.nch) * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    if (R == 2)
+        return launch_adj_r<2>(d_tabs, d_ptabs, d_pden, n_cosmo, n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg,
+                               every, d_gS, d_lam, d_grad, first, lds, s);
+    return launch_adj_r<5>(d_tabs, d_ptabs, d_pden, n_cosmo, n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg, every,
+                           d_gS, d_lam, d_grad, first, lds, s);
+}
+
+int launch_grad_assemble(int n_cosmo, int n_k, int ell_max, const double *d_gCl, const double *d_Cl,
+                         const double *d_Cns, const double *d_Cp, const double *d_pden, const double *d_adj,
+                         double *d_grad, void *stream) {
+    const int n3 = 3 * (ell_max + 1);
+    hipLaunchKernelGGL(grad_assemble_kernel, dim3(n_cosmo), dim3(ASM_THREADS), 0, (hipStream_t)stream, n_cosmo, n_k,
+                       n3, d_gCl, d_Cl, d_Cns, d_Cp, d_pden, d_adj, d_grad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("gradient assembly launch: ") + hipGetErrorString(e));
+        return CMB_E_DEVICE;
+    }
+    return CMB_OK;
+}
+
+}  // namespace cmbhip

@@ -1386,11 +1386,12 @@ def test_autograd_spectra_from_sources(ctx):
 
 
 def test_autograd_cl_of_params(ctx):
-    """cl_of_params for two cosmologies (16 modes, l <= 120): C_l and the
-    gradient of sum gC C_l with respect to (h, omega_b, omega_cdm, ln A_s,
-    n_s, tau_reio) equal cmb_jacobian's C_l and its derivatives contracted
-    with gC; against the oracle's frozen-step derivatives contracted with the
-    same gC, each parameter to 1e-6 of sum |gC| |dC/dtheta|."""
+    """cl_of_params for two cosmologies (16 modes, l <= 120): C_l equals
+    cmb_solve's and the gradient of sum gC C_l with respect to (h, omega_b,
+    omega_cdm, ln A_s, n_s, tau_reio) equals cmb_gradient's, bit for bit (the
+    backward pass is that call); against the oracle's frozen-step derivatives
+    contracted with the same gC, each parameter to 1e-4 of
+    sum |gC| |dC/dtheta|."""
     import torch
     import oracle as O
     import paper_2602_15104_amd as L
@@ -1408,25 +1409,24 @@ def test_autograd_cl_of_params(ctx):
     C = AG.cl_of_params(ctx, theta, cosmos[0], wl.prec, wl.k, wl.n_tau, lm)
     (C * torch.tensor(gC0, device="cuda:0")).sum().backward()
     g = theta.grad.numpy()
-    # the same cosmologies through cmb_jacobian directly
+    # the same cosmologies through cmb_solve and cmb_gradient directly
     exact = [AG._cosmo_at(cosmos[0], row) for row in th]
     tabs = [L.Tables(c, wl.prec, wl.k, wl.n_tau) for c in exact]
+    out = L.solve_batch(ctx, tabs, lm, keep_S=False, keep_Delta=False)
     C2 = torch.empty((2, 3, lm + 1), dtype=torch.float64, device="cuda:0")
-    J = torch.empty((2, 6, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    G2 = torch.empty((2, 6), dtype=torch.float64, device="cuda:0")
     st = torch.empty((2, len(wl.k)), dtype=torch.int32, device="cuda:0")
-    ctx.jacobian(tabs, lm, C2, J, st, rel=1e-4, order=4)
+    ctx.gradient(tabs, lm, torch.tensor(gC0, device="cuda:0"), C2, G2, st, rel=1e-4)
     torch.cuda.synchronize()
-    assert torch.equal(C.detach(), C2)
-    Jg = J.cpu().numpy()
-    vjp = np.einsum("ipal,ial->ip", Jg, gC0)
-    assert np.all(np.abs(g - vjp) <= 1e-12 * np.einsum("ipal,ial->ip", np.abs(Jg), np.abs(gC0)))
+    assert torch.equal(C.detach(), out["Cl"]) and torch.equal(C2, out["Cl"])
+    assert np.array_equal(g, G2.cpu().numpy())
     for i, c in enumerate(exact):
         _, Jo, _ = O.jacobian(c, wl.prec, wl.k, wl.n_tau, lm, True, rel=1e-4, order=4)
         for p in range(6):
             ref = float(np.sum(gC0[i] * Jo[p]))
             scale = float(np.sum(np.abs(gC0[i] * Jo[p])))
             _say("autograd theta cosmology", i, "param", AG.PARAMS[p], g[i, p], ref)
-            assert abs(g[i, p] - ref) <= 1e-6 * scale, (i, p)
+            assert abs(g[i, p] - ref) <= 1e-4 * scale, (i, p)
 
 
 def test_batch_consistency_errors(ctx):
