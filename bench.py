@@ -212,7 +212,7 @@ def config2_sweep(ctx, batches):
         n_k = len(wl.k)
         S = torch.empty((B, n_k, 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
         st = torch.empty((B, n_k), dtype=torch.int32, device="cuda:0")
-        D = torch.empty((B, 2, wl.ell_max - 1, n_k), dtype=torch.float64, device="cuda:0")
+        D = torch.empty((B, 2, n_k, wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
         C = torch.empty((B, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         res = []
@@ -289,7 +289,7 @@ def main():
 
     def alloc(b):
         return (torch.empty((b, n_k, 3, n_tau), dtype=torch.float64, device=dev),
-                torch.empty((b, 2, lmax - 1, n_k), dtype=torch.float64, device=dev),
+                torch.empty((b, 2, n_k, lmax - 1), dtype=torch.float64, device=dev),
                 torch.empty((b, 3, lmax + 1), dtype=torch.float64, device=dev),
                 torch.empty((b, n_k), dtype=torch.int32, device=dev),
                 torch.empty((b, n_k), dtype=torch.int32, device=dev))
@@ -352,7 +352,7 @@ def main():
     if args.variants:
         ktg = L.transfer_kgrid(lmax, float(wl.k[0]), float(wl.k[-1]))
         St = torch.empty((B, len(ktg), 3, n_tau), dtype=torch.float64, device=dev)
-        Dt = torch.empty((B, 2, lmax - 1, len(ktg)), dtype=torch.float64, device=dev)
+        Dt = torch.empty((B, 2, len(ktg), lmax - 1), dtype=torch.float64, device=dev)
         Ct = torch.empty((B, 3, lmax + 1), dtype=torch.float64, device=dev)
         Pk = torch.empty((B, n_k), dtype=torch.float64, device=dev)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -165,9 +165,10 @@ int cmb_perturb_pk(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, dou
 /*
  * Line-of-sight projection (App. B.4, transfer integrals; trapezoid in ln a):
  * from sources d_S (layout above, any values) to
- *   d_Delta: device, [n_cosmo][2][ell_max-1][n_k] doubles (Delta_T, Delta_E
- *            for ell = 2..ell_max, k fastest); the E plane is written as 0
- *            when the tables have no polarisation hierarchy.
+ *   d_Delta: device, [n_cosmo][2][n_k][ell_max-1] doubles (Delta_T, Delta_E
+ *            for ell = 2..ell_max, ell fastest: each mode's multipoles are
+ *            contiguous); the E plane is written as 0 when the tables have
+ *            no polarisation hierarchy.
  * Bessel functions by recurrence on the GPU; ell_max in [2, 10000]
  * (else CMB_E_INVALID) and n_tau <= 4096 (else CMB_E_UNSUPPORTED: each
  * 256-lane workgroup holds at most 16 output times per lane).
@@ -240,7 +241,7 @@ int cmb_transfer_kgrid(int ell_max, double k_lo, double k_hi, double *k_out, int
  * and cmb_cl do on the perturbation grid.
  *   kt:      host [n_kt], strictly increasing inside [k_0, k_{n_k-1}]
  *   d_St:    device [n_cosmo][n_kt][3][n_tau], the interpolated sources
- *   d_Delta: device [n_cosmo][2][ell_max-1][n_kt];  d_Cl: device [n_cosmo][3][ell_max+1]
+ *   d_Delta: device [n_cosmo][2][n_kt][ell_max-1];  d_Cl: device [n_cosmo][3][ell_max+1]
  * Caller-owned buffers, asynchronous on hip_stream.  Errors: CMB_E_INVALID,
  * CMB_E_DEVICE, CMB_E_NOMEM. */
 int cmb_spectra_on_grid(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int ell_max, const double *d_S,
@@ -362,7 +363,7 @@ int cmb_gradient(cmb_ctx *ctx, const cmb_tables *const *tabs, int n_cosmo, int e
  *   dL/dS_T0 = w_j sum_l G_T j_l,  dL/dS_T1 = w_j sum_l G_T j_l',
  *   dL/dS_T2 = w_j sum_l [s_pol G_T (3 j_l'' + j_l)/2 + c_l sqrt(6) G_E j_l/x^2],
  * with the projection kernel's Bessel recurrence and cut.
- *   d_Delta: device [n_cosmo][2][ell_max-1][n_k] (cmb_los at these sources);
+ *   d_Delta: device [n_cosmo][2][n_k][ell_max-1] (cmb_los at these sources);
  *   d_gCl:   device [n_cosmo][3][ell_max+1] dL/dC_l (TT, TE, EE; l < 2 ignored);
  *   d_gS:    device [n_cosmo][n_k][3][n_tau] dL/dS.
  * Asynchronous on hip_stream.  Errors: CMB_E_INVALID, CMB_E_UNSUPPORTED,

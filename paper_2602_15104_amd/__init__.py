@@ -454,7 +454,7 @@ def alloc_outputs(tabs, ell_max: int, device: str = "cuda:0", keep_S: bool = Tru
         "nsteps": torch.empty((B, n_k), dtype=torch.int32, device=device),
     }
     out["S"] = torch.empty((B, n_k, 3, n_tau), dtype=torch.float64, device=device) if keep_S else None
-    out["Delta"] = torch.empty((B, 2, ell_max - 1, n_k), dtype=torch.float64, device=device) if keep_Delta else None
+    out["Delta"] = torch.empty((B, 2, n_k, ell_max - 1), dtype=torch.float64, device=device) if keep_Delta else None
     return out
 
 

@@ -46,7 +46,7 @@ class _SpectraFromSources(torch.autograd.Function):
         n, n_k = int(S.shape[0]), int(S.shape[1])
         if n != len(tabs):
             raise ValueError("one table per cosmology row of S")
-        Delta = torch.empty((n, 2, ell_max - 1, n_k), dtype=torch.float64, device=S.device)
+        Delta = torch.empty((n, 2, n_k, ell_max - 1), dtype=torch.float64, device=S.device)
         Cl = torch.empty((n, 3, ell_max + 1), dtype=torch.float64, device=S.device)
         stream = torch.cuda.current_stream(S.device).cuda_stream
         context.los(tabs, ell_max, S, Delta, stream=stream)

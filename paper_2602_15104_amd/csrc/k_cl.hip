@@ -1,10 +1,13 @@
 // K3: k quadrature to the angular power spectra (arXiv 2602.15104, eq.
 // c_ell_def with the primordial spectrum of eq. PK_pivot):
 //   C_l^XY = 4 pi sum_i w_i P(k_i) Delta_X(l,k_i) Delta_Y(l,k_i) / k_i,
-// trapezoid weights w_i on the mode grid, XY in {TT, TE, EE}.  One wavefront
-// per (cosmology, l); lanes stride over k and the wavefront sum uses a fixed
-// shuffle tree, so results are bitwise reproducible.  With dlog set, P(k) is
-// weighted by ln(k/k_pivot): the derivative of C_l with respect to n_s.
+// trapezoid weights w_i on the mode grid, XY in {TT, TE, EE}.  One lane per
+// (cosmology, l): with Delta[c][type][k][l - 2] the lanes of a wavefront
+// read consecutive l of one k (coalesced), and each lane sums over k in
+// order, so results are bitwise reproducible.  The k weights w_i P(k_i)/k_i
+// of the cosmology are formed once per workgroup in LDS (in chunks of
+// CL_KCHUNK modes).  With dlog set, P(k) is weighted by ln(k/k_pivot): the
+// derivative of C_l with respect to n_s.
 //
 // Also the finite-difference combination of spectra for the parameter
 // derivatives (central or five-point stencil).
@@ -15,43 +18,50 @@
 namespace cmbhip {
 namespace {
 
-__global__ void __launch_bounds__(64) cl_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int ell_max,
-                                                const double *__restrict__ Delta, double *__restrict__ Cl,
-                                                long out_stride, int dlog) {
+constexpr int CL_BLOCK = 256;
+constexpr int CL_KCHUNK = 2048;
+
+__global__ void __launch_bounds__(CL_BLOCK) cl_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k,
+                                                      int ell_max, const double *__restrict__ Delta,
+                                                      double *__restrict__ Cl, long out_stride, int dlog) {
+    __shared__ double wk[CL_KCHUNK];
     const int c = blockIdx.y;
-    const int l = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int l = blockIdx.x * CL_BLOCK + threadIdx.x;
     const DevTab &tb = tabs[c];
     double *out = Cl + (size_t)c * out_stride;
-    if (l < 2) {
-        if (lane < 3) out[lane * (ell_max + 1) + l] = 0.0;
-        return;
-    }
     const int nl = ell_max - 1;
-    const double *T = Delta + (size_t)c * 2 * nl * n_k + (size_t)(l - 2) * n_k;
-    const double *E = T + (size_t)nl * n_k;
+    const bool on = l >= 2 && l <= ell_max;
+    const double *T = Delta + (size_t)c * 2 * n_k * nl + (on ? l - 2 : 0);
+    const double *E = T + (size_t)n_k * nl;
     double tt = 0.0, te = 0.0, ee = 0.0;
-    for (int i = lane; i < n_k; i += 64) {
-        double ki = tb.k[i];
-        double kl = i > 0 ? tb.k[i - 1] : ki;
-        double kr = i + 1 < n_k ? tb.k[i + 1] : ki;
-        double f = 0.5 * (kr - kl) * tb.A_s * pow(ki / tb.k_pivot, tb.n_s - 1.0) / ki;
-        if (dlog) f *= log(ki / tb.k_pivot);
-        double t = T[i], e = E[i];
-        tt = fma(f * t, t, tt);
-        te = fma(f * t, e, te);
-        ee = fma(f * e, e, ee);
+    for (int k0 = 0; k0 < n_k; k0 += CL_KCHUNK) {
+        const int nk = n_k - k0 < CL_KCHUNK ? n_k - k0 : CL_KCHUNK;
+        __syncthreads();  // the previous chunk's weights are no longer read
+        for (int j = threadIdx.x; j < nk; j += CL_BLOCK) {
+            const int i = k0 + j;
+            const double ki = tb.k[i];
+            const double kl = i > 0 ? tb.k[i - 1] : ki;
+            const double kr = i + 1 < n_k ? tb.k[i + 1] : ki;
+            double f = 0.5 * (kr - kl) * tb.A_s * pow(ki / tb.k_pivot, tb.n_s - 1.0) / ki;
+            if (dlog) f *= log(ki / tb.k_pivot);
+            wk[j] = f;
+        }
+        __syncthreads();
+        if (on) {
+            const double *Tc = T + (size_t)k0 * nl, *Ec = E + (size_t)k0 * nl;
+            for (int j = 0; j < nk; ++j) {
+                const double f = wk[j], t = Tc[(size_t)j * nl], e = Ec[(size_t)j * nl];
+                tt = fma(f * t, t, tt);
+                te = fma(f * t, e, te);
+                ee = fma(f * e, e, ee);
+            }
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        tt += __shfl_down(tt, off, 64);
-        te += __shfl_down(te, off, 64);
-        ee += __shfl_down(ee, off, 64);
-    }
-    if (lane == 0) {
+    if (l <= ell_max) {
         const double fpi = 4.0 * 3.14159265358979323846;
-        out[l] = fpi * tt;
-        out[(ell_max + 1) + l] = fpi * te;
-        out[2 * (ell_max + 1) + l] = fpi * ee;
+        out[l] = on ? fpi * tt : 0.0;
+        out[(ell_max + 1) + l] = on ? fpi * te : 0.0;
+        out[2 * (ell_max + 1) + l] = on ? fpi * ee : 0.0;
     }
 }
 
@@ -121,7 +131,7 @@ int launch_merge_status(int n_base, int n_k, int n_rep, const int *d_rep, int *d
 
 int launch_cl_ex(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
                  long out_stride, int dlog, void *stream) {
-    dim3 grid((unsigned)(ell_max + 1), (unsigned)n_cosmo), block(64);
+    dim3 grid((unsigned)((ell_max + CL_BLOCK) / CL_BLOCK), (unsigned)n_cosmo), block(CL_BLOCK);
     hipLaunchKernelGGL(cl_kernel, grid, block, 0, (hipStream_t)stream, d_tabs, n_cosmo, n_k, ell_max, d_Delta, d_Cl,
                        out_stride, dlog);
     hipError_t e = hipGetLastError();
@@ -134,15 +144,7 @@ int launch_cl_ex(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const 
 
 int launch_cl(const DevTab *d_tabs, int n_cosmo, int n_k, int ell_max, const double *d_Delta, double *d_Cl,
               void *stream) {
-    dim3 grid((unsigned)(ell_max + 1), (unsigned)n_cosmo), block(64);
-    hipLaunchKernelGGL(cl_kernel, grid, block, 0, (hipStream_t)stream, d_tabs, n_cosmo, n_k, ell_max, d_Delta, d_Cl,
-                       (long)3 * (ell_max + 1), 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        set_error(std::string("cl launch: ") + hipGetErrorString(e));
-        return CMB_E_DEVICE;
-    }
-    return CMB_OK;
+    return launch_cl_ex(d_tabs, n_cosmo, n_k, ell_max, d_Delta, d_Cl, (long)3 * (ell_max + 1), 0, stream);
 }
 
 }  // namespace cmbhip

@@ -54,8 +54,10 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
     const double *S1 = S0 + n_tau;
     const double *S2 = S1 + n_tau;
     const int nl = ell_max - 1;
-    double *DT = Delta + (size_t)c * 2 * nl * n_k;
-    double *DE = DT + (size_t)nl * n_k;
+    // this mode's rows of Delta[c][type][k][l - 2] (l fastest: each workgroup
+    // writes its own contiguous spans)
+    double *DT = Delta + ((size_t)c * 2 * n_k + ik) * nl;
+    double *DE = Delta + ((size_t)(c * 2 + 1) * n_k + ik) * nl;
     const int ltop = ell_max + 1;
 
     double cA[M], cB[M], cC[M], cD[M], cE[M], rx[M], jl[M], jp[M];
@@ -70,7 +72,9 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
         if (j >= n_tau) continue;
         double x = k * tb.chi_src[j];
         double w = tb.w_src[j];
-        double s0 = S0[j], s1 = S1[j], s2 = S2[j];
+        // the sources are read once: streamed past the L2 (nontemporal)
+        double s0 = __builtin_nontemporal_load(S0 + j), s1 = __builtin_nontemporal_load(S1 + j),
+               s2 = __builtin_nontemporal_load(S2 + j);
         double p2 = s_pol * s2;
         if (x == 0.0) {
             // j_l = j_l' = 0, (3j''+j)/2 = delta_l2/5, j_l/x^2 = delta_l2/15
@@ -138,8 +142,8 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
     lstart = lstart < 2 ? 2 : lstart;
     // zeros above the walk
     for (int l = ell_max - tid; l > lstart; l -= BLOCK) {
-        DT[(size_t)(l - 2) * n_k + ik] = 0.0;
-        DE[(size_t)(l - 2) * n_k + ik] = 0.0;
+        DT[l - 2] = 0.0;
+        DE[l - 2] = 0.0;
     }
     const int sum_id = tid >> 3, sub = tid & 7;  // 32 sums x 8 lanes in the reduction
     for (int lb = lstart; lb >= 2; lb -= LB) {
@@ -183,10 +187,10 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
             if (sub == 0 && valid) {
                 int l = lb - i;
                 if (v == 0) {
-                    DT[(size_t)(l - 2) * n_k + ik] = a;
+                    DT[l - 2] = a;
                 } else {
                     double cl = sqrt(3.0 * (l + 2.0) * (l + 1.0) * l * (l - 1.0) / 8.0);
-                    DE[(size_t)(l - 2) * n_k + ik] = want_E ? cl * a : 0.0;
+                    DE[l - 2] = want_E ? cl * a : 0.0;
                 }
             }
         }
@@ -211,21 +215,20 @@ __global__ void __launch_bounds__(256) cl_adj_kernel(const DevTab *__restrict__ 
     const int nl = ell_max - 1;
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long)n_cosmo * nl * n_k) return;
-    const int ik = (int)(t % n_k);
-    const int li = (int)((t / n_k) % nl);
+    const int li = (int)(t % nl);
+    const int ik = (int)((t / nl) % n_k);
     const int c = (int)(t / ((long)nl * n_k));
     const DevTab &tb = tabs[c];
     const double ki = tb.k[ik];
     const double kl = ik > 0 ? tb.k[ik - 1] : ki, kr = ik + 1 < n_k ? tb.k[ik + 1] : ki;
     const double f = 4.0 * 3.14159265358979323846 * 0.5 * (kr - kl) * tb.A_s * pow(ki / tb.k_pivot, tb.n_s - 1.0) / ki;
-    const double *D = Delta + (size_t)c * 2 * nl * n_k;
-    const double dT = D[(size_t)li * n_k + ik], dE = D[(size_t)(nl + li) * n_k + ik];
+    const size_t rT = ((size_t)c * 2 * n_k + ik) * nl + li, rE = rT + (size_t)n_k * nl;  // Delta[c][type][k][l-2]
+    const double dT = Delta[rT], dE = Delta[rE];
     const double *g = gC + (size_t)c * 3 * (ell_max + 1);
     const int l = li + 2;
     const double gtt = g[l], gte = want_E ? g[(ell_max + 1) + l] : 0.0, gee = want_E ? g[2 * (ell_max + 1) + l] : 0.0;
-    double *o = G + (size_t)c * 2 * nl * n_k;
-    o[(size_t)li * n_k + ik] = f * (2.0 * gtt * dT + gte * dE);
-    o[(size_t)(nl + li) * n_k + ik] = want_E ? f * (gte * dT + 2.0 * gee * dE) : 0.0;
+    G[rT] = f * (2.0 * gtt * dT + gte * dE);
+    G[rE] = want_E ? f * (gte * dT + 2.0 * gee * dE) : 0.0;
 }
 
 template <int M>
@@ -239,8 +242,8 @@ __global__ void __launch_bounds__(BLOCK) los_adj_kernel(const DevTab *__restrict
     const DevTab &tb = tabs[c];
     const double k = tb.k[ik];
     const int nl = ell_max - 1;
-    const double *GT = G + (size_t)c * 2 * nl * n_k;
-    const double *GE = GT + (size_t)nl * n_k;
+    const double *GT = G + ((size_t)c * 2 * n_k + ik) * nl;  // this mode's rows of G[c][type][k][l - 2]
+    const double *GE = G + ((size_t)(c * 2 + 1) * n_k + ik) * nl;
     double *g0 = gS + ((size_t)c * n_k + ik) * 3 * n_tau, *g1 = g0 + n_tau, *g2 = g1 + n_tau;
     const int ltop = ell_max + 1;
     double rx[M], jl[M], jp[M], a0[M], a1[M], a2[M];
@@ -308,8 +311,8 @@ __global__ void __launch_bounds__(BLOCK) los_adj_kernel(const DevTab *__restrict
     const int lstart = s_lstart;
     for (int l = lstart; l >= 2; --l) {
         const double fl = (double)l;
-        const double gt = GT[(size_t)(l - 2) * n_k + ik];
-        const double ge = want_E ? GE[(size_t)(l - 2) * n_k + ik] * sqrt(3.0 * (fl + 2.0) * (fl + 1.0) * fl * (fl - 1.0) / 8.0) *
+        const double gt = GT[l - 2];
+        const double ge = want_E ? GE[l - 2] * sqrt(3.0 * (fl + 2.0) * (fl + 1.0) * fl * (fl - 1.0) / 8.0) *
                                        2.449489742783178098
                                  : 0.0;
         const double c21 = 2.0 * fl + 1.0, q = fl * (fl + 1.0);
@@ -327,8 +330,8 @@ __global__ void __launch_bounds__(BLOCK) los_adj_kernel(const DevTab *__restrict
             }
         }
     }
-    const double gt2 = GT[ik];
-    const double ge2 = want_E ? GE[ik] * sqrt(3.0 * 4.0 * 3.0 * 2.0 * 1.0 / 8.0) * 2.449489742783178098 : 0.0;
+    const double gt2 = GT[0];
+    const double ge2 = want_E ? GE[0] * sqrt(3.0 * 4.0 * 3.0 * 2.0 * 1.0 / 8.0) * 2.449489742783178098 : 0.0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int j = tid + m * BLOCK;

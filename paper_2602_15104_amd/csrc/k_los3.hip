@@ -168,8 +168,8 @@ __global__ void __launch_bounds__(BLOCK) los3_kernel(const DevTab *__restrict__ 
     const double *S1 = S0 + n_tau;
     const double *S2 = S1 + n_tau;
     const int nl = ell_max - 1;
-    double *DT = Delta + (size_t)c * 2 * nl * n_k;
-    double *DE = DT + (size_t)nl * n_k;
+    double *DT = Delta + ((size_t)c * 2 * n_k + ik) * nl;  // this mode's rows of Delta[c][type][k][l - 2]
+    double *DE = Delta + ((size_t)(c * 2 + 1) * n_k + ik) * nl;
 
     double cA[M], cB[M], cC[M], cE[M], xx[M], rx[M], jm[M];
     int lstop[M];
@@ -183,7 +183,9 @@ __global__ void __launch_bounds__(BLOCK) los3_kernel(const DevTab *__restrict__ 
         if (j >= n_tau) continue;
         const double x = k * tb.chi_src[j];
         const double w = tb.w_src[j];
-        const double s0 = S0[j], s1 = S1[j], s2 = S2[j];
+        // read once: nontemporal, as in los_kernel
+        const double s0 = __builtin_nontemporal_load(S0 + j), s1 = __builtin_nontemporal_load(S1 + j),
+                     s2 = __builtin_nontemporal_load(S2 + j);
         const double p2 = s_pol * s2;
         if (x == 0.0) {
             // j_l = j_l' = 0, (3j''+j)/2 = delta_l2/5, j_l/x^2 = delta_l2/15
@@ -223,8 +225,8 @@ __global__ void __launch_bounds__(BLOCK) los3_kernel(const DevTab *__restrict__ 
     __syncthreads();
     const int ltop = s_lstop;  // >= 2: l = 2 always visited (x = 0 terms)
     for (int l = ltop + 1 + tid; l <= ell_max; l += BLOCK) {
-        DT[(size_t)(l - 2) * n_k + ik] = 0.0;
-        DE[(size_t)(l - 2) * n_k + ik] = 0.0;
+        DT[l - 2] = 0.0;
+        DE[l - 2] = 0.0;
     }
     const int sum_id = tid >> 3, sub = tid & 7;
     for (int lb = 2; lb <= ltop; lb += LB) {
@@ -265,10 +267,10 @@ __global__ void __launch_bounds__(BLOCK) los3_kernel(const DevTab *__restrict__ 
             if (sub == 0 && valid) {
                 const int l = lb + i;
                 if (v == 0) {
-                    DT[(size_t)(l - 2) * n_k + ik] = a;
+                    DT[l - 2] = a;
                 } else {
                     const double cl = sqrt(3.0 * (l + 2.0) * (l + 1.0) * l * (l - 1.0) / 8.0);
-                    DE[(size_t)(l - 2) * n_k + ik] = want_E ? cl * a : 0.0;
+                    DE[l - 2] = want_E ? cl * a : 0.0;
                 }
             }
         }

@@ -53,6 +53,12 @@ def src_err(Sg, So):
     return worst
 
 
+def lk(D):
+    """Transfer functions as the library lays them out, [..., 2, n_k, l - 2],
+    in the oracle's order [..., 2, l - 2, n_k]."""
+    return np.swapaxes(D, -1, -2)
+
+
 def cl_err(Cg, Co, lmin=2):
     tt = np.max(np.abs(Cg[0, lmin:] / Co[0, lmin:] - 1))
     if np.any(Co[2, lmin:] != 0):
@@ -125,13 +131,13 @@ def test_los_cl_from_same_sources(ctx):
     rng = np.random.Generator(np.random.PCG64(5))
     S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
     dS = torch.tensor(S, device="cuda:0")
-    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
     ctx.los([tab], wl.ell_max, dS, D)
     ctx.cl([tab], wl.ell_max, D, C)
     torch.cuda.synchronize()
     DT, DE = O.los(t_or, S[0], wl.ell_max, True)
-    Dg = D.cpu().numpy()[0]
+    Dg = lk(D.cpu().numpy()[0])
     for ik in range(len(wl.k)):
         for plane, ref in ((0, DT), (1, DE)):
             den = np.max(np.abs(ref[:, ik]))
@@ -160,13 +166,13 @@ def test_los_cl_maximum_sizes(ctx):
     t_or = O.build_tables(wl.cosmo, wl.prec, k, n_tau)
     rng = np.random.Generator(np.random.PCG64(9))
     S = rng.standard_normal((1, len(k), 3, n_tau))
-    D = torch.empty((1, 2, lmax - 1, len(k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(k), lmax - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, lmax + 1), dtype=torch.float64, device="cuda:0")
     ctx.los([tab], lmax, torch.tensor(S, device="cuda:0"), D)
     ctx.cl([tab], lmax, D, C)
     torch.cuda.synchronize()
     DT, DE = O.los(t_or, S[0], lmax, True)
-    Dg = D.cpu().numpy()[0]
+    Dg = lk(D.cpu().numpy()[0])
     worst = 0.0
     for ik in range(len(k)):
         for plane, ref in ((0, DT), (1, DE)):
@@ -179,7 +185,7 @@ def test_los_cl_maximum_sizes(ctx):
     _say("max-size projection err", worst)
     big = L.Tables(wl.cosmo, wl.prec, k[:2], n_tau + 1)
     Sb = torch.zeros((1, 2, 3, n_tau + 1), dtype=torch.float64, device="cuda:0")
-    Db = torch.empty((1, 2, lmax - 1, 2), dtype=torch.float64, device="cuda:0")
+    Db = torch.empty((1, 2, 2, lmax - 1), dtype=torch.float64, device="cuda:0")
     with pytest.raises(L.CmbError) as e:
         ctx.los([big], lmax, Sb, Db)
     assert e.value.name == "CMB_E_UNSUPPORTED"
@@ -204,13 +210,13 @@ def test_spike_source_closed_form_gpu(ctx):
     S[0, :, 0, j] = 1.0 / ex["w_src"][j]
     ell_max = 40
     dS = torch.tensor(S, device="cuda:0")
-    D = torch.empty((1, 2, ell_max - 1, len(k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(k), ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, ell_max + 1), dtype=torch.float64, device="cuda:0")
     ctx.los([tab], ell_max, dS, D)
     ctx.cl([tab], ell_max, D, C)
     torch.cuda.synchronize()
     from scipy.special import spherical_jn
-    Dg = D.cpu().numpy()[0, 0]
+    Dg = lk(D.cpu().numpy()[0, 0])
     for ik in (10, 777, 3000, 5999):
         np.testing.assert_allclose(Dg[:, ik], spherical_jn(np.arange(2, ell_max + 1), k[ik] * chis), rtol=1e-11,
                                    atol=1e-17)
@@ -347,7 +353,7 @@ def test_single_mode_and_lmax2(ctx):
     r = O.solve(wl.cosmo, wl.prec, wl.k, wl.n_tau, 2, True)
     assert src_err(g["S"][0], r["S"]) <= 1e-8
     assert np.all(g["Cl"][0] == 0) and np.all(r["Cl"] == 0)
-    D = g["Delta"][0]
+    D = lk(g["Delta"][0])
     den = np.max(np.abs(r["DT"]))
     assert np.max(np.abs(D[0] - r["DT"])) <= 1e-9 * den
     wl.k = np.array([0.005, 0.01])
@@ -588,11 +594,11 @@ def _gpu_on_grid(ctx, tabs, ell_max, S, kt):
     B, n_tau = len(tabs), tabs[0].n_tau
     dS = S if isinstance(S, torch.Tensor) else torch.tensor(S, device="cuda:0")
     St = torch.empty((B, len(kt), 3, n_tau), dtype=torch.float64, device="cuda:0")
-    D = torch.empty((B, 2, ell_max - 1, len(kt)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((B, 2, len(kt), ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((B, 3, ell_max + 1), dtype=torch.float64, device="cuda:0")
     ctx.spectra_on_grid(tabs, ell_max, dS, kt, St, D, C)
     torch.cuda.synchronize()
-    return St.cpu().numpy(), D.cpu().numpy(), C.cpu().numpy()
+    return St.cpu().numpy(), lk(D.cpu().numpy()), C.cpu().numpy()
 
 
 def test_transfer_grid_interp_same_sources(ctx):
@@ -729,13 +735,13 @@ def test_los_bessel3_same_sources(ctx):
     rng = np.random.Generator(np.random.PCG64(17))
     S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
     dS = torch.tensor(S, device="cuda:0")
-    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
     ctx.los_bessel3([tab], wl.ell_max, dS, D)
     ctx.cl([tab], wl.ell_max, D, C)
     torch.cuda.synchronize()
     DT, DE = B3.los3(t_or, S[0], wl.ell_max, True, T=B3.Table(wl.ell_max))
-    Dg = D.cpu().numpy()[0]
+    Dg = lk(D.cpu().numpy()[0])
     worst = 0.0
     for ik in range(len(wl.k)):
         for plane, ref in ((0, DT), (1, DE)):
@@ -758,7 +764,7 @@ def test_los_bessel3_config1_error(ctx):
     tab = L.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
     g = run_gpu(ctx, [tab], wl.ell_max)
     dS = torch.tensor(g["S"], device="cuda:0")
-    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
     ctx.los_bessel3([tab], wl.ell_max, dS, D)
     ctx.cl([tab], wl.ell_max, D, C)
@@ -935,7 +941,7 @@ def test_lensed_cl_config1(ctx):
     Lu, lmax, n_mu = wl.ell_max, 2000, 3700
     tab = L_.Tables(wl.cosmo, wl.prec, wl.k, wl.n_tau)
     S, st, _, Dm = _gpu_matter(ctx, [tab], want_pk=False)
-    D = torch.empty((1, 2, Lu - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), Lu - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, Lu + 1), dtype=torch.float64, device="cuda:0")
     P = torch.empty((1, Lu + 1), dtype=torch.float64, device="cuda:0")
     ctx.los([tab], Lu, S, D)
@@ -1192,7 +1198,7 @@ def test_spectra_adjoint_parity(ctx):
     S = rng.standard_normal((1, len(wl.k), 3, wl.n_tau))
     gC = rng.standard_normal((1, 3, wl.ell_max + 1))
     dS = torch.tensor(S, device="cuda:0")
-    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     gS = torch.empty_like(dS)
     ctx.los([tab], wl.ell_max, dS, D)
     ctx.spectra_adjoint([tab], wl.ell_max, D, torch.tensor(gC, device="cuda:0"), gS)
@@ -1219,7 +1225,7 @@ def test_spectra_adjoint_dot_product_config1(ctx):
     V = torch.tensor(rng.standard_normal(g["S"].shape) * np.abs(g["S"]).max(axis=-1, keepdims=True), device="cuda:0")
     gC = torch.tensor(rng.standard_normal((1, 3, wl.ell_max + 1)) / np.maximum(np.abs(g["Cl"]), 1e-30),
                       device="cuda:0")
-    D = torch.empty((1, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((1, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     C = torch.empty((1, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
 
     def loss(Sx):
@@ -1323,7 +1329,7 @@ def test_sources_adjoint_chain(ctx):
     rng = np.random.Generator(np.random.PCG64(73))
     S = rng.standard_normal((2, len(wl.k), 3, wl.n_tau))
     gC = rng.standard_normal((2, 3, wl.ell_max + 1))
-    D = torch.empty((2, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((2, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     ctx.los(tabs, wl.ell_max, torch.tensor(S, device="cuda:0"), D)
     gS = torch.empty((2, len(wl.k), 3, wl.n_tau), dtype=torch.float64, device="cuda:0")
     ctx.spectra_adjoint(tabs, wl.ell_max, D, torch.tensor(gC, device="cuda:0"), gS)
@@ -1364,7 +1370,7 @@ def test_autograd_spectra_from_sources(ctx):
     gC = torch.tensor(gC0, device="cuda:0")
     Cl = spectra_from_sources(ctx, tabs, wl.ell_max, S)
     (Cl * gC).sum().backward()
-    D = torch.empty((2, 2, wl.ell_max - 1, len(wl.k)), dtype=torch.float64, device="cuda:0")
+    D = torch.empty((2, 2, len(wl.k), wl.ell_max - 1), dtype=torch.float64, device="cuda:0")
     C2 = torch.empty((2, 3, wl.ell_max + 1), dtype=torch.float64, device="cuda:0")
     Sd = S.detach().clone()
     ctx.los(tabs, wl.ell_max, Sd, D)
@@ -1446,7 +1452,7 @@ def test_batch_consistency_errors(ctx):
     dev = "cuda:0"
     S = torch.full((2, 8, 3, 41), float("nan"), dtype=torch.float64, device=dev)
     st = torch.full((2, 8), -7, dtype=torch.int32, device=dev)
-    D = torch.full((2, 2, 19, 8), float("nan"), dtype=torch.float64, device=dev)
+    D = torch.full((2, 2, 8, 19), float("nan"), dtype=torch.float64, device=dev)
     C = torch.full((2, 3, 21), float("nan"), dtype=torch.float64, device=dev)
     for tabs in ([], [a, other_k], [a, other_tau], [a, other_h]):
         calls = (lambda: ctx.perturb(tabs, S, st), lambda: ctx.los(tabs, 20, S, D),
