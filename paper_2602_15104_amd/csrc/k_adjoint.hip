@@ -48,23 +48,17 @@ namespace {
 // adjoint (dL/dy, dL/dK_0) and the parameter accumulators carry from one
 // segment's launch to the previous one's in global memory.
 
-constexpr int NAF = 4;  // adjoint fields per row: right-hand side, solution, elimination U and V
-constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3;
+constexpr int NAF = 7;  // adjoint fields per row
+// right-hand side, solution, elimination U and V, and the row's coupling
+// coefficients u_H, u_E, u_P (how h', eta', Pi enter it) at the current stage
+constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3, AF_UH = 4, AF_UE = 5, AF_UP = 6;
 constexpr int NPAR = 4;  // parameters with table tangents: h, omega_b, omega_cdm, tau_reio
-
-// the transposed chain coefficients of a row: its diagonal, and the
-// off-diagonals of the transpose (the previous row's super-diagonal, the
-// next row's sub-diagonal); zero outside the row's chain
-__device__ inline void coef_t(int row, const Lay &L, const Bk &s, const DevPrec &p, const DevTab &tb, double &dd,
-                              double &sub, double &sup) {
-    const RowCo c = row_coef(row, L, s, p, tb);
-    dd = c.d;
-    sub = sup = 0.0;
-    Chain cs;
-    if (!chain_of(row, L, cs)) return;
-    if (row > cs.cb) sub = row_coef(row - 1, L, s, p, tb).c;
-    if (row + 1 < cs.cb + cs.cn) sup = row_coef(row + 1, L, s, p, tb).a;
-}
+// stage backgrounds kept per mode: the 2 NPAR perturbed tables' (slot q) and
+// the mode's own (slot 2 NPAR)
+constexpr int NBKS = 2 * NPAR + 1;
+// record fields (free in the reverse kernel) that cache the current stage's
+// chain coefficients of each row: y'_row = a y_{row-1} + d y_row + c y_{row+1} + ...
+constexpr int F_A = F_M, F_D = F_MN, F_C = F_U;
 
 // how a row enters the couplings: h' = w_H . y, eta' = w_E . y, Pi = w_P . y
 // (App. B.3, eqs. hprime and etaprime; Pi = 2 sigma_gamma + G_0 + G_2)
@@ -84,17 +78,23 @@ __device__ inline void w_row(int row, const Lay &L, const Bk &s, const DevPrec &
     }
 }
 
-// doubles of LDS per mode of the reverse kernel: a forward slab, the adjoint
-// fields of every row and one vector of N rows (the forcing at an output)
+// doubles of LDS per mode of the reverse kernel: the records of the forward
+// kernel's slab and its exchange area, the adjoint fields of every row, one
+// vector of NP rows (the forcing at an output), the stage backgrounds and
+// dL/dK_j of every stage and row (each lane only touches its own rows there).
+// The workgroup's LDS starts with the shared multipliers table.
 __host__ __device__ constexpr int adj_slab_doubles(int NP, int nch) {
-    return slab_doubles(NP, nch) + (NP + 2 * PADR) * NAF + NP;
+    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NP + 2 * PADR) * NAF + NP + NBKS * NBK + NSTG * NP;
+}
+__host__ __device__ constexpr int adj_lds_doubles(int NP, int nch, int spw) {
+    return stat_doubles(NP) + spw * adj_slab_doubles(NP, nch);
 }
 
 template <int R>
 struct AdjRows {
-    double y[R], K[NSTG][R];  // the step's start state and stage derivatives (forward)
-    double yb[R], Kb[NSTG][R];  // dL/dy_n and dL/dK_j being accumulated
-    double Y5b[R];              // dL/dy_{n+1} (seed of the last stage)
+    double y[R];    // the step's start state
+    double yb[R];   // dL/dy_n being accumulated
+    double Y5b[R];  // dL/dy_{n+1} (seed of the last stage)
 };
 
 template <int R>
@@ -116,16 +116,32 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     const int N = L.N;
     const int TR = traj_rec(N);
     Slab m;
-    double *af, *gv;
+    double *af, *gv, *bks, *kbb;
     {
-        double *base = lds + (size_t)grp * adj_slab_doubles(NP, L.nch);
+        double *stat = lds;
+        double *base = lds + stat_doubles(NP) + (size_t)grp * adj_slab_doubles(NP, L.nch);
         m.base = base;
-        m.st = nullptr;  // the multipliers table is not used here
+        m.st = stat;
         m.AX = base + (NP + 2 * PADR) * STR;
-        m.BK = m.AX + ax_doubles(L.nch);
-        af = base + slab_doubles(NP, L.nch);
+        m.BK = nullptr;  // the forward kernel's stage records are not used here
+        af = m.AX + ax_doubles(L.nch);
         gv = af + (NP + 2 * PADR) * NAF;
+        bks = gv + NP;
+        kbb = bks + NBKS * NBK;
         for (int i = gl; i < adj_slab_doubles(NP, L.nch); i += G) base[i] = 0.0;
+        for (int i = gl; i < stat_doubles(NP); i += G) stat[i] = 0.0;
+        wsync();
+        // the rows' time-independent multipliers (every group writes the same values)
+        for (int r = 0; r < R; ++r) {
+            const int row = gl * R + r;
+            double ca, cc, cd, cp;
+            row_static(row, L, ca, cc, cd, cp);
+            double *q = stat + (row + PADR) * SST;
+            q[S_CA] = ca;
+            q[S_CC] = cc;
+            q[S_CD] = cd;
+            q[S_CP] = cp;
+        }
         wsync();
     }
     if (lin >= n_sys) return;
@@ -133,6 +149,8 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     const DevTab &tb = tabs[c];
     const double k = tb.k[ik];
     auto afr = [&](int row) { return af + (row + PADR) * NAF; };
+    // dL/dK_j of this lane's row r
+    auto kbr = [&](int j, int r) __attribute__((always_inline)) -> double & { return kbb[j * NP + gl * R + r]; };
     auto group_sum = [&](double v) __attribute__((always_inline)) {
         v += dpp_f64<0xB1>(v);
         v += dpp_f64<0x4E>(v);
@@ -150,56 +168,116 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     auto pt = [&](int q) -> const DevTab & { return ptabs[(size_t)q * n_cosmo + c]; };
     double acc[NPAR] = {0.0, 0.0, 0.0, 0.0};  // this lane's share of dL/dtheta_p
 
+    // this lane's rows: generic chain rows (fifth of their chain onward, whose
+    // entries are multipliers of kH and trunc, and -T on the photon chains)
+    // and the rest (the chains' top rows and the isolated rows)
+    unsigned gen = 0, pho = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = gl * R + r;
+        Chain cs;
+        if (row < N && chain_of(row, L, cs)) {
+            if (row - cs.cb >= 4) gen |= 1u << r;
+            if (cs.ty <= 1) pho |= 1u << r;
+        }
+    }
+    // entries of row `row` of A at background s (as row_coef): the multipliers
+    // table for generic rows, the top-row formulas otherwise
+    auto coef_at = [&](int row, const Bk &s, bool generic, bool photon) __attribute__((always_inline)) {
+        RowCo r{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (row >= N) return r;
+        if (generic) {
+            const double *q = m.sta(row);
+            r.a = q[S_CA] * s.kH;
+            r.c = q[S_CC] * s.kH;
+            r.d = photon ? fma(q[S_CD], s.trunc, -s.T) : q[S_CD] * s.trunc;
+            return r;
+        }
+        Chain cs;
+        if (chain_of(row, L, cs)) return top_coef<false>(cs.ty, row - cs.cb, L, s, p, 0.0, 0.0);
+        if (row == L.rDC) r.uH = -0.5;
+        if (row == L.rETA) r.uE = 1.0;
+        if (row == L.rDG) r.uH = -2.0 / 3.0;
+        return r;
+    };
+
     AdjRows<R> w;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = gl * R + r;
         const bool in = row < N && !first;
         w.Y5b[r] = in ? lm[row] : 0.0;
-        w.Kb[NSTG - 1][r] = in ? lm[N + row] : 0.0;
+        kbr(NSTG - 1, r) = in ? lm[N + row] : 0.0;
     }
     const double *lo = tb.lna_src;
     const bool final_seg = seg == 0;
     int nst = hist_n[mode] - seg * every;  // this mode's steps in the segment
     nst = nst < 0 ? 0 : (nst > every ? every : nst);
 
-    // Ybar -> A^T Ybar for this lane's rows, the vector in AF_B of every row
+    // the backgrounds at ln a = tt of the perturbed tables (slots 0 .. 2 NPAR-1)
+    // and of the mode's own (slot 2 NPAR), one per lane
+    auto stage_bks = [&](double tt) __attribute__((always_inline)) {
+        for (int q = gl; q < NBKS; q += G) {
+            Bk b;
+            bk_at<false>(q < 2 * NPAR ? pt(q) : tb, p, k, tt, b);
+            __builtin_memcpy(bks + q * NBK, &b, sizeof(Bk));
+        }
+        wsync();
+    };
+    auto bk_ref = [&](int q) __attribute__((always_inline)) -> const Bk & {
+        return *reinterpret_cast<const Bk *>(bks + q * NBK);
+    };
+
+    // A^T b for this lane's rows, b in AF_B of every row.  Each lane first
+    // caches its rows' entries of A at this stage (chain a, d, c in the
+    // records, the couplings' u in the adjoint fields; the transposed solve
+    // reads them too) and its share of u . b.
     auto apply_t = [&](const Bk &s, double *out) __attribute__((always_inline)) {
         double zH = 0.0, zE = 0.0, zP = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
-            if (row < N) {
-                const RowCo cc = row_coef(row, L, s, p, tb);
-                const double v = afr(row)[AF_B];
-                zH = fma(cc.uH, v, zH);
-                zE = fma(cc.uE, v, zE);
-                zP = fma(cc.uP, v, zP);
-            }
+            const RowCo cc = coef_at(row, s, (gen >> r) & 1u, (pho >> r) & 1u);
+            double *q = m.rec(row);
+            q[F_A] = cc.a;
+            q[F_D] = cc.d;
+            q[F_C] = cc.c;
+            double *f = afr(row);
+            f[AF_UH] = cc.uH;
+            f[AF_UE] = cc.uE;
+            f[AF_UP] = cc.uP;
+            const double v = f[AF_B];
+            zH = fma(cc.uH, v, zH);
+            zE = fma(cc.uE, v, zE);
+            zP = fma(cc.uP, v, zP);
         }
         zH = group_sum(zH);
         zE = group_sum(zE);
         zP = group_sum(zP);
+        wsync();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
             double v = 0.0;
             if (row < N) {
-                double dd, sub, sup, wH, wE, wP;
-                coef_t(row, L, s, p, tb, dd, sub, sup);
-                w_row(row, L, s, p, wH, wE, wP);
-                v = dd * afr(row)[AF_B];
-                if (sub != 0.0) v = fma(sub, afr(row - 1)[AF_B], v);
-                if (sup != 0.0) v = fma(sup, afr(row + 1)[AF_B], v);
+                Chain cs;
+                const bool inch = chain_of(row, L, cs);
+                v = m.rec(row)[F_D] * afr(row)[AF_B];
+                // (A^T)_{row,row-1} = A_{row-1,row} (c of the row above), (A^T)_{row,row+1} = a of the row below
+                if (inch && row > cs.cb) v = fma(m.rec(row - 1)[F_C], afr(row - 1)[AF_B], v);
+                if (inch && row + 1 < cs.cb + cs.cn) v = fma(m.rec(row + 1)[F_A], afr(row + 1)[AF_B], v);
                 if (row == 2) v = fma(-(4.0 / 3.0) * s.invHc, afr(L.rDG)[AF_B], v);  // delta_g' = -(4/3) theta_g / Hc ...
                 if (row == L.rDG) v = fma(0.25 * s.k2H, afr(2)[AF_B], v);          // theta_g' = ... + k^2 delta_g / (4 Hc)
+                double wH, wE, wP;
+                w_row(row, L, s, p, wH, wE, wP);
                 v = fma(wH, zH, fma(wE, zE, fma(wP, zP, v)));
             }
             out[r] = v;
         }
     };
 
-    // x = (I - g A)^-T b: b in AF_B of every row, x into AF_X of every row
+    // x = (I - g A)^-T b: b in AF_B of every row, x into AF_X of every row; the
+    // entries of A as apply_t cached them at this stage
     auto solve_t = [&](const Bk &s, double g) __attribute__((always_inline)) {
         // (1) chains, one lane each: upward elimination x_j = U_j + V_j x_{j-1};
         // the top four rows' U as affine maps of zeta (constant, H, E, P parts)
@@ -210,12 +288,14 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             double tU[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}, tV[4] = {0, 0, 0, 0};
             for (int j = ch.cn - 1; j >= 0; --j) {
                 const int row = ch.cb + j;
-                double dd, sub, sup, wH, wE, wP;
-                coef_t(row, L, s, p, tb, dd, sub, sup);
+                const double dd = m.rec(row)[F_D];
+                const double sub = j > 0 ? m.rec(row - 1)[F_C] : 0.0;
+                const double sup = j + 1 < ch.cn ? m.rec(row + 1)[F_A] : 0.0;
                 double piv = 1.0 - g * dd;
                 double rhs = afr(row)[AF_B];
                 double xH = 0.0, xE = 0.0, xP = 0.0;  // coupling columns (top rows)
                 if (j < 4) {
+                    double wH, wE, wP;
                     w_row(row, L, s, p, wH, wE, wP);
                     xH = g * wH;
                     xE = g * wE;
@@ -283,8 +363,8 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         if (gl == 0) {
             double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, d[3] = {0, 0, 0};
             auto add = [&](int row, double x0, double xh, double xe, double xp) {
-                const RowCo cc = row_coef(row, L, s, p, tb);
-                const double u[3] = {cc.uH, cc.uE, cc.uP};
+                const double *f = afr(row);
+                const double u[3] = {f[AF_UH], f[AF_UE], f[AF_UP]};
                 for (int i = 0; i < 3; ++i) {
                     d[i] = fma(u[i], x0, d[i]);
                     C[i][0] = fma(u[i], xh, C[i][0]);
@@ -355,32 +435,57 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         wsync();
     };
 
-    // mu . (A(theta+) - A(theta-)) v / den for every parameter into acc: v in
-    // the RY records of every row, mu for this lane's rows
-    auto theta_rhs = [&](double tt, const double *mu) __attribute__((always_inline)) {
-        for (int q = 0; q < 2 * NPAR; ++q) {
-            Bk sp;
-            bk_at<false>(pt(q), p, k, tt, sp);
-            if (gl == 0) {
-                double H, E, P;
-                aux_from_rows(m, L, sp, p, pt(q), k, H, E, P);
-                m.AX[0] = H;
-                m.AX[1] = E;
-                m.AX[2] = P;
-            }
-            wsync();
-            double f[R];
-            rhs_rows<R>(m, L, sp, p, pt(q), gl, f);
-            double d = 0.0;
+    // sum over the perturbed tables q of mu . (A(theta_q) v), differenced into
+    // acc: v in the RY records of every row, mu for this lane's rows, the
+    // tables' backgrounds in the stage slots.  A generic row's entries are
+    // the multipliers times kH, trunc and T, so its part is
+    // kH_q g1 + trunc_q g2 - T_q g3 with sums g formed once; the other rows
+    // take their entries at each background, and the couplings (h', eta',
+    // Pi) of v at each background (App. B.3, eqs. hprime and etaprime).
+    auto theta_stage = [&](const double *mu) __attribute__((always_inline)) {
+        double g1 = 0.0, g2 = 0.0, g3 = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (gl * R + r < N) d = fma(mu[r], f[r], d);
-            const double dq = (q & 1 ? -d : d) / den[q >> 1];
-#pragma unroll
-            for (int i = 0; i < NPAR; ++i)
-                if ((q >> 1) == i) acc[i] += dq;
-            wsync();
+        for (int r = 0; r < R; ++r) {
+            if (!((gen >> r) & 1u)) continue;
+            const int row = gl * R + r;
+            const double *q = m.sta(row);
+            const double yr = m.ry(row);
+            g1 = fma(mu[r], fma(q[S_CA], m.ry(row - 1), q[S_CC] * m.ry(row + 1)), g1);
+            g2 = fma(mu[r] * q[S_CD], yr, g2);
+            if ((pho >> r) & 1u) g3 = fma(mu[r], yr, g3);
         }
+        const double Yeta = m.ry(L.rETA), Ydc = m.ry(L.rDC), Y0 = m.ry(0), Ydg = m.ry(L.rDG), YbV = m.ry(L.bV);
+        const double Y1 = m.ry(1), Y2 = m.ry(2), YbV1 = m.ry(L.bV + 1);
+        const double Pv = p.lp > 0 ? 2.0 * m.ry(3) + m.ry(L.bG) + m.ry(L.bG + 2) : 0.0;
+        double dq[2 * NPAR];
+        for (int qi = 0; qi < 2 * NPAR; ++qi) {
+            const Bk &sq = bk_ref(qi);
+            double d = fma(sq.kH, g1, fma(sq.trunc, g2, -sq.T * g3));
+            const double H = fma(sq.cH1, Yeta, sq.cH2 * fma(sq.rc, Ydc, fma(sq.rb, Y0, fma(sq.rg, Ydg, sq.rur * YbV))));
+            const double E = sq.cE * fma(sq.rb, Y1, fma((4.0 / 3.0) * sq.rg, Y2, (4.0 / 3.0) * sq.rur * YbV1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = gl * R + r;
+                if (((gen >> r) & 1u) || row >= N) continue;
+                const RowCo cc = coef_at(row, sq, false, false);
+                Chain cs;
+                double v = 0.0;
+                if (chain_of(row, L, cs)) {
+                    const double ym = row > cs.cb ? m.ry(row - 1) : 0.0;
+                    const double yp = row + 1 < cs.cb + cs.cn ? m.ry(row + 1) : 0.0;
+                    v = fma(cc.c, yp, fma(cc.d, m.ry(row), cc.a * ym));
+                    if (row == 2) v = fma(0.25 * sq.k2H, Ydg, v);
+                } else if (row == L.rDG) {
+                    v = (-(4.0 / 3.0) * sq.invHc) * Y2;
+                }
+                v = fma(cc.uP, Pv, fma(cc.uE, E, fma(cc.uH, H, v)));
+                d = fma(mu[r], v, d);
+            }
+            dq[qi] = d;
+        }
+#pragma unroll
+        for (int i = 0; i < NPAR; ++i) acc[i] += (dq[2 * i] - dq[2 * i + 1]) / den[i];
+        wsync();
     };
 
     for (int n = nst - 1; n >= 0; --n) {
@@ -388,16 +493,19 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         const double t = qrec[0], h = qrec[1], tn = qrec[2], hh = tn - t;
         const double g = h * GAMMA;
         const bool start = final_seg && n == 0;  // the integration's first step
+        // the step's stage derivatives of this lane's rows (from the trajectory)
+        double Kr[NSTG][R];
+#pragma unroll
+        for (int j = 0; j < NSTG; ++j)
+#pragma unroll
+            for (int r = 0; r < R; ++r) Kr[j][r] = gl * R + r < N ? qrec[3 + (1 + j) * N + gl * R + r] : 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
-            const bool in = row < N;
-            w.y[r] = in ? qrec[3 + row] : 0.0;
-#pragma unroll
-            for (int j = 0; j < NSTG; ++j) w.K[j][r] = in ? qrec[3 + (1 + j) * N + row] : 0.0;
+            w.y[r] = row < N ? qrec[3 + row] : 0.0;
             w.yb[r] = 0.0;
 #pragma unroll
-            for (int j = 0; j < NSTG - 1; ++j) w.Kb[j][r] = 0.0;
+            for (int j = 0; j < NSTG - 1; ++j) kbr(j, r) = 0.0;
         }
         // the output times of this step: (t_n, t_{n+1}], the first step also t_0
         int o0 = 0, o1 = n_tau;
@@ -430,9 +538,9 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             for (int r = 0; r < R; ++r) {
                 double y5 = w.y[r];
 #pragma unroll
-                for (int j = 0; j < NSTG - 1; ++j) y5 = fma(h * Ka[NSTG - 1][j], w.K[j][r], y5);
-                y5 = fma(g, w.K[NSTG - 1][r], y5);
-                m.ry(gl * R + r) = h00 * w.y[r] + h10 * hh * w.K[0][r] + h01 * y5 + h11 * hh * w.K[NSTG - 1][r];
+                for (int j = 0; j < NSTG - 1; ++j) y5 = fma(h * Ka[NSTG - 1][j], Kr[j][r], y5);
+                y5 = fma(g, Kr[NSTG - 1][r], y5);
+                m.ry(gl * R + r) = h00 * w.y[r] + h10 * hh * Kr[0][r] + h01 * y5 + h11 * hh * Kr[NSTG - 1][r];
             }
             wsync();
             if (gl == 0) sources_adj_point<false>(tb, p, L, n_tau, ik, o, gS + mode * 3 * n_tau, gv);
@@ -441,9 +549,9 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             for (int r = 0; r < R; ++r) {
                 const double G_ = gv[gl * R + r];
                 w.yb[r] = fma(h00, G_, w.yb[r]);
-                w.Kb[0][r] = fma(h10 * hh, G_, w.Kb[0][r]);
+                kbr(0, r) = fma(h10 * hh, G_, kbr(0, r));
                 w.Y5b[r] = fma(h01, G_, w.Y5b[r]);
-                w.Kb[NSTG - 1][r] = fma(h11 * hh, G_, w.Kb[NSTG - 1][r]);
+                kbr(NSTG - 1, r) = fma(h11 * hh, G_, kbr(NSTG - 1, r));
             }
             // the sources' own dependence on the parameters at this state: one
             // perturbed table per lane
@@ -464,95 +572,84 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         // stages, last to first
         for (int si = NSTG - 1; si >= 1; --si) {
             const double ts = (Kc[si] == 1.0) ? tn : t + Kc[si] * h;
-            Bk s;
-            bk_at<false>(tb, p, k, ts, s);
-            double Yb[R], Ys[R];
+            stage_bks(ts);
+            const Bk &s = bk_ref(2 * NPAR);
+            double Ys[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double rr = w.y[r];
+                double ks = Kr[0][r];
 #pragma unroll
                 for (int j = 0; j < NSTG - 1; ++j)
-                    if (j < si) rr = fma(h * Ka[si][j], w.K[j][r], rr);
-                double ks = w.K[0][r];
+                    if (j < si) rr = fma(h * Ka[si][j], Kr[j][r], rr);
 #pragma unroll
                 for (int j = 1; j < NSTG; ++j)
-                    if (si == j) ks = w.K[j][r];
+                    if (si == j) ks = Kr[j][r];
                 Ys[r] = fma(g, ks, rr);
-                double kb = w.Kb[0][r];
-#pragma unroll
-                for (int j = 1; j < NSTG; ++j)
-                    if (si == j) kb = w.Kb[j][r];
-                afr(gl * R + r)[AF_B] = kb;
+                afr(gl * R + r)[AF_B] = kbr(si, r);
             }
             wsync();
             double at[R];
-            apply_t(s, at);  // A_s^T Kbar_s
+            apply_t(s, at);  // A_s^T Kbar_s (and this stage's entries cached)
             wsync();
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                Yb[r] = at[r] + (si == NSTG - 1 ? w.Y5b[r] : 0.0);
-                afr(gl * R + r)[AF_B] = Yb[r];
-            }
+            for (int r = 0; r < R; ++r)
+                afr(gl * R + r)[AF_B] = at[r] + (si == NSTG - 1 ? w.Y5b[r] : 0.0);
             wsync();
             solve_t(s, g);  // Rbar_s into AF_X
             double mu[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double rb = gl * R + r < N ? afr(gl * R + r)[AF_X] : 0.0;
-                double kb = w.Kb[0][r];
-#pragma unroll
-                for (int j = 1; j < NSTG; ++j)
-                    if (si == j) kb = w.Kb[j][r];
-                mu[r] = fma(g, rb, kb);
+                mu[r] = fma(g, rb, kbr(si, r));
                 w.yb[r] += rb;
 #pragma unroll
                 for (int j = 0; j < NSTG - 1; ++j)
-                    if (j < si) w.Kb[j][r] = fma(h * Ka[si][j], rb, w.Kb[j][r]);
+                    if (j < si) kbr(j, r) = fma(h * Ka[si][j], rb, kbr(j, r));
                 m.ry(gl * R + r) = Ys[r];
             }
             wsync();
-            theta_rhs(ts, mu);  // the stage matrix's dependence on the parameters
+            theta_stage(mu);  // the stage matrix's dependence on the parameters
         }
         if (start) {
             // K_0 = A(t_0) y_0 at the start, and y_0 from the initial conditions
-            Bk s;
-            bk_at<false>(tb, p, k, t, s);
+            stage_bks(t);
+            const Bk &s = bk_ref(2 * NPAR);
             double at[R], mu[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                afr(gl * R + r)[AF_B] = w.Kb[0][r];
+                afr(gl * R + r)[AF_B] = kbr(0, r);
                 m.ry(gl * R + r) = w.y[r];
-                mu[r] = w.Kb[0][r];
+                mu[r] = kbr(0, r);
             }
             wsync();
             apply_t(s, at);
             wsync();
-            theta_rhs(t, mu);
+            theta_stage(mu);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 w.yb[r] += at[r];
-                w.Kb[0][r] = 0.0;
+                kbr(0, r) = 0.0;
             }
+            double dq[2 * NPAR];
             for (int q = 0; q < 2 * NPAR; ++q) {
-                Bk sp;
-                bk_at<false>(pt(q), p, k, t, sp);
+                const Bk &sp = bk_ref(q);
                 double d = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int row = gl * R + r;
                     if (row < N) d = fma(w.yb[r], ic_row<false>(row, L, sp, pt(q), k), d);
                 }
-                const double dq = (q & 1 ? -d : d) / den[q >> 1];
-#pragma unroll
-                for (int i = 0; i < NPAR; ++i)
-                    if ((q >> 1) == i) acc[i] += dq;
+                dq[q] = d;
             }
+#pragma unroll
+            for (int i = 0; i < NPAR; ++i) acc[i] += (dq[2 * i] - dq[2 * i + 1]) / den[i];
         }
         // to the previous step: dL/dy_n seeds its last stage, dL/dK_0 its K_5
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             w.Y5b[r] = w.yb[r];
-            w.Kb[NSTG - 1][r] = w.Kb[0][r];
+            kbr(NSTG - 1, r) = kbr(0, r);
         }
     }
     // carry to the previous segment (or, after the first, dL/dy_0)
@@ -561,7 +658,7 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         const int row = gl * R + r;
         if (row < N) {
             lm[row] = w.Y5b[r];
-            lm[N + row] = w.Kb[NSTG - 1][r];
+            lm[N + row] = kbr(NSTG - 1, r);
         }
     }
 #pragma unroll
@@ -570,7 +667,6 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         if (gl == 0) gr[q] = (first ? 0.0 : gr[q]) + v;
     }
 }
-
 
 // The gradient of L = sum dL/dC_l C_l per cosmology, assembled from its
 // parts (one workgroup per cosmology): the reverse sweep's per-mode sums for
@@ -649,7 +745,7 @@ bool adjoint_supported(const DevPrec &p) {
     group_shape(p, R, G);
     const Lay L = make_lay(p);
     if (G > 64 || (R != 2 && R != 5)) return false;
-    return (size_t)(64 / G) * adj_slab_doubles(G * R, L.nch) * sizeof(double) <= 65536;
+    return (size_t)adj_lds_doubles(G * R, L.nch, 64 / G) * sizeof(double) <= 65536;
 }
 
 int launch_adjoint_segment(const DevTab *d_tabs, const DevTab *d_ptabs, const double *d_pden, int n_cosmo, int n_k,
@@ -667,7 +763,7 @@ int launch_adjoint_segment(const DevTab *d_tabs, const DevTab *d_ptabs, const do
     int R, G;
     group_shape(p, R, G);
     const Lay L = make_lay(p);
-    const size_t lds = (size_t)(64 / G) * adj_slab_doubles(G * R, L.nch) * sizeof(double);
+    const size_t lds = (size_t)adj_lds_doubles(G * R, L.nch, 64 / G) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     if (R == 2)
         return launch_adj_r<2>(d_tabs, d_ptabs, d_pden, n_cosmo, n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg,
