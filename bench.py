@@ -236,6 +236,40 @@ def config2_sweep(ctx, batches):
                         "2000 output times, l <= 2500", "rows": rows}
 
 
+def gradient_only(args, W, L, dev):
+    """The differentiation workload alone: cmb_gradient over a batch of
+    config-1 cosmologies with seeded dL/dC_l, timed per call (host table
+    builds of the perturbed cosmologies included)."""
+    import torch
+    wl = W.config1()
+    B = args.batch
+    cosmos = W.perturbed_cosmologies(B, seed=20260215)
+    for c in cosmos:
+        c["N_nu_massless"] = 3.0
+    tabs = [L.Tables(c, wl.prec, wl.k, wl.n_tau) for c in cosmos]
+    ctx = L.Context(0)
+    lmax, n_k = wl.ell_max, len(wl.k)
+    gen = torch.Generator(device="cpu").manual_seed(61)
+    gC = torch.randn((B, 3, lmax + 1), generator=gen, dtype=torch.float64).to(dev)
+    Gc = torch.empty((B, 3, lmax + 1), dtype=torch.float64, device=dev)
+    Gg = torch.empty((B, 6), dtype=torch.float64, device=dev)
+    Gs = torch.empty((B, n_k), dtype=torch.int32, device=dev)
+    times = []
+    for i in range(args.gradient_only):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.gradient(tabs, lmax, gC, Gc, Gg, Gs, rel=1e-4)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] gradient {i + 1}/{args.gradient_only}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "dL/dtheta of C_ell (6 parameters) per second, batched", "value": B / min(times),
+                      "unit": "gradients/s", "s_per_batch": min(times), "batch": B, "calls": len(times),
+                      "modes_not_ok": int((Gs != 0).sum().item()), "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "config-1 physics, batch of seeded cosmologies, seeded dL/dC_l, "
+                                             "checkpoints every 64 steps"}}))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +287,9 @@ def main():
                     help="also time config 2 (massive neutrino) at these comma-separated batch sizes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--gradient-only", type=int, default=0, metavar="REPS",
+                    help="only time the differentiation workload (config-1 physics, --batch cosmologies, "
+                         "cmb_gradient) REPS times, print one JSON line and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by cosmology "
@@ -273,6 +310,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}))
+        return
+    if args.gradient_only:
+        gradient_only(args, W, L, dev)
         return
     wl = W.config1()
     B = args.batch
