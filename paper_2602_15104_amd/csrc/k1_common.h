@@ -316,10 +316,16 @@ __host__ __device__ constexpr int ax_doubles(int nch) { return (4 + 16 * nch + 1
 // one stage's background record (a Bk, padded to an even count)
 constexpr int NBK = 24;
 static_assert(NBK * sizeof(double) >= sizeof(Bk), "a stage record holds a Bk");
-// doubles of LDS per mode for NP rows: records, exchange area, and the
-// backgrounds of the implicit stages
+// doubles of LDS per mode for NP rows: records, exchange area, the
+// backgrounds of the implicit stages, and two spare doubles.  The spare
+// doubles skew consecutive slabs of a wavefront across the LDS banks: with
+// eight slabs per wavefront an unpadded 556-double slab put the same record
+// of several slabs in one bank group (0.97 conflict cycles per conflict-free
+// LDS cycle at C1 batch 32), and a pad of 2 (mod 8) doubles took the batch's
+// perturbation kernel from 127.9 to 122.0 ms (a pad of 4 (mod 8) made it
+// slower; the results are the same bits).
 __host__ __device__ constexpr int slab_doubles(int NP, int nch) {
-    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NSTG - 1) * NBK;
+    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NSTG - 1) * NBK + 2;
 }
 // doubles of the shared multipliers table for NP rows
 __host__ __device__ constexpr int stat_doubles(int NP) { return (NP + 2 * PADR) * SST; }
