@@ -48,10 +48,8 @@ namespace {
 // adjoint (dL/dy, dL/dK_0) and the parameter accumulators carry from one
 // segment's launch to the previous one's in global memory.
 
-constexpr int NAF = 7;  // adjoint fields per row
-// right-hand side, solution, elimination U and V, and the row's coupling
-// coefficients u_H, u_E, u_P (how h', eta', Pi enter it) at the current stage
-constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3, AF_UH = 4, AF_UE = 5, AF_UP = 6;
+constexpr int NAF = 4;  // adjoint fields per row: right-hand side, solution, elimination U and V
+constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3;
 constexpr int NPAR = 4;  // parameters with table tangents: h, omega_b, omega_cdm, tau_reio
 // stage backgrounds kept per mode: the 2 NPAR perturbed tables' (slot q) and
 // the mode's own (slot 2 NPAR)
@@ -59,6 +57,27 @@ constexpr int NBKS = 2 * NPAR + 1;
 // record fields (free in the reverse kernel) that cache the current stage's
 // chain coefficients of each row: y'_row = a y_{row-1} + d y_row + c y_{row+1} + ...
 constexpr int F_A = F_M, F_D = F_MN, F_C = F_U;
+
+// The entries of a chain's top rows and of the isolated rows are linear in
+// eight background quantities, the bases 1, 1/Hc, kH, k^2/Hc, T, R T,
+// c_s^2 k^2/Hc and the truncation rate (and u_P is T times a constant).  A
+// table per wavefront holds, for each such row, the multiplier of every
+// basis in its entries a, d, c, and its u_H, u_E and u_P / T; it is filled
+// once from the row formulas themselves, at unit backgrounds.
+constexpr int NBAS = 8;
+constexpr int TBLW = 3 * NBAS + 4;  // a, d, c per basis; u_H, u_E, u_P / T; spare
+__device__ inline void bases_of(const Bk &s, double *v) {
+    v[0] = 1.0;
+    v[1] = s.invHc;
+    v[2] = s.kH;
+    v[3] = s.k2H;
+    v[4] = s.T;
+    v[5] = s.R * s.T;
+    v[6] = s.cs2 * s.k2H;
+    v[7] = s.trunc;
+}
+// rows of the table: four top rows per chain, then delta_c, eta, delta_g
+__host__ __device__ constexpr int top_rows(int nch) { return 4 * nch + 3; }
 
 // how a row enters the couplings: h' = w_H . y, eta' = w_E . y, Pi = w_P . y
 // (App. B.3, eqs. hprime and etaprime; Pi = 2 sigma_gamma + G_0 + G_2)
@@ -87,7 +106,7 @@ __host__ __device__ constexpr int adj_slab_doubles(int NP, int nch) {
     return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NP + 2 * PADR) * NAF + NP + NBKS * NBK + NSTG * NP;
 }
 __host__ __device__ constexpr int adj_lds_doubles(int NP, int nch, int spw) {
-    return stat_doubles(NP) + spw * adj_slab_doubles(NP, nch);
+    return stat_doubles(NP) + top_rows(nch) * TBLW + spw * adj_slab_doubles(NP, nch);
 }
 
 template <int R>
@@ -117,9 +136,10 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     const int TR = traj_rec(N);
     Slab m;
     double *af, *gv, *bks, *kbb;
+    double *const tbl = lds + stat_doubles(NP);  // the top rows' basis multipliers (shared)
     {
         double *stat = lds;
-        double *base = lds + stat_doubles(NP) + (size_t)grp * adj_slab_doubles(NP, L.nch);
+        double *base = lds + stat_doubles(NP) + top_rows(L.nch) * TBLW + (size_t)grp * adj_slab_doubles(NP, L.nch);
         m.base = base;
         m.st = stat;
         m.AX = base + (NP + 2 * PADR) * STR;
@@ -200,6 +220,69 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         if (row == L.rDG) r.uH = -2.0 / 3.0;
         return r;
     };
+    // the table row of a chain's top row or an isolated row (-1 otherwise)
+    auto top_index = [&](int row) __attribute__((always_inline)) -> int {
+        if (row >= N) return -1;
+        if (row == L.rDC) return 4 * L.nch;
+        if (row == L.rETA) return 4 * L.nch + 1;
+        if (row == L.rDG) return 4 * L.nch + 2;
+        for (int ch = 0; ch < L.nch; ++ch) {
+            const Chain cs = chain_by_index(ch, L);
+            if (row >= cs.cb && row < cs.cb + 4 && row < cs.cb + cs.cn) return 4 * ch + (row - cs.cb);
+        }
+        return -1;
+    };
+    // fill the table (every group writes the same values)
+    for (int idx = gl; idx < top_rows(L.nch); idx += G) {
+        int row = -1;
+        if (idx >= 4 * L.nch) {
+            row = idx == 4 * L.nch ? L.rDC : (idx == 4 * L.nch + 1 ? L.rETA : L.rDG);
+        } else {
+            const Chain cs = chain_by_index(idx / 4, L);
+            if (idx % 4 < cs.cn) row = cs.cb + idx % 4;
+        }
+        double *e = tbl + idx * TBLW;
+        for (int i = 0; i < TBLW; ++i) e[i] = 0.0;
+        if (row < 0) continue;
+        const Bk z{};
+        const RowCo c0 = coef_at(row, z, false, false);
+        auto put = [&](int b, const RowCo &hi, const RowCo &lo_) {
+            e[b] = hi.a - lo_.a;
+            e[NBAS + b] = hi.d - lo_.d;
+            e[2 * NBAS + b] = hi.c - lo_.c;
+        };
+        put(0, c0, RowCo{0.0, 0.0, 0.0, 0.0, 0.0, 0.0});
+        e[3 * NBAS] = c0.uH;
+        e[3 * NBAS + 1] = c0.uE;
+        Bk sb = z;
+        sb.invHc = 1.0;
+        put(1, coef_at(row, sb, false, false), c0);
+        sb = z;
+        sb.kH = 1.0;
+        put(2, coef_at(row, sb, false, false), c0);
+        sb = z;
+        sb.k2H = 1.0;
+        const RowCo ck = coef_at(row, sb, false, false);
+        put(3, ck, c0);
+        sb = z;
+        sb.T = 1.0;
+        const RowCo cT = coef_at(row, sb, false, false);
+        put(4, cT, c0);
+        e[3 * NBAS + 2] = cT.uP - c0.uP;
+        sb.R = 1.0;
+        put(5, coef_at(row, sb, false, false), cT);
+        sb = z;
+        sb.k2H = 1.0;
+        sb.cs2 = 1.0;
+        put(6, coef_at(row, sb, false, false), ck);
+        sb = z;
+        sb.trunc = 1.0;
+        put(7, coef_at(row, sb, false, false), c0);
+    }
+    wsync();
+    int cidx[R];  // this lane's rows' table rows (-1 for generic rows)
+#pragma unroll
+    for (int r = 0; r < R; ++r) cidx[r] = ((gen >> r) & 1u) ? -1 : top_index(gl * R + r);
 
     AdjRows<R> w;
 #pragma unroll
@@ -242,11 +325,7 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             q[F_A] = cc.a;
             q[F_D] = cc.d;
             q[F_C] = cc.c;
-            double *f = afr(row);
-            f[AF_UH] = cc.uH;
-            f[AF_UE] = cc.uE;
-            f[AF_UP] = cc.uP;
-            const double v = f[AF_B];
+            const double v = afr(row)[AF_B];
             zH = fma(cc.uH, v, zH);
             zE = fma(cc.uE, v, zE);
             zP = fma(cc.uP, v, zP);
@@ -362,9 +441,9 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         // (2) one lane: the coupling unknowns zeta = (u_H.x, u_E.x, u_P.x)
         if (gl == 0) {
             double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, d[3] = {0, 0, 0};
-            auto add = [&](int row, double x0, double xh, double xe, double xp) {
-                const double *f = afr(row);
-                const double u[3] = {f[AF_UH], f[AF_UE], f[AF_UP]};
+            auto add = [&](int idx, double x0, double xh, double xe, double xp) {
+                const double *f = tbl + idx * TBLW + 3 * NBAS;
+                const double u[3] = {f[0], f[1], f[2] * s.T};
                 for (int i = 0; i < 3; ++i) {
                     d[i] = fma(u[i], x0, d[i]);
                     C[i][0] = fma(u[i], xh, C[i][0]);
@@ -376,19 +455,19 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
                 const Chain cs = chain_by_index(ch, L);
                 for (int j = 0; j < 4 && j < cs.cn; ++j) {
                     const double *q = m.AX + 4 + 16 * ch + 4 * j;
-                    add(cs.cb + j, q[0], q[1], q[2], q[3]);
+                    add(4 * ch + j, q[0], q[1], q[2], q[3]);
                 }
             }
             double wH, wE, wP;
             w_row(L.rDC, L, s, p, wH, wE, wP);
-            add(L.rDC, afr(L.rDC)[AF_B], g * wH, 0.0, 0.0);
+            add(4 * L.nch, afr(L.rDC)[AF_B], g * wH, 0.0, 0.0);
             w_row(L.rETA, L, s, p, wH, wE, wP);
-            add(L.rETA, afr(L.rETA)[AF_B], g * wH, 0.0, 0.0);
+            add(4 * L.nch + 1, afr(L.rETA)[AF_B], g * wH, 0.0, 0.0);
             w_row(L.rDG, L, s, p, wH, wE, wP);
             {
                 const double *q = m.AX + 4 + 4 * 2;  // theta_g, row 2 of the first chain
                 const double lk = g * 0.25 * s.k2H;
-                add(L.rDG, fma(lk, q[0], afr(L.rDG)[AF_B]), fma(lk, q[1], g * wH), lk * q[2], lk * q[3]);
+                add(4 * L.nch + 2, fma(lk, q[0], afr(L.rDG)[AF_B]), fma(lk, q[1], g * wH), lk * q[2], lk * q[3]);
             }
             // (I - C) zeta = d by the adjugate
             const double a00 = 1.0 - C[0][0], a01 = -C[0][1], a02 = -C[0][2];
@@ -437,50 +516,57 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
 
     // sum over the perturbed tables q of mu . (A(theta_q) v), differenced into
     // acc: v in the RY records of every row, mu for this lane's rows, the
-    // tables' backgrounds in the stage slots.  A generic row's entries are
-    // the multipliers times kH, trunc and T, so its part is
-    // kH_q g1 + trunc_q g2 - T_q g3 with sums g formed once; the other rows
-    // take their entries at each background, and the couplings (h', eta',
-    // Pi) of v at each background (App. B.3, eqs. hprime and etaprime).
+    // tables' backgrounds in the stage slots.  Every entry of A is a sum of
+    // background bases times static multipliers (generic rows: kH, trunc and
+    // -T; the other rows from the table), so mu . A v is the bases dotted
+    // with sums G_b formed once per stage, plus the couplings (h', eta', Pi)
+    // of v at each background (App. B.3, eqs. hprime and etaprime).  The
+    // constant basis cancels in the differences and is left out.
     auto theta_stage = [&](const double *mu) __attribute__((always_inline)) {
-        double g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        double Gb[NBAS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double UH = 0.0, UE = 0.0, UPT = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (!((gen >> r) & 1u)) continue;
             const int row = gl * R + r;
-            const double *q = m.sta(row);
+            if (row >= N) continue;
             const double yr = m.ry(row);
-            g1 = fma(mu[r], fma(q[S_CA], m.ry(row - 1), q[S_CC] * m.ry(row + 1)), g1);
-            g2 = fma(mu[r] * q[S_CD], yr, g2);
-            if ((pho >> r) & 1u) g3 = fma(mu[r], yr, g3);
+            if ((gen >> r) & 1u) {
+                const double *q = m.sta(row);
+                Gb[2] = fma(mu[r], fma(q[S_CA], m.ry(row - 1), q[S_CC] * m.ry(row + 1)), Gb[2]);
+                Gb[7] = fma(mu[r] * q[S_CD], yr, Gb[7]);
+                if ((pho >> r) & 1u) Gb[4] = fma(-mu[r], yr, Gb[4]);
+                continue;
+            }
+            if (cidx[r] < 0) continue;
+            const double *e = tbl + cidx[r] * TBLW;
+            Chain cs;
+            const bool inch = chain_of(row, L, cs);
+            const double ym = (inch && row > cs.cb) ? m.ry(row - 1) : 0.0;
+            const double yp = (inch && row + 1 < cs.cb + cs.cn) ? m.ry(row + 1) : 0.0;
+#pragma unroll
+            for (int bb = 1; bb < NBAS; ++bb)
+                Gb[bb] = fma(mu[r], fma(e[bb], ym, fma(e[NBAS + bb], yr, e[2 * NBAS + bb] * yp)), Gb[bb]);
+            UH = fma(mu[r], e[3 * NBAS], UH);
+            UE = fma(mu[r], e[3 * NBAS + 1], UE);
+            UPT = fma(mu[r], e[3 * NBAS + 2], UPT);
+            if (row == 2) Gb[3] = fma(0.25 * mu[r], m.ry(L.rDG), Gb[3]);  // theta_g' ... + k^2 delta_g / (4 Hc)
+            if (row == L.rDG) Gb[1] = fma(-(4.0 / 3.0) * mu[r], m.ry(2), Gb[1]);  // delta_g' = -(4/3) theta_g / Hc ...
         }
         const double Yeta = m.ry(L.rETA), Ydc = m.ry(L.rDC), Y0 = m.ry(0), Ydg = m.ry(L.rDG), YbV = m.ry(L.bV);
         const double Y1 = m.ry(1), Y2 = m.ry(2), YbV1 = m.ry(L.bV + 1);
         const double Pv = p.lp > 0 ? 2.0 * m.ry(3) + m.ry(L.bG) + m.ry(L.bG + 2) : 0.0;
         double dq[2 * NPAR];
+#pragma unroll
         for (int qi = 0; qi < 2 * NPAR; ++qi) {
             const Bk &sq = bk_ref(qi);
-            double d = fma(sq.kH, g1, fma(sq.trunc, g2, -sq.T * g3));
+            double v[NBAS];
+            bases_of(sq, v);
+            double d = 0.0;
+#pragma unroll
+            for (int bb = 1; bb < NBAS; ++bb) d = fma(Gb[bb], v[bb], d);
             const double H = fma(sq.cH1, Yeta, sq.cH2 * fma(sq.rc, Ydc, fma(sq.rb, Y0, fma(sq.rg, Ydg, sq.rur * YbV))));
             const double E = sq.cE * fma(sq.rb, Y1, fma((4.0 / 3.0) * sq.rg, Y2, (4.0 / 3.0) * sq.rur * YbV1));
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int row = gl * R + r;
-                if (((gen >> r) & 1u) || row >= N) continue;
-                const RowCo cc = coef_at(row, sq, false, false);
-                Chain cs;
-                double v = 0.0;
-                if (chain_of(row, L, cs)) {
-                    const double ym = row > cs.cb ? m.ry(row - 1) : 0.0;
-                    const double yp = row + 1 < cs.cb + cs.cn ? m.ry(row + 1) : 0.0;
-                    v = fma(cc.c, yp, fma(cc.d, m.ry(row), cc.a * ym));
-                    if (row == 2) v = fma(0.25 * sq.k2H, Ydg, v);
-                } else if (row == L.rDG) {
-                    v = (-(4.0 / 3.0) * sq.invHc) * Y2;
-                }
-                v = fma(cc.uP, Pv, fma(cc.uE, E, fma(cc.uH, H, v)));
-                d = fma(mu[r], v, d);
-            }
+            d = fma(UH, H, fma(UE, E, fma(UPT * sq.T, Pv, d)));
             dq[qi] = d;
         }
 #pragma unroll
