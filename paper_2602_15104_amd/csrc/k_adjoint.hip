@@ -365,7 +365,55 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             double U1 = 0.0, V1 = 0.0;  // of the row below
             // top rows 0..3: affine U, and V (zero beyond a chain shorter than four rows)
             double tU[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}, tV[4] = {0, 0, 0, 0};
-            for (int j = ch.cn - 1; j >= 0; --j) {
+            // Generic rows cn-1 .. 4 in continuant form, with no division on the
+            // dependent path: M_j = piv_j M_{j+1} - g^2 sup_j sub_{j+1} M_{j+2} (the
+            // forward solve's pivots: sup_j sub_{j+1} = a_{j+1} c_j <= 0, so every
+            // term is non-negative) and Z_j = rhs_j M_{j+1} + g sup_j Z_{j+1}; then
+            // U_j = Z_j / M_j and V_j = g sub_j M_{j+1} / M_j.  Each row keeps
+            // (M_{j+1}, M_j, Z_j) in its fields (B, V, U) for the row lanes to
+            // divide; M and Z are rescaled by 2^-332 whenever M passes 2^332.
+            if (ch.cn > 4) {
+                double M1 = 1.0, M2 = 0.0, Z1 = 0.0;  // M_{j+1}, M_{j+2}, Z_{j+1}
+                int row = ch.cb + ch.cn - 1;
+                double dd = m.rec(row)[F_D], cj = m.rec(row)[F_C], rh = afr(row)[AF_B];
+                double aup = 0.0;  // a_{j+1}: none below the last row
+                for (int j = ch.cn - 1; j >= 4; --j) {
+                    row = ch.cb + j;
+                    // the next row's entries, loaded ahead of this row's arithmetic
+                    const double na = m.rec(row)[F_A];
+                    double nd = 0.0, nc = 0.0, nr = 0.0;
+                    if (j > 4) {
+                        nd = m.rec(row - 1)[F_D];
+                        nc = m.rec(row - 1)[F_C];
+                        nr = afr(row - 1)[AF_B];
+                    }
+                    const double piv = 1.0 - g * dd;
+                    const double gs = g * aup;
+                    const double M = fma(piv, M1, (-gs * g * cj) * M2);
+                    const double Z = fma(rh, M1, gs * Z1);
+                    double *f = afr(row);
+                    f[AF_B] = M1;
+                    f[AF_V] = M;
+                    f[AF_U] = Z;
+                    M2 = M1;
+                    M1 = M;
+                    Z1 = Z;
+                    if (M1 > 0x1p332) {
+                        M1 *= 0x1p-332;
+                        M2 *= 0x1p-332;
+                        Z1 *= 0x1p-332;
+                    }
+                    dd = nd;
+                    cj = nc;
+                    rh = nr;
+                    aup = na;
+                }
+                // row 4's U and V for the top rows (sub_4 = c_3)
+                const double iM = rcp(M1);
+                U1 = Z1 * iM;
+                V1 = g * m.rec(ch.cb + 3)[F_C] * M2 * iM;
+            }
+            for (int j = (ch.cn < 4 ? ch.cn : 4) - 1; j >= 0; --j) {
                 const int row = ch.cb + j;
                 const double dd = m.rec(row)[F_D];
                 const double sub = j > 0 ? m.rec(row - 1)[F_C] : 0.0;
@@ -395,12 +443,7 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
                 const double p2 = fma(-g * sup, V1, piv);
                 const double ip = rcp(p2);
                 const double V = g * sub * ip;
-                if (j >= 4) {
-                    const double U = fma(g * sup, U1, rhs) * ip;
-                    afr(row)[AF_U] = U;
-                    afr(row)[AF_V] = V;
-                    U1 = U;
-                } else {
+                {
                     // affine: the row below contributes only through its
                     // constant part (generic rows) or its affine map (top rows)
                     const double gs = g * sup;
@@ -436,6 +479,20 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
                 q[2] = xe;
                 q[3] = xp;
             }
+        }
+        wsync();
+        // (1b) row lanes: U_j = Z_j / M_j and V_j = g sub_j M_{j+1} / M_j of the
+        // generic rows (independent reciprocals, off the chains' dependent path)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!((gen >> r) & 1u)) continue;
+            const int row = gl * R + r;
+            double *f = afr(row);
+            const double iM = rcp(f[AF_V]);
+            const double U = f[AF_U] * iM;
+            const double V = g * m.rec(row - 1)[F_C] * f[AF_B] * iM;
+            f[AF_U] = U;
+            f[AF_V] = V;
         }
         wsync();
         // (2) one lane: the coupling unknowns zeta = (u_H.x, u_E.x, u_P.x)
