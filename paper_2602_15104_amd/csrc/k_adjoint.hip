@@ -880,14 +880,29 @@ int launch_adj_r(const DevTab *d_tabs, const DevTab *d_ptabs, const double *d_pd
     return CMB_OK;
 }
 
+// The reverse kernel's group shape: 32 lanes of three rows for hierarchies of
+// 65..96 rows (config 1: 79), two modes per wavefront; otherwise the forward
+// kernel's narrow shape.  At config 1, batch 32, the 32-lane groups took a
+// gradient from 2.80 to 2.52 s against 16 lanes of five rows (64 lanes of
+// two: 3.77 s): the row-parallel work per lane shrinks, and the kernel holds
+// one wavefront per SIMD in either shape.
+void adjoint_shape(const DevPrec &p, int &R, int &G) {
+    group_shape(p, R, G);
+    const int N = make_lay(p).N;
+    if (N > 64 && N <= 96) {
+        R = 3;
+        G = 32;
+    }
+}
+
 }  // namespace
 
 bool adjoint_supported(const DevPrec &p) {
     if (p.nq > 0) return false;
     int R, G;
-    group_shape(p, R, G);
+    adjoint_shape(p, R, G);
     const Lay L = make_lay(p);
-    if (G > 64 || (R != 2 && R != 5)) return false;
+    if (G > 64 || (R != 2 && R != 3 && R != 5)) return false;
     return (size_t)adj_lds_doubles(G * R, L.nch, 64 / G) * sizeof(double) <= 65536;
 }
 
@@ -904,10 +919,13 @@ int launch_adjoint_segment(const DevTab *d_tabs, const DevTab *d_ptabs, const do
         return CMB_E_INVALID;
     }
     int R, G;
-    group_shape(p, R, G);
+    adjoint_shape(p, R, G);
     const Lay L = make_lay(p);
     const size_t lds = (size_t)adj_lds_doubles(G * R, L.nch, 64 / G) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
+    if (R == 3)
+        return launch_adj_r<3>(d_tabs, d_ptabs, d_pden, n_cosmo, n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg,
+                               every, d_gS, d_lam, d_grad, first, lds, s);
     if (R == 2)
         return launch_adj_r<2>(d_tabs, d_ptabs, d_pden, n_cosmo, n_k, n_tau, p, G, d_traj, traj_cap, d_hist_n, seg,
                                every, d_gS, d_lam, d_grad, first, lds, s);
