@@ -155,6 +155,46 @@ def test_gradient_start_state_dot_products(ctx):
         assert e <= 1e-6, (ik, e)
 
 
+@pytest.mark.parametrize("case", ["few", "config1"])
+def test_gradient_matches_frozen_step_central_differences(ctx, case):
+    """Against the library's own frozen-step central differences
+    (cmb_jacobian, order 2, rel 1e-4), which replay the very steps the
+    adjoint differentiates: the adjoint's table tangents are the same
+    central differences, so the two agree far below their O(rel^2)
+    truncation, within 1e-6 of sum |dL/dC_l dC_l/dtheta_p| (measured
+    2.5e-7 at worst).  Against the five-point stencil they differ by that
+    truncation (up to 1.1e-5), which is why the oracle comparison's bar is
+    1e-4."""
+    import torch
+    import paper_2602_15104_amd as L
+    if case == "few":
+        wl, cosmos = _case("few")
+    else:
+        wl = W.config1()
+        cosmos = [wl.cosmo]
+    lm = wl.ell_max
+    tabs = [L.Tables(c, wl.prec, wl.k, wl.n_tau) for c in cosmos]
+    n = len(tabs)
+    gC = _seeded_gC(n, lm, 47 if case == "few" else 61)
+    _say("gradient vs central differences:", case)
+    _, g, st, _ = _gradient(ctx, tabs, lm, gC)
+    assert np.all(st == 0)
+    C = torch.empty((n, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    J = torch.empty((n, 6, 3, lm + 1), dtype=torch.float64, device="cuda:0")
+    sj = torch.empty((n, len(wl.k)), dtype=torch.int32, device="cuda:0")
+    ctx.jacobian(tabs, lm, C, J, sj, rel=1e-4, order=2)
+    torch.cuda.synchronize()
+    assert np.all(sj.cpu().numpy() == 0)
+    Jn = J.cpu().numpy()
+    for i in range(n):
+        for p in range(6):
+            ref = float(np.sum(gC[i] * Jn[i, p]))
+            scale = float(np.sum(np.abs(gC[i] * Jn[i, p])))
+            e = abs(g[i, p] - ref) / scale
+            _say("central", case, "cosmology", i, "param", p, "err", e)
+            assert e <= 1e-6, (i, p, e)
+
+
 def test_gradient_config1(ctx):
     """Config 1 (400 modes, 2000 output times, l <= 2500), fiducial cosmology:
     dL/dtheta for seeded dL/dC_l against the stored oracle derivatives
