@@ -290,7 +290,7 @@ __device__ RowCo row_coef(int row, const Lay &L, const Bk &s, const DevPrec &p, 
 // recurrence replace S_j and M_{j+1} in place.
 constexpr int STR = 4;
 constexpr int F_RY = 0, F_M = 1, F_MN = 2, F_U = 3;
-constexpr int F_V = F_MN;  // V_j, written over M_{j+1} once the pivots are formed
+constexpr int F_V = F_MN;  // V_j of the downward recurrence (U_j in F_U)
 // the multipliers table: SST doubles per row (CC and CP adjacent)
 constexpr int SST = 4;
 constexpr int S_CC = 0, S_CP = 1, S_CA = 2, S_CD = 3;

@@ -56,6 +56,10 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int lin = blockIdx.x * spw + grp;
     const Lay L = make_lay(p);
     const int NP = G * R;
+    // pivots of the chain rows formed in the upward sweep (groups of five or
+    // more rows per lane, several modes per wavefront) or by a row-parallel pass
+    // (fewer rows per lane, and the record and replay instances); the same bits
+    constexpr bool PIV = R >= 5 && !HIST;
     Slab m;
     {
         double *stat = lds;
@@ -342,13 +346,13 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         wsync();
         for (int si = 1; si < NSTG; ++si) {
             __builtin_memcpy(&s, m.BK + (si - 1) * NBK, sizeof(Bk));
-            // stage weights h a_sj for j < s (zero otherwise): fixed-length sums keep
-            // every register index static
+            const double gkH = g * s.kH, gT_ph = g * s.T, gtr = g * s.trunc;
+            // (A) stage right-hand sides y_n + sum_{j<s} h a_sj K_j, row-parallel;
+            // the weights h a_sj for j >= s are zero: fixed-length sums keep every
+            // register index static
             double hA[NSTG - 1];
 #pragma unroll
             for (int j = 0; j < NSTG - 1; ++j) hA[j] = (j < si) ? h * Ka[si][j] : 0.0;
-            const double gkH = g * s.kH, gT_ph = g * s.T, gtr = g * s.trunc;
-            // (A) stage right-hand sides, row-parallel
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double acc = w.y[r];
@@ -358,8 +362,14 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 m.ry(gl * R + r) = acc;
             }
             wsync();
-            // (B) upward elimination of each chain, one lane per chain
+            // (B) upward elimination of each chain, one lane per chain.  The top
+            // rows' affine maps are set on every lane first: a value that only
+            // the sweeping lanes define must not stay undefined in the other
+            // lanes while they run the sections in between (the downward pass
+            // reads these maps from registers)
             Aff top[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) top[j] = Aff{0.0, 0.0, 0.0, 0.0};
             double vq = 0.0;  // streaming rate of this lane's massive node
             if (sweeper) {
                 const double gT = photon_chain ? gT_ph : 0.0;
@@ -370,21 +380,38 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                 // T_j = r_j N_{j+1} - c_j T_{j+1}, the eliminated pivot and rhs
                 // are N_j / N_{j+1} and T_j / N_{j+1}.  Kept as M_j = N_j u^(j-cn),
                 // S_j = T_j u^(j+1-cn) with u = g v (v the chain's streaming rate),
-                // both recurrences take two operations a row (S_j / u is stored):
+                // both recurrences take two operations a row:
                 //   M_j = (b_j / u) M_{j+1} + CP_j M_{j+2},  S_j = r_j M_{j+1} + CC_j S_{j+1}.
                 // Every M_j >= M_{j+1} > 0 (b_j >= 1, CP_j >= 0): no cancellation, no
                 // division on the dependent path; M, S are rescaled by 2^-332 per
-                // block whenever M passes 2^332.  Blocks of four rows always run
-                // whole: rows above the fifth only receive values nobody reads.
+                // block whenever M passes 2^332.  The downward recurrence
+                // y_j = U_j - V_j y_{j-1} takes U_j = T_j / N_j = S_j / (u M_j) and
+                // V_j = a_j N_{j+1} / N_j = -CA_j M_{j+1} / M_j.  With several modes
+                // per wavefront (PIV) both are formed here, beside the recurrences
+                // (the reciprocal is off their dependent path), and only they are
+                // stored: LDS stores cost a whole wavefront's store bandwidth however
+                // few lanes are active, and with four wavefronts per CU they are what
+                // this serial section waits on.  With a mode per wavefront or two,
+                // the sweep stores M_j, M_{j+1} and S_j / u and the row lanes form
+                // U_j, V_j in a pass of their own (D0), with the same operations, so
+                // both give the same bits.  Blocks of four rows always run whole: rows
+                // above the fifth only receive values nobody reads.
                 if (cn >= 5) {
                     const double bq = (1.0 + gT) * iu;
                     double *rl = m.rec(cb + cn - 1);
-                    double M1 = fma(-gtr, m.sta(cb + cn - 1)[S_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
-                    rl[F_M] = M1;
-                    rl[F_MN] = M2;
-                    rl[F_U] = S1 * iu;
-                    // prefetched (RY, CC) and CP of the next block, rows j0 .. j0-3
-                    double pr[4], pc[4], pp[4];
+                    const double *sl = m.sta(cb + cn - 1);
+                    double M1 = fma(-gtr, sl[S_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
+                    if constexpr (PIV) {
+                        const double iM = rcp(M1);
+                        rl[F_U] = (S1 * iu) * iM;
+                        rl[F_V] = -sl[S_CA] * M2 * iM;
+                    } else {
+                        rl[F_M] = M1;
+                        rl[F_MN] = M2;
+                        rl[F_U] = S1 * iu;
+                    }
+                    // prefetched RY, CC, CP and CA of the next block, rows j0 .. j0-3
+                    double pr[4], pc[4], pp[4], pa[4];
                     const double *pb = m.rec(cb + cn - 5);  // row j0 - 3 of the first block
                     const double *ps = m.sta(cb + cn - 5);
 #pragma unroll
@@ -392,12 +419,14 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         pr[q] = pb[(3 - q) * STR + F_RY];
                         pc[q] = ps[(3 - q) * SST + S_CC];
                         pp[q] = ps[(3 - q) * SST + S_CP];
+                        pa[q] = PIV ? ps[(3 - q) * SST + S_CA] : 0.0;
                     }
-                    // one block: rows j0 .. j0-3 from (cr, cc, cp) while the next
-                    // block's values load into (nr, nc, np); two blocks per trip with
-                    // the buffers alternating, so no register copies between blocks
+                    // one block: rows j0 .. j0-3 from (cr, cc, cp, ca) while the next
+                    // block's values load into (nr, nc, np, na); two blocks per trip
+                    // with the buffers alternating, so no register copies between blocks
                     auto up_block = [&](const double(&cr)[4], const double(&cc)[4], const double(&cp)[4],
-                                        double(&nr)[4], double(&nc)[4], double(&np)[4], int j0) {
+                                        const double(&ca)[4], double(&nr)[4], double(&nc)[4], double(&np)[4],
+                                        double(&na)[4], int j0) {
                         double *cbk = m.rec(j0 - 3 + cb);
                         const double *nb = cbk - 4 * STR;
                         const double *ns = m.sta(j0 - 3 + cb) - 4 * SST;
@@ -406,6 +435,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                             nr[q] = nb[(3 - q) * STR + F_RY];
                             nc[q] = ns[(3 - q) * SST + S_CC];
                             np[q] = ns[(3 - q) * SST + S_CP];
+                            if constexpr (PIV) na[q] = ns[(3 - q) * SST + S_CA];
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
@@ -415,39 +445,50 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                             M1 = M0;
                             S1 = S0;
                             double *rq = cbk + (3 - q) * STR;
-                            rq[F_M] = M1;
-                            rq[F_MN] = M2;
-                            rq[F_U] = S1 * iu;
+                            if constexpr (PIV) {
+                                const double iM = rcp(M1);
+                                rq[F_U] = (S1 * iu) * iM;
+                                rq[F_V] = -ca[q] * M2 * iM;
+                            } else {
+                                rq[F_M] = M1;
+                                rq[F_MN] = M2;
+                                rq[F_U] = S1 * iu;
+                            }
                         }
                         const double f = M1 > 0x1p332 ? 0x1p-332 : 1.0;
                         M1 *= f;
                         M2 *= f;
                         S1 *= f;
                     };
-                    double qr[4], qc[4], qp[4];
+                    double qr[4], qc[4], qp[4], qa[4];
                     int j0 = cn - 2;
                     for (; j0 >= 8; j0 -= 8) {
-                        up_block(pr, pc, pp, qr, qc, qp, j0);
-                        up_block(qr, qc, qp, pr, pc, pp, j0 - 4);
+                        up_block(pr, pc, pp, pa, qr, qc, qp, qa, j0);
+                        up_block(qr, qc, qp, qa, pr, pc, pp, pa, j0 - 4);
                     }
-                    if (j0 >= 4) up_block(pr, pc, pp, qr, qc, qp, j0);
+                    if (j0 >= 4) up_block(pr, pc, pp, pa, qr, qc, qp, qa, j0);
                 }
                 // top rows 3 .. 0 carry the couplings.  Their elimination goes on
                 // in continuant form, with no division on the dependent path: in
-                // the common scale of these rows (N_j / u^(cn-4)),
+                // units of the generic row 4's continuant (N_j / N_4),
                 //   Q_j = be_j Q_{j+1} - ga_j b_{j+1} Q_{j+2},  Z_j = z_j Q_{j+1} - ga_j Z_{j+1}
-                // for z the rhs and each coupling column, where the generic row 4
-                // enters as Q_4 = M_4, b_4 Q_5 = -CA_4 M_5, Z_4 = S_4 / u (zero for
-                // the couplings).  Then pivot_j = Q_j / Q_{j+1} and z'_j / pivot_j =
+                // for z the rhs and each coupling column, where row 4 enters as
+                // Q_4 = 1, b_4 Q_5 = -CA_4 M_5 / M_4 = V_4 and Z_4 = U_4 (zero for the
+                // couplings).  Then pivot_j = Q_j / Q_{j+1} and z'_j / pivot_j =
                 // Z_j / Q_j: the four reciprocals are independent of one another.
                 // (A four-row chain starts from Q_4 = 1, Q_5 = 0, Z_4 = 0.)
                 double Q1 = 1.0, Q2 = 0.0, bq1 = 0.0, Z0 = 0.0, ZH = 0.0, ZE = 0.0, ZP = 0.0;
                 if (cn >= 5) {
                     const double *r4 = m.rec(cb + 4);
-                    Q1 = r4[F_M];
-                    Q2 = r4[F_MN];
-                    bq1 = -m.sta(cb + 4)[S_CA];
-                    Z0 = r4[F_U];
+                    bq1 = 1.0;
+                    if constexpr (PIV) {
+                        Q2 = r4[F_V];
+                        Z0 = r4[F_U];
+                    } else {  // the operations of the D0 pass below
+                        const double iM = rcp(r4[F_M]);
+                        Q2 = -m.sta(cb + 4)[S_CA] * r4[F_MN] * iM;
+                        Z0 = r4[F_U] * iM;
+                    }
                 }
                 double Qs[5], z0[4], zH[4], zE[4], zP[4], al[4];
                 Qs[4] = Q1;
@@ -500,18 +541,20 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             }
             wsync();
             // (D0) row lanes turn the continuants of the generic rows into the
-            // downward recurrence y_j = U_j - V_j y_{j-1}:
-            // U_j = T_j / N_j = S_j / (u M_j),  V_j = a_j N_{j+1} / N_j = -CA_j M_{j+1} / M_j
+            // downward recurrence y_j = U_j - V_j y_{j-1} (wide shapes only; see
+            // the upward sweep): U_j = S_j / (u M_j),  V_j = -CA_j M_{j+1} / M_j
             // (selects rather than a branch per row, so the rows' loads and
             // reciprocals overlap; other rows keep their values)
+            if constexpr (!PIV) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double *q = m.rec(gl * R + r);
-                const double ca = m.sta(gl * R + r)[S_CA], fm = q[F_M], fu = q[F_U], fmn = q[F_MN];
-                const double iM = rcp(fm);
-                const bool gen = ca != 0.0;
-                q[F_U] = gen ? fu * iM : fu;
-                q[F_V] = gen ? -ca * fmn * iM : fmn;
+                for (int r = 0; r < R; ++r) {
+                    double *q = m.rec(gl * R + r);
+                    const double ca = m.sta(gl * R + r)[S_CA], fm = q[F_M], fu = q[F_U], fmn = q[F_MN];
+                    const double iM = rcp(fm);
+                    const bool gen = ca != 0.0;
+                    q[F_U] = gen ? fu * iM : fu;
+                    q[F_V] = gen ? -ca * fmn * iM : fmn;
+                }
             }
             // (C) couplings: 3x3 (2x2 without polarisation) system, one lane
             if (gl == 0) {
