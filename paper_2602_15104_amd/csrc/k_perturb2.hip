@@ -33,6 +33,13 @@ namespace cmbhip {
 
 namespace {
 
+// p, made opaque to the optimiser where it is formed: addresses derived from it
+// are computed at their use instead of being hoisted as loop invariants.
+__device__ inline double *lane_ptr(double *p) {
+    __asm__ volatile("" : "+v"(p));
+    return p;
+}
+
 // Modes: either the whole [n_cosmo][n_k] batch (items == nullptr; outputs in
 // Sout/status/nsteps, largest k first) or the work list items[n_items] of
 // (cosmology, mode) pairs, each cosmology with its own grids and its own
@@ -58,8 +65,8 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
     const int NP = G * R;
     // pivots of the chain rows formed in the upward sweep (groups of five or
     // more rows per lane, several modes per wavefront) or by a row-parallel pass
-    // (fewer rows per lane, and the record and replay instances); the same bits
-    constexpr bool PIV = R >= 5 && !HIST;
+    // (fewer rows per lane); the same bits
+    constexpr bool PIV = R >= 5;
     Slab m;
     {
         double *stat = lds;
@@ -303,12 +310,15 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
         if (slot >= tb.ck_cap) return;
         double *q = ckp + (size_t)slot * ck_stride;
         if (gl == 0) q[0] = t;
+        // this lane's rows from a base formed here (opaque to the optimiser, so
+        // that the per-row addresses are not hoisted out of the step loop and
+        // held in registers for the whole integration)
+        double *qr = lane_ptr(q + 1 + gl * R);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int row = gl * R + r;
-            if (row < N) {
-                q[1 + row] = w.y[r];
-                q[1 + N + row] = w.K[0][r];
+            if (gl * R + r < N) {
+                qr[r] = w.y[r];
+                qr[N + r] = w.K[0][r];
             }
         }
     };
@@ -723,13 +733,13 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     q[1] = h;
                     q[2] = tn;
                 }
+                double *qr = lane_ptr(q + 3 + gl * R);  // as in put_ck
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int row = gl * R + r;
-                    if (row < N) {
-                        q[3 + row] = w.y[r];
+                    if (gl * R + r < N) {
+                        qr[r] = w.y[r];
 #pragma unroll
-                        for (int j = 0; j < NSTG; ++j) q[3 + (1 + j) * N + row] = w.K[j][r];
+                        for (int j = 0; j < NSTG; ++j) qr[(1 + j) * N + r] = w.K[j][r];
                     }
                 }
             }
