@@ -40,7 +40,7 @@ constexpr int LB = 12;  // multipoles per reduction batch (LDS stays below 64 Ki
 constexpr int PAD = 1;
 
 template <int M>
-__global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) los_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
                                                     int ell_max, int want_E, double s_pol,
                                                     const double *__restrict__ S, double *__restrict__ Delta) {
     __shared__ double red[2][LB][BLOCK + PAD];
@@ -146,33 +146,52 @@ __global__ void __launch_bounds__(BLOCK) los_kernel(const DevTab *__restrict__ t
         DE[l - 2] = 0.0;
     }
     const int sum_id = tid >> 3, sub = tid & 7;  // 32 sums x 8 lanes in the reduction
+    // The recurrence's two arrays take turns: at multipole l the array A holds
+    // j_l and B holds j_{l+1}, and B receives j_{l-1}; the next multipole reads
+    // them the other way round.  So no value is moved between registers.  The
+    // multipoles go in pairs (the batches hold an even number, LB, but the
+    // last), so the array that is current at l depends only on the parity of
+    // lstart - l; each output time's start values, frozen above its l_act, are
+    // placed so that the current array holds j_{l_act} when the walk reaches it.
+    static_assert(LB % 2 == 0, "batches of an even number of multipoles");
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if ((lstart - lact[m]) & 1) {
+            const double t = jl[m];
+            jl[m] = jp[m];
+            jp[m] = t;
+        }
+    }
+    auto one_l = [&](int i, int l, double(&A)[M], double(&B)[M]) __attribute__((always_inline)) {
+        double fl = (double)l;
+        double q = fl * (fl + 1.0);
+        double c21 = 2.0 * fl + 1.0;
+        double tacc = 0.0, eacc = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (l <= lact[m]) {
+                double j = A[m], j1 = B[m];
+                double P = fma(q, cB[m], fma(fl, cD[m], cA[m]));
+                tacc = fma(j, P, fma(-j1, cC[m], tacc));
+                eacc = fma(cE[m], j, eacc);
+                B[m] = fma(c21 * rx[m], j, -j1);
+            }
+        }
+        if (l == 2) {
+            tacc += t2_extra;
+            eacc += e2_extra;
+        }
+        red[0][i][tid] = tacc;
+        red[1][i][tid] = eacc;
+    };
     for (int lb = lstart; lb >= 2; lb -= LB) {
         int nb = lb - 1 < LB ? lb - 1 : LB;  // multipoles in this batch: lb, lb-1, ..., lb-nb+1
-        for (int i = 0; i < nb; ++i) {
-            int l = lb - i;
-            double fl = (double)l;
-            double q = fl * (fl + 1.0);
-            double c21 = 2.0 * fl + 1.0;
-            double tacc = 0.0, eacc = 0.0;
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (l <= lact[m]) {
-                    double j = jl[m], j1 = jp[m];
-                    double P = fma(q, cB[m], fma(fl, cD[m], cA[m]));
-                    tacc = fma(j, P, fma(-j1, cC[m], tacc));
-                    eacc = fma(cE[m], j, eacc);
-                    double jm = fma(c21 * rx[m], j, -j1);
-                    jp[m] = j;
-                    jl[m] = jm;
-                }
-            }
-            if (l == 2) {
-                tacc += t2_extra;
-                eacc += e2_extra;
-            }
-            red[0][i][tid] = tacc;
-            red[1][i][tid] = eacc;
+        int i = 0;
+        for (; i + 1 < nb; i += 2) {
+            one_l(i, lb - i, jl, jp);
+            one_l(i + 1, lb - i - 1, jp, jl);
         }
+        if (i < nb) one_l(i, lb - i, jl, jp);  // the last batch's odd multipole
         __syncthreads();
         {
             int v = sum_id / LB, i = sum_id % LB;
