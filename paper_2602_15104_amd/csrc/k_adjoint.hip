@@ -369,51 +369,72 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             // dependent path: M_j = piv_j M_{j+1} - g^2 sup_j sub_{j+1} M_{j+2} (the
             // forward solve's pivots: sup_j sub_{j+1} = a_{j+1} c_j <= 0, so every
             // term is non-negative) and Z_j = rhs_j M_{j+1} + g sup_j Z_{j+1}; then
-            // U_j = Z_j / M_j and V_j = g sub_j M_{j+1} / M_j.  Each row keeps
-            // (M_{j+1}, M_j, Z_j) in its fields (B, V, U) for the row lanes to
-            // divide; M and Z are rescaled by 2^-332 whenever M passes 2^332.
+            // U_j = Z_j / M_j and V_j = g sub_j M_{j+1} / M_j, formed here beside
+            // the recurrences (the reciprocal is off their dependent path) and the
+            // only values stored.  Rows go in blocks of four with the next block's
+            // entries in flight; M and Z are rescaled by 2^-332 at the end of a
+            // block whenever M passes 2^332 (U and V are ratios: the same bits).
+            // Blocks always run whole: rows above the fifth receive values nobody
+            // reads, and reads stay within the record pads.
             if (ch.cn > 4) {
+                const int cb = ch.cb;
                 double M1 = 1.0, M2 = 0.0, Z1 = 0.0;  // M_{j+1}, M_{j+2}, Z_{j+1}
-                int row = ch.cb + ch.cn - 1;
-                double dd = m.rec(row)[F_D], cj = m.rec(row)[F_C], rh = afr(row)[AF_B];
-                double aup = 0.0;  // a_{j+1}: none below the last row
-                for (int j = ch.cn - 1; j >= 4; --j) {
-                    row = ch.cb + j;
-                    // the next row's entries, loaded ahead of this row's arithmetic
-                    const double na = m.rec(row)[F_A];
-                    double nd = 0.0, nc = 0.0, nr = 0.0;
-                    if (j > 4) {
-                        nd = m.rec(row - 1)[F_D];
-                        nc = m.rec(row - 1)[F_C];
-                        nr = afr(row - 1)[AF_B];
+                double aup = 0.0;                     // a_{j+1}: none below the last row
+                // entries of rows j0 .. j0-3 (d, c, a, rhs) and c of row j0-4
+                struct Blk {
+                    double d[4], c[5], a[4], r[4];
+                };
+                auto load_blk = [&](int j0, Blk &e) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double *rq = m.rec(cb + j0 - q);
+                        e.d[q] = rq[F_D];
+                        e.c[q] = rq[F_C];
+                        e.a[q] = rq[F_A];
+                        e.r[q] = afr(cb + j0 - q)[AF_B];
                     }
-                    const double piv = 1.0 - g * dd;
-                    const double gs = g * aup;
-                    const double M = fma(piv, M1, (-gs * g * cj) * M2);
-                    const double Z = fma(rh, M1, gs * Z1);
-                    double *f = afr(row);
-                    f[AF_B] = M1;
-                    f[AF_V] = M;
-                    f[AF_U] = Z;
-                    M2 = M1;
-                    M1 = M;
-                    Z1 = Z;
-                    if (M1 > 0x1p332) {
-                        M1 *= 0x1p-332;
-                        M2 *= 0x1p-332;
-                        Z1 *= 0x1p-332;
+                    e.c[4] = m.rec(cb + j0 - 4)[F_C];
+                };
+                auto up_blk = [&](const Blk &e, Blk &nx, int j0) __attribute__((always_inline)) {
+                    load_blk(j0 - 4, nx);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double piv = 1.0 - g * e.d[q];
+                        const double gs = g * aup;
+                        const double M = fma(piv, M1, (-gs * g * e.c[q]) * M2);
+                        const double Z = fma(e.r[q], M1, gs * Z1);
+                        const double iM = rcp(M);
+                        double *f = afr(cb + j0 - q);
+                        f[AF_U] = Z * iM;
+                        f[AF_V] = g * e.c[q + 1] * M1 * iM;  // sub_j = c_{j-1}
+                        M2 = M1;
+                        M1 = M;
+                        Z1 = Z;
+                        aup = e.a[q];
                     }
-                    dd = nd;
-                    cj = nc;
-                    rh = nr;
-                    aup = na;
+                    const double sc = M1 > 0x1p332 ? 0x1p-332 : 1.0;
+                    M1 *= sc;
+                    M2 *= sc;
+                    Z1 *= sc;
+                };
+                Blk e0, e1;
+                load_blk(ch.cn - 1, e0);
+                int j0 = ch.cn - 1;
+                for (; j0 >= 8; j0 -= 8) {
+                    up_blk(e0, e1, j0);
+                    up_blk(e1, e0, j0 - 4);
                 }
-                // row 4's U and V for the top rows (sub_4 = c_3)
-                const double iM = rcp(M1);
-                U1 = Z1 * iM;
-                V1 = g * m.rec(ch.cb + 3)[F_C] * M2 * iM;
+                if (j0 >= 4) up_blk(e0, e1, j0);
+                // row 4's U and V for the top rows (sub_4 = c_3), as stored above
+                U1 = afr(cb + 4)[AF_U];
+                V1 = afr(cb + 4)[AF_V];
             }
-            for (int j = (ch.cn < 4 ? ch.cn : 4) - 1; j >= 0; --j) {
+            // top rows 3 .. 0 with static indices (every register array index a
+            // constant); rows at or past the end of a chain shorter than four
+            // rows are skipped, as their affine maps and V stay zero
+#pragma unroll
+            for (int j = 3; j >= 0; --j) {
+                if (j >= ch.cn) continue;
                 const int row = ch.cb + j;
                 const double dd = m.rec(row)[F_D];
                 const double sub = j > 0 ? m.rec(row - 1)[F_C] : 0.0;
@@ -481,20 +502,6 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             }
         }
         wsync();
-        // (1b) row lanes: U_j = Z_j / M_j and V_j = g sub_j M_{j+1} / M_j of the
-        // generic rows (independent reciprocals, off the chains' dependent path)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!((gen >> r) & 1u)) continue;
-            const int row = gl * R + r;
-            double *f = afr(row);
-            const double iM = rcp(f[AF_V]);
-            const double U = f[AF_U] * iM;
-            const double V = g * m.rec(row - 1)[F_C] * f[AF_B] * iM;
-            f[AF_U] = U;
-            f[AF_V] = V;
-        }
-        wsync();
         // (2) one lane: the coupling unknowns zeta = (u_H.x, u_E.x, u_P.x)
         if (gl == 0) {
             double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, d[3] = {0, 0, 0};
@@ -555,17 +562,43 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         // (3) chains: the top rows from zeta, the others downwards
         if (gl < L.nch) {
             const Chain ch = chain_by_index(gl, L);
+            const int cb = ch.cb, cn = ch.cn;
             const double zH = m.AX[0], zE = m.AX[1], zP = m.AX[2];
             double xp = 0.0;
-            for (int j = 0; j < ch.cn; ++j) {
-                const int row = ch.cb + j;
-                if (j < 4) {
-                    const double *q = m.AX + 4 + 16 * gl + 4 * j;
-                    xp = fma(q[1], zH, fma(q[2], zE, fma(q[3], zP, q[0])));
-                } else {
-                    xp = fma(afr(row)[AF_V], xp, afr(row)[AF_U]);
+            for (int j = 0; j < 4 && j < cn; ++j) {
+                const double *q = m.AX + 4 + 16 * gl + 4 * j;
+                xp = fma(q[1], zH, fma(q[2], zE, fma(q[3], zP, q[0])));
+                afr(cb + j)[AF_X] = xp;
+            }
+            // generic rows in blocks of four with the next block's U, V in
+            // flight; rows past the chain end go to a spare record
+            double pu[4], pv[4], qu[4], qv[4];
+            auto load_uv = [&](int j0, double(&u)[4], double(&v)[4]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double *f = afr(cb + j0 + q);
+                    u[q] = f[AF_U];
+                    v[q] = f[AF_V];
                 }
-                afr(row)[AF_X] = xp;
+            };
+            double *const spare = afr(-1);
+            auto down_blk = [&](const double(&u)[4], const double(&v)[4], double(&nu)[4], double(&nv)[4], int j0)
+                                __attribute__((always_inline)) {
+                load_uv(j0 + 4, nu, nv);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    xp = fma(v[q], xp, u[q]);
+                    (j0 + q < cn ? afr(cb + j0 + q) : spare)[AF_X] = xp;
+                }
+            };
+            if (cn > 4) {
+                load_uv(4, pu, pv);
+                int j0 = 4;
+                for (; j0 + 4 < cn; j0 += 8) {
+                    down_blk(pu, pv, qu, qv, j0);
+                    down_blk(qu, qv, pu, pv, j0 + 4);
+                }
+                if (j0 < cn) down_blk(pu, pv, qu, qv, j0);
             }
         }
         wsync();
