@@ -50,6 +50,10 @@ namespace {
 
 constexpr int NAF = 4;  // adjoint fields per row: right-hand side, solution, elimination U and V
 constexpr int AF_B = 0, AF_X = 1, AF_U = 2, AF_V = 3;
+// per-row flags of a lane's rows (bit positions)
+constexpr unsigned RI_VALID = 1u, RI_TOP = 2u, RI_UP = 4u, RI_DN = 8u, RI_TG = 16u, RI_DG = 32u, RI_DC = 64u,
+                   RI_ETA = 128u;
+constexpr int RI_WH = 8, RI_WE = 11, RI_WP = 13;
 constexpr int NPAR = 4;  // parameters with table tangents: h, omega_b, omega_cdm, tau_reio
 // stage backgrounds kept per mode: the 2 NPAR perturbed tables' (slot q) and
 // the mode's own (slot 2 NPAR)
@@ -192,15 +196,55 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     // entries are multipliers of kH and trunc, and -T on the photon chains)
     // and the rest (the chains' top rows and the isolated rows)
     unsigned gen = 0, pho = 0;
+    // and per row what the stage code asks of the layout, found once here:
+    // inside the matrix, a chain's top row, the chain neighbours above and
+    // below, the theta_g / delta_g link rows, and how the row enters the
+    // couplings (which factor of h' = w_H . y, eta' = w_E . y, Pi = w_P . y,
+    // as w_row states them)
+    unsigned rinfo[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = gl * R + r;
+        unsigned f = 0;
         Chain cs;
-        if (row < N && chain_of(row, L, cs)) {
-            if (row - cs.cb >= 4) gen |= 1u << r;
-            if (cs.ty <= 1) pho |= 1u << r;
+        if (row < N) {
+            f |= RI_VALID;
+            if (chain_of(row, L, cs)) {
+                if (row - cs.cb >= 4) gen |= 1u << r;
+                else f |= RI_TOP;
+                if (cs.ty <= 1) pho |= 1u << r;
+                if (row > cs.cb) f |= RI_UP;
+                if (row + 1 < cs.cb + cs.cn) f |= RI_DN;
+            }
+            if (row == 2) f |= RI_TG;
+            if (row == L.rDG) f |= RI_DG;
+            if (row == L.rDC) f |= RI_DC;
+            if (row == L.rETA) f |= RI_ETA;
+            unsigned wh = 0, we = 0, wp = 0;
+            if (row == L.rETA) wh = 1;
+            if (row == L.rDC) wh = 2;
+            if (row == 0) wh = 3;
+            if (row == L.rDG) wh = 4;
+            if (row == L.bV) wh = 5;
+            if (row == 1) we = 1;
+            if (row == 2) we = 2;
+            if (row == L.bV + 1) we = 3;
+            if (p.lp > 0) {
+                if (row == 3) wp = 2;
+                if (row == L.bG || row == L.bG + 2) wp = 1;
+            }
+            f |= wh << RI_WH | we << RI_WE | wp << RI_WP;
         }
+        rinfo[r] = f;
     }
+    // w_row of a row from its flags (the same products)
+    auto w_of = [&](unsigned f, const Bk &s, double &wH, double &wE, double &wP) __attribute__((always_inline)) {
+        const unsigned wh = (f >> RI_WH) & 7u, we = (f >> RI_WE) & 3u, wp = (f >> RI_WP) & 3u;
+        wH = wh == 1 ? s.cH1 : wh == 2 ? s.cH2 * s.rc : wh == 3 ? s.cH2 * s.rb : wh == 4 ? s.cH2 * s.rg
+                                                                              : wh == 5 ? s.cH2 * s.rur : 0.0;
+        wE = we == 1 ? s.cE * s.rb : we == 2 ? s.cE * (4.0 / 3.0) * s.rg : we == 3 ? s.cE * (4.0 / 3.0) * s.rur : 0.0;
+        wP = wp == 2 ? 2.0 : wp == 1 ? 1.0 : 0.0;
+    };
     // entries of row `row` of A at background s (as row_coef): the multipliers
     // table for generic rows, the top-row formulas otherwise
     auto coef_at = [&](int row, const Bk &s, bool generic, bool photon) __attribute__((always_inline)) {
@@ -316,19 +360,56 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
     // records, the couplings' u in the adjoint fields; the transposed solve
     // reads them too) and its share of u . b.
     auto apply_t = [&](const Bk &s, double *out) __attribute__((always_inline)) {
+        // the chains' top rows (position j static, type per lane): entries into
+        // the records, coupling coefficients into the free adjoint fields
+        // (U, V, X) for the row lanes
+        if (gl < L.nch) {
+            const Chain ch = chain_by_index(gl, L);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j >= ch.cn) continue;
+                const RowCo cc = top_coef<false>(ch.ty, j, L, s, p, 0.0, 0.0);
+                double *q = m.rec(ch.cb + j);
+                q[F_A] = cc.a;
+                q[F_D] = cc.d;
+                q[F_C] = cc.c;
+                double *f = afr(ch.cb + j);
+                f[AF_U] = cc.uH;
+                f[AF_V] = cc.uE;
+                f[AF_X] = cc.uP;
+            }
+        }
+        wsync();
         double zH = 0.0, zE = 0.0, zP = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
-            const RowCo cc = coef_at(row, s, (gen >> r) & 1u, (pho >> r) & 1u);
-            double *q = m.rec(row);
-            q[F_A] = cc.a;
-            q[F_D] = cc.d;
-            q[F_C] = cc.c;
+            const unsigned fl = rinfo[r];
+            double uH = 0.0, uE = 0.0, uP = 0.0;
+            if ((gen >> r) & 1u) {
+                const double *q = m.sta(row);
+                double *e = m.rec(row);
+                e[F_A] = q[S_CA] * s.kH;
+                e[F_C] = q[S_CC] * s.kH;
+                e[F_D] = ((pho >> r) & 1u) ? fma(q[S_CD], s.trunc, -s.T) : q[S_CD] * s.trunc;
+            } else if (fl & RI_TOP) {
+                const double *f = afr(row);
+                uH = f[AF_U];
+                uE = f[AF_V];
+                uP = f[AF_X];
+            } else {  // isolated rows and padding: no entries
+                double *e = m.rec(row);
+                e[F_A] = 0.0;
+                e[F_D] = 0.0;
+                e[F_C] = 0.0;
+                if (fl & RI_DC) uH = -0.5;
+                if (fl & RI_ETA) uE = 1.0;
+                if (fl & RI_DG) uH = -2.0 / 3.0;
+            }
             const double v = afr(row)[AF_B];
-            zH = fma(cc.uH, v, zH);
-            zE = fma(cc.uE, v, zE);
-            zP = fma(cc.uP, v, zP);
+            zH = fma(uH, v, zH);
+            zE = fma(uE, v, zE);
+            zP = fma(uP, v, zP);
         }
         zH = group_sum(zH);
         zE = group_sum(zE);
@@ -337,18 +418,17 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int row = gl * R + r;
+            const unsigned fl = rinfo[r];
             double v = 0.0;
-            if (row < N) {
-                Chain cs;
-                const bool inch = chain_of(row, L, cs);
+            if (fl & RI_VALID) {
                 v = m.rec(row)[F_D] * afr(row)[AF_B];
                 // (A^T)_{row,row-1} = A_{row-1,row} (c of the row above), (A^T)_{row,row+1} = a of the row below
-                if (inch && row > cs.cb) v = fma(m.rec(row - 1)[F_C], afr(row - 1)[AF_B], v);
-                if (inch && row + 1 < cs.cb + cs.cn) v = fma(m.rec(row + 1)[F_A], afr(row + 1)[AF_B], v);
-                if (row == 2) v = fma(-(4.0 / 3.0) * s.invHc, afr(L.rDG)[AF_B], v);  // delta_g' = -(4/3) theta_g / Hc ...
-                if (row == L.rDG) v = fma(0.25 * s.k2H, afr(2)[AF_B], v);          // theta_g' = ... + k^2 delta_g / (4 Hc)
+                if (fl & RI_UP) v = fma(m.rec(row - 1)[F_C], afr(row - 1)[AF_B], v);
+                if (fl & RI_DN) v = fma(m.rec(row + 1)[F_A], afr(row + 1)[AF_B], v);
+                if (fl & RI_TG) v = fma(-(4.0 / 3.0) * s.invHc, afr(L.rDG)[AF_B], v);  // delta_g' = -(4/3) theta_g / Hc ...
+                if (fl & RI_DG) v = fma(0.25 * s.k2H, afr(2)[AF_B], v);          // theta_g' = ... + k^2 delta_g / (4 Hc)
                 double wH, wE, wP;
-                w_row(row, L, s, p, wH, wE, wP);
+                w_of(fl, s, wH, wE, wP);
                 v = fma(wH, zH, fma(wE, zE, fma(wP, zP, v)));
             }
             out[r] = v;
@@ -629,18 +709,16 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             }
             if (cidx[r] < 0) continue;
             const double *e = tbl + cidx[r] * TBLW;
-            Chain cs;
-            const bool inch = chain_of(row, L, cs);
-            const double ym = (inch && row > cs.cb) ? m.ry(row - 1) : 0.0;
-            const double yp = (inch && row + 1 < cs.cb + cs.cn) ? m.ry(row + 1) : 0.0;
+            const double ym = (rinfo[r] & RI_UP) ? m.ry(row - 1) : 0.0;
+            const double yp = (rinfo[r] & RI_DN) ? m.ry(row + 1) : 0.0;
 #pragma unroll
             for (int bb = 1; bb < NBAS; ++bb)
                 Gb[bb] = fma(mu[r], fma(e[bb], ym, fma(e[NBAS + bb], yr, e[2 * NBAS + bb] * yp)), Gb[bb]);
             UH = fma(mu[r], e[3 * NBAS], UH);
             UE = fma(mu[r], e[3 * NBAS + 1], UE);
             UPT = fma(mu[r], e[3 * NBAS + 2], UPT);
-            if (row == 2) Gb[3] = fma(0.25 * mu[r], m.ry(L.rDG), Gb[3]);  // theta_g' ... + k^2 delta_g / (4 Hc)
-            if (row == L.rDG) Gb[1] = fma(-(4.0 / 3.0) * mu[r], m.ry(2), Gb[1]);  // delta_g' = -(4/3) theta_g / Hc ...
+            if (rinfo[r] & RI_TG) Gb[3] = fma(0.25 * mu[r], m.ry(L.rDG), Gb[3]);  // theta_g' ... + k^2 delta_g / (4 Hc)
+            if (rinfo[r] & RI_DG) Gb[1] = fma(-(4.0 / 3.0) * mu[r], m.ry(2), Gb[1]);  // delta_g' = -(4/3) theta_g / Hc ...
         }
         const double Yeta = m.ry(L.rETA), Ydc = m.ry(L.rDC), Y0 = m.ry(0), Ydg = m.ry(L.rDG), YbV = m.ry(L.bV);
         const double Y1 = m.ry(1), Y2 = m.ry(2), YbV1 = m.ry(L.bV + 1);
