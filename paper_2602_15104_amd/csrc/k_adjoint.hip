@@ -106,8 +106,11 @@ __device__ inline void w_row(int row, const Lay &L, const Bk &s, const DevPrec &
 // vector of NP rows (the forcing at an output), the stage backgrounds and
 // dL/dK_j of every stage and row (each lane only touches its own rows there).
 // The workgroup's LDS starts with the shared multipliers table.
+// the forcing vector's area also holds, during the stages, the parameter
+// contraction's per-parameter differences (NPAR x (NBAS + 2) doubles)
+__host__ __device__ constexpr int gv_doubles(int NP) { return NP > NPAR * (NBAS + 2) ? NP : NPAR * (NBAS + 2); }
 __host__ __device__ constexpr int adj_slab_doubles(int NP, int nch) {
-    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NP + 2 * PADR) * NAF + NP + NBKS * NBK + NSTG * NP;
+    return (NP + 2 * PADR) * STR + ax_doubles(nch) + (NP + 2 * PADR) * NAF + gv_doubles(NP) + NBKS * NBK + NSTG * NP;
 }
 __host__ __device__ constexpr int adj_lds_doubles(int NP, int nch, int spw) {
     return stat_doubles(NP) + top_rows(nch) * TBLW + spw * adj_slab_doubles(NP, nch);
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
         m.BK = nullptr;  // the forward kernel's stage records are not used here
         af = m.AX + ax_doubles(L.nch);
         gv = af + (NP + 2 * PADR) * NAF;
-        bks = gv + NP;
+        bks = gv + gv_doubles(NP);
         kbb = bks + NBKS * NBK;
         for (int i = gl; i < adj_slab_doubles(NP, L.nch); i += G) base[i] = 0.0;
         for (int i = gl; i < stat_doubles(NP); i += G) stat[i] = 0.0;
@@ -720,25 +723,47 @@ __global__ void __launch_bounds__(64) adjoint_kernel(const DevTab *__restrict__ 
             if (rinfo[r] & RI_TG) Gb[3] = fma(0.25 * mu[r], m.ry(L.rDG), Gb[3]);  // theta_g' ... + k^2 delta_g / (4 Hc)
             if (rinfo[r] & RI_DG) Gb[1] = fma(-(4.0 / 3.0) * mu[r], m.ry(2), Gb[1]);  // delta_g' = -(4/3) theta_g / Hc ...
         }
-        const double Yeta = m.ry(L.rETA), Ydc = m.ry(L.rDC), Y0 = m.ry(0), Ydg = m.ry(L.rDG), YbV = m.ry(L.bV);
-        const double Y1 = m.ry(1), Y2 = m.ry(2), YbV1 = m.ry(L.bV + 1);
-        const double Pv = p.lp > 0 ? 2.0 * m.ry(3) + m.ry(L.bG) + m.ry(L.bG + 2) : 0.0;
-        double dq[2 * NPAR];
+        // mu . (A(theta+) - A(theta-)) v / den is linear in the bases and the
+        // couplings h', eta', Pi of v at each background: their differences
+        // between the two tables of a parameter, divided by den, are formed once
+        // per stage, one parameter per lane, and left in gv (free between
+        // output times) for every lane to dot with its own sums.  Differencing
+        // the bases before the contraction also cancels the two nearly equal
+        // tables on exact inputs rather than on rounded sums.
+        constexpr int DVW = NBAS + 2;  // bases 1..7, then H, E, T Pi
+        if (gl < NPAR) {
+            const int i = gl;
+            const Bk &sa = bk_ref(2 * i), &sb = bk_ref(2 * i + 1);
+            const double Yeta = m.ry(L.rETA), Ydc = m.ry(L.rDC), Y0 = m.ry(0), Ydg = m.ry(L.rDG), YbV = m.ry(L.bV);
+            const double Y1 = m.ry(1), Y2 = m.ry(2), YbV1 = m.ry(L.bV + 1);
+            const double Pv = p.lp > 0 ? 2.0 * m.ry(3) + m.ry(L.bG) + m.ry(L.bG + 2) : 0.0;
+            auto HE = [&](const Bk &sq, double &H, double &E) __attribute__((always_inline)) {
+                H = fma(sq.cH1, Yeta, sq.cH2 * fma(sq.rc, Ydc, fma(sq.rb, Y0, fma(sq.rg, Ydg, sq.rur * YbV))));
+                E = sq.cE * fma(sq.rb, Y1, fma((4.0 / 3.0) * sq.rg, Y2, (4.0 / 3.0) * sq.rur * YbV1));
+            };
+            double va[NBAS], vb[NBAS], Ha, Ea, Hb, Eb;
+            bases_of(sa, va);
+            bases_of(sb, vb);
+            HE(sa, Ha, Ea);
+            HE(sb, Hb, Eb);
+            const double id = 1.0 / den[i];
+            double *dv = gv + i * DVW;
 #pragma unroll
-        for (int qi = 0; qi < 2 * NPAR; ++qi) {
-            const Bk &sq = bk_ref(qi);
-            double v[NBAS];
-            bases_of(sq, v);
+            for (int bb = 1; bb < NBAS; ++bb) dv[bb - 1] = (va[bb] - vb[bb]) * id;
+            dv[NBAS - 1] = (Ha - Hb) * id;
+            dv[NBAS] = (Ea - Eb) * id;
+            dv[NBAS + 1] = (sa.T - sb.T) * Pv * id;
+        }
+        wsync();
+#pragma unroll
+        for (int i = 0; i < NPAR; ++i) {
+            const double *dv = gv + i * DVW;
             double d = 0.0;
 #pragma unroll
-            for (int bb = 1; bb < NBAS; ++bb) d = fma(Gb[bb], v[bb], d);
-            const double H = fma(sq.cH1, Yeta, sq.cH2 * fma(sq.rc, Ydc, fma(sq.rb, Y0, fma(sq.rg, Ydg, sq.rur * YbV))));
-            const double E = sq.cE * fma(sq.rb, Y1, fma((4.0 / 3.0) * sq.rg, Y2, (4.0 / 3.0) * sq.rur * YbV1));
-            d = fma(UH, H, fma(UE, E, fma(UPT * sq.T, Pv, d)));
-            dq[qi] = d;
+            for (int bb = 1; bb < NBAS; ++bb) d = fma(Gb[bb], dv[bb - 1], d);
+            d = fma(UH, dv[NBAS - 1], fma(UE, dv[NBAS], fma(UPT, dv[NBAS + 1], d)));
+            acc[i] += d;
         }
-#pragma unroll
-        for (int i = 0; i < NPAR; ++i) acc[i] += (dq[2 * i] - dq[2 * i + 1]) / den[i];
         wsync();
     };
 
