@@ -411,6 +411,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     double *rl = m.rec(cb + cn - 1);
                     const double *sl = m.sta(cb + cn - 1);
                     double M1 = fma(-gtr, sl[S_CD], 1.0 + gT) * iu, M2 = 1.0, S1 = rl[F_RY];
+                    double caP = sl[S_CA];  // CA_{j+1} for the next row j (CP_j = -CC_j CA_{j+1})
                     if constexpr (PIV) {
                         const double iM = rcp(M1);
                         rl[F_U] = (S1 * iu) * iM;
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                     for (int q = 0; q < 4; ++q) {
                         pr[q] = pb[(3 - q) * STR + F_RY];
                         pc[q] = ps[(3 - q) * SST + S_CC];
-                        pp[q] = ps[(3 - q) * SST + S_CP];
+                        pp[q] = PIV ? 0.0 : ps[(3 - q) * SST + S_CP];
                         pa[q] = PIV ? ps[(3 - q) * SST + S_CA] : 0.0;
                     }
                     // one block: rows j0 .. j0-3 from (cr, cc, cp, ca) while the next
@@ -444,12 +445,15 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
                         for (int q = 0; q < 4; ++q) {
                             nr[q] = nb[(3 - q) * STR + F_RY];
                             nc[q] = ns[(3 - q) * SST + S_CC];
-                            np[q] = ns[(3 - q) * SST + S_CP];
+                            if constexpr (!PIV) np[q] = ns[(3 - q) * SST + S_CP];
                             if constexpr (PIV) na[q] = ns[(3 - q) * SST + S_CA];
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const double M0 = fma(bq, M1, cp[q] * M2);
+                            // CP_j = -CC_j CA_{j+1}, CA_{j+1} being the row below's
+                            const double cpq = PIV ? -cc[q] * caP : cp[q];
+                            if constexpr (PIV) caP = ca[q];
+                            const double M0 = fma(bq, M1, cpq * M2);
                             const double S0 = fma(cr[q], M1, cc[q] * S1);
                             M2 = M1;
                             M1 = M0;

@@ -274,8 +274,9 @@ def test_launch_shape_invariance(ctx):
 def test_dense_shape_record_replay(ctx):
     """Step histories in the dense launch shape (8-lane groups, 8400 modes):
     the recorded history and sources of one cosmology equal its solo record
-    (a whole wavefront per mode) bit for bit, and replaying the dense
-    histories reproduces the sources."""
+    (a whole wavefront per mode) bit for bit, replaying the dense histories
+    reproduces the sources, and the record launch's sources equal the plain
+    launch's on every mode."""
     import torch
     import paper_2602_15104_amd as L
     wl = W.config1()
@@ -309,6 +310,14 @@ def test_dense_shape_record_replay(ctx):
     ctx.perturb_replay(tabs, H, Hn, S2, st2)
     torch.cuda.synchronize()
     assert torch.all(st2 == 0) and torch.equal(S2, S)
+    # the record instance (its own compiled kernel) against the plain one on
+    # the same 8400 modes: every source, bit for bit
+    S3 = torch.empty_like(S)
+    st3 = torch.empty_like(st)
+    ns3 = torch.empty_like(st)
+    ctx.perturb(tabs, S3, st3, ns3)
+    torch.cuda.synchronize()
+    assert torch.all(st3 == 0) and torch.equal(S3, S)
 
 
 def test_batched_parity_box_cosmologies(ctx):
