@@ -39,7 +39,7 @@ enum {
 enum {
     CMB_K_OK = 0,
     CMB_K_MAX_STEPS = 1,      /* max_steps attempted steps before ln a = 0 */
-    CMB_K_NONFINITE = 2,      /* NaN/Inf in the error estimate */
+    CMB_K_NONFINITE = 2,      /* NaN/Inf in the error estimate or the time */
     CMB_K_STEP_UNDERFLOW = 3  /* step size fell below 1e-12 in ln a */
 };
 

@@ -39,6 +39,80 @@ constexpr int BLOCK = 256;
 constexpr int LB = 12;  // multipoles per reduction batch (LDS stays below 64 KiB)
 constexpr int PAD = 1;
 
+// Start values of the walk at one output time (x = k chi > 0).
+// x > l_max + 32: the upward recurrence j_{l+1} = (2l+1)/x j_l - j_{l-1} from
+// (j_0, j_1) to (jl, jp) = (j_{l_max}, j_{l_max+1}).
+__device__ inline void seed_upward(double ix, double j0, double j1, int ltop, double &jl, double &jp) {
+    double a = j0, b = j1;
+#pragma unroll 2
+    for (int l = 1; l < ltop; ++l) {
+        const double nb = (2.0 * l + 1.0) * ix * b - a;
+        a = b;
+        b = nb;
+    }
+    jp = b;  // j_{ltop}
+    jl = a;  // j_{ell_max}
+}
+
+// Otherwise Miller's downward recurrence from l_s(x) to l = 0, the pair at
+// l_act = min(l_max, l_cut(x)) recorded on the way and the whole normalised
+// by j_0 (or j_1 where larger); values above 1e250 are rescaled by 1e-250.
+// The steps above l_act + 1 (nothing recorded yet), the recording step and
+// the steps below it run as three loops, so that no step tests for l_act;
+// the factor 2l + 1 is carried as a double (exact: an integer far below 2^53)
+// instead of converted from l at every step.
+__device__ inline void seed_miller(double x, double ix, double j0, double j1, int ell_max, double &jl, double &jp,
+                                   int &lact) {
+    const int lc = ell_cut_rule(x);
+    const int la = lc < ell_max ? lc : ell_max;
+    const int ls = ell_start_rule(x);
+    double hi = 0.0, lo = 1e-200;  // J_{l+1}, J_l at l = ls
+    double rp = 0.0, rl = 0.0;
+    double c = 2.0 * ls + 1.0;  // 2l + 1 of the next step
+    const double c_rec = 2.0 * la + 3.0;  // the step at l = l_act + 1
+#pragma unroll 2
+    for (; c > c_rec; c -= 2.0) {
+        const double nlo = c * ix * lo - hi;
+        hi = lo;
+        lo = nlo;
+        if (__builtin_expect(fabs(lo) > 1e250, 0)) {
+            lo *= 1e-250;
+            hi *= 1e-250;
+        }
+    }
+    {  // l = l_act + 1: (hi, lo) becomes (J_{l_act+1}, J_{l_act})
+        const double nlo = c * ix * lo - hi;
+        hi = lo;
+        lo = nlo;
+        rp = hi;
+        rl = lo;
+        if (__builtin_expect(fabs(lo) > 1e250, 0)) {
+            lo *= 1e-250;
+            hi *= 1e-250;
+            rp *= 1e-250;
+            rl *= 1e-250;
+        }
+        c -= 2.0;
+    }
+#pragma unroll 2
+    for (; c > 2.0; c -= 2.0) {  // l = l_act .. 1
+        const double nlo = c * ix * lo - hi;
+        hi = lo;
+        lo = nlo;
+        if (__builtin_expect(fabs(lo) > 1e250, 0)) {
+            lo *= 1e-250;
+            hi *= 1e-250;
+            rp *= 1e-250;
+            rl *= 1e-250;
+        }
+    }
+    // lo = J_0, hi = J_1
+    const double sc = (fabs(j0) >= fabs(j1)) ? j0 / lo : j1 / hi;
+    jp = rp * sc;
+    jl = rl * sc;
+    lact = la;
+}
+
 template <int M>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) los_kernel(const DevTab *__restrict__ tabs, int n_cosmo, int n_k, int n_tau,
                                                     int ell_max, int want_E, double s_pol,
@@ -93,42 +167,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
         sincos(x, &sx, &cx);
         double j0 = sx * ix, j1 = (sx * ix - cx) * ix;
         if (x >= ltop + 32) {
-            // upward: (a, b) = (j_{l-1}, j_l)
-            double a = j0, b = j1;
-            for (int l = 1; l < ltop; ++l) {
-                double nb = (2.0 * l + 1.0) * ix * b - a;
-                a = b;
-                b = nb;
-            }
-            jp[m] = b;  // j_{ltop}
-            jl[m] = a;  // j_{ell_max}
+            seed_upward(ix, j0, j1, ltop, jl[m], jp[m]);
             lact[m] = ell_max;
         } else {
-            int lc = ell_cut_rule(x);
-            int la = lc < ell_max ? lc : ell_max;
-            int ls = ell_start_rule(x);
-            double hi = 0.0, lo = 1e-200;  // J_{l+1}, J_l at l = ls
-            double rp = 0.0, rl = 0.0;
-            for (int l = ls; l > 0; --l) {
-                double nlo = (2.0 * l + 1.0) * ix * lo - hi;
-                hi = lo;
-                lo = nlo;
-                if (l - 1 == la) {
-                    rp = hi;
-                    rl = lo;
-                }
-                if (fabs(lo) > 1e250) {
-                    lo *= 1e-250;
-                    hi *= 1e-250;
-                    rp *= 1e-250;
-                    rl *= 1e-250;
-                }
-            }
-            // lo = J_0, hi = J_1
-            double sc = (fabs(j0) >= fabs(j1)) ? j0 / lo : j1 / hi;
-            jp[m] = rp * sc;
-            jl[m] = rl * sc;
-            lact[m] = la;
+            seed_miller(x, ix, j0, j1, ell_max, jl[m], jp[m], lact[m]);
         }
         my_lmax = lact[m] > my_lmax ? lact[m] : my_lmax;
     }
@@ -169,17 +211,13 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
         double tacc = 0.0, eacc = 0.0;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            if (l <= lact[m]) {
+            if (__builtin_expect(l <= lact[m], 1)) {  // (nearly always: laid out inline)
                 double j = A[m], j1 = B[m];
                 double P = fma(q, cB[m], fma(fl, cD[m], cA[m]));
                 tacc = fma(j, P, fma(-j1, cC[m], tacc));
                 eacc = fma(cE[m], j, eacc);
                 B[m] = fma(c21 * rx[m], j, -j1);
             }
-        }
-        if (l == 2) {
-            tacc += t2_extra;
-            eacc += e2_extra;
         }
         red[0][i][tid] = tacc;
         red[1][i][tid] = eacc;
@@ -192,6 +230,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
             one_l(i + 1, lb - i - 1, jp, jl);
         }
         if (i < nb) one_l(i, lb - i, jl, jp);  // the last batch's odd multipole
+        if (lb - nb + 1 == 2) {  // l = 2 closes the last batch: the x = 0 terms
+            red[0][nb - 1][tid] += t2_extra;
+            red[1][nb - 1][tid] += e2_extra;
+        }
         __syncthreads();
         {
             int v = sum_id / LB, i = sum_id % LB;
@@ -287,39 +329,10 @@ __global__ void __launch_bounds__(BLOCK) los_adj_kernel(const DevTab *__restrict
         sincos(x, &sx, &cx);
         const double j0 = sx * ix, j1 = (sx * ix - cx) * ix;
         if (x >= ltop + 32) {
-            double a = j0, b = j1;
-            for (int l = 1; l < ltop; ++l) {
-                const double nb = (2.0 * l + 1.0) * ix * b - a;
-                a = b;
-                b = nb;
-            }
-            jp[m] = b;
-            jl[m] = a;
+            seed_upward(ix, j0, j1, ltop, jl[m], jp[m]);
             lact[m] = ell_max;
         } else {
-            const int lc = ell_cut_rule(x);
-            const int la = lc < ell_max ? lc : ell_max;
-            const int ls = ell_start_rule(x);
-            double hi = 0.0, lo = 1e-200, rp = 0.0, rl = 0.0;
-            for (int l = ls; l > 0; --l) {
-                const double nlo = (2.0 * l + 1.0) * ix * lo - hi;
-                hi = lo;
-                lo = nlo;
-                if (l - 1 == la) {
-                    rp = hi;
-                    rl = lo;
-                }
-                if (fabs(lo) > 1e250) {
-                    lo *= 1e-250;
-                    hi *= 1e-250;
-                    rp *= 1e-250;
-                    rl *= 1e-250;
-                }
-            }
-            const double sc = (fabs(j0) >= fabs(j1)) ? j0 / lo : j1 / hi;
-            jp[m] = rp * sc;
-            jl[m] = rl * sc;
-            lact[m] = la;
+            seed_miller(x, ix, j0, j1, ell_max, jl[m], jp[m], lact[m]);
         }
         my_lmax = lact[m] > my_lmax ? lact[m] : my_lmax;
     }

@@ -816,6 +816,9 @@ __global__ void __launch_bounds__(64) perturb2_kernel(const DevTab *__restrict__
             break;
         }
     }
+    // a time that is not a number ends the loop as if the mode had finished:
+    // report it instead of a result
+    if (st == CMB_K_OK && !seg_open && !(t >= 0.0)) st = CMB_K_NONFINITE;
     // matter power spectrum today (App. B.4, eq. PK) from the state at a = 1:
     // 2 pi^2/k^3 P_R(k) [sum rho_i delta_i / sum rho_i]^2 over CDM, baryons and
     // the massive neutrinos (0 for a mode that did not finish)
