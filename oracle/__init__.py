@@ -93,6 +93,10 @@ def lib():
             L.oracle_perturb_many_hist.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_int, dp, dp,
                                                    dp, dp, ctypes.c_int, dp, dp, ip, ip, ip, dp, ip, ctypes.c_int,
                                                    ctypes.c_int]
+            L.oracle_perturb_many_tangent.restype = ctypes.c_int
+            L.oracle_perturb_many_tangent.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OTab), dp, ctypes.c_int,
+                                                      ctypes.c_int, ctypes.POINTER(_OPrec), ctypes.c_int, dp,
+                                                      ctypes.c_int, dp, dp, dp, ip, dp, ip, ctypes.c_int]
             L.oracle_rhs.restype = None
             L.oracle_rhs.argtypes = [ctypes.POINTER(_OTab), ctypes.POINTER(_OPrec), ctypes.c_double, ctypes.c_double,
                                      dp, dp]
@@ -384,6 +388,95 @@ def jacobian(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, re
             J[slot[name]] = (8.0 * d1 - d2) / (12.0 * e)
     J[3] = C
     J[4] = cl_dns(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    return C, J, st
+
+
+def perturb_tangent(t, tabs, eps, hist, hist_n, order: int = 4):
+    """Forward-mode tangents of the sources along the given step histories
+    (oracle_perturb_tangent): tabs[d] are the tables at theta_d + eps[d],
+    - eps[d] and, for order 4, + 2 eps[d], - 2 eps[d].
+    Returns (S[n_k][3][n_tau], Sd[n_k][nd][3][n_tau], status[n_k])."""
+    nd = len(tabs)
+    k = np.ascontiguousarray(t.k, dtype=np.float64)
+    n_out = len(t.lna_src)
+    hist = np.ascontiguousarray(hist, dtype=np.float64)
+    hist_n = np.ascontiguousarray(hist_n, dtype=np.int32)
+    S = np.zeros((len(k), 3, n_out))
+    Sd = np.zeros((len(k), nd, 3, n_out))
+    st = np.zeros(len(k), dtype=np.int32)
+    b = _Bound(t)
+    bound = [[_Bound(x) for x in row] + [_Bound(row[0])] * (4 - len(row)) for row in tabs]
+    tt = (_OTab * (4 * nd))(*[x.tab for row in bound for x in row])
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    p = make_prec(t.prec, len(t.bg.q))
+    lna_out = np.ascontiguousarray(t.lna_src, dtype=np.float64)
+    lib().oracle_perturb_many_tangent(ctypes.byref(b.tab), tt, _dp(e), nd, order, ctypes.byref(p), len(k), _dp(k),
+                                      n_out, _dp(lna_out), _dp(S), _dp(Sd), _ip(st), _dp(hist), _ip(hist_n),
+                                      hist.shape[1])
+    return S, Sd, st
+
+
+def cl_tangent(k, DT, DE, dDT, dDE, ell_max: int, pol: bool, A_s: float, n_s: float, k_pivot: float = 0.05):
+    """Derivative of cl along (dDT, dDE) [l-2][k] (the quadrature is bilinear
+    in the transfer functions): Cdot_XY = sum_k 4 pi w_k P(k)/k
+    (dDelta_X Delta_Y + Delta_X dDelta_Y).  Returns [3][ell_max+1]."""
+    k = np.asarray(k, dtype=np.float64)
+    kl = np.concatenate(([k[0]], k[:-1]))
+    kr = np.concatenate((k[1:], [k[-1]]))
+    f = 4 * math.pi * 0.5 * (kr - kl) * A_s * (k / k_pivot) ** (n_s - 1.0) / k
+    C = np.zeros((3, ell_max + 1))
+    C[0, 2:] = np.sum(f * 2.0 * DT * dDT, axis=1)
+    if pol:
+        C[1, 2:] = np.sum(f * (dDT * DE + DT * dDE), axis=1)
+        C[2, 2:] = np.sum(f * 2.0 * DE * dDE, axis=1)
+    return C
+
+
+def jacobian_tangent(cosmo: dict, prec: dict, k, n_tau: int, ell_max: int, pol: bool, rel: float = 1e-4,
+                     order: int = 4):
+    """dC_l/dtheta [6][3][ell_max+1] by forward mode (section 3; the paper's
+    default derivative option): the tangents of the frozen-step discrete map
+    (perturb_tangent) with the tables' own dependence on h, omega_b,
+    omega_cdm and tau_reio taken as differences (central for order 2,
+    five-point for order 4) of table-dependent quantities between the tables
+    at theta (1 + m rel), m = +-1 (and +-2); then the projection's tangent,
+    los(tables, Sdot) plus the same difference of los at fixed sources, and
+    the quadrature's (cl_tangent).  ln A_s and n_s as in jacobian.
+    Returns (C_l, J, status of the base run)."""
+    if order not in (2, 4):
+        raise ValueError("order must be 2 or 4")
+    t = build_tables(cosmo, prec, k, n_tau)
+    S0, st, ns, hist, hn = perturb_hist(t)
+    mults = (1.0, -1.0, 2.0, -2.0)[: 2 if order == 2 else 4]
+    tabs, eps = [], []
+    for name in JAC_PARAMS:
+        row = []
+        for mult in mults:
+            c2 = dict(cosmo)
+            c2[name] = cosmo[name] * (1.0 + mult * rel)
+            row.append(build_tables(c2, prec, k, n_tau))
+        tabs.append(row)
+        eps.append(rel * cosmo[name])
+    S, Sd, st2 = perturb_tangent(t, tabs, eps, hist, hn, order)
+    DT, DE = los(t, S, ell_max, pol)
+    C = cl(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    J = np.zeros((6, 3, ell_max + 1))
+    slot = {"h": 0, "omega_b": 1, "omega_cdm": 2, "tau_reio": 5}
+
+    def diff(vals, e):
+        if order == 2:
+            return (vals[0] - vals[1]) / (2.0 * e)
+        return (8.0 * (vals[0] - vals[1]) - (vals[2] - vals[3])) / (12.0 * e)
+
+    for d, name in enumerate(JAC_PARAMS):
+        dT, dE = los(t, Sd[:, d], ell_max, pol)
+        at = [los(x, S, ell_max, pol) for x in tabs[d]]
+        dT = dT + diff([a[0] for a in at], eps[d])
+        dE = dE + diff([a[1] for a in at], eps[d])
+        J[slot[name]] = cl_tangent(t.k, DT, DE, dT, dE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    J[3] = C
+    J[4] = cl_dns(t.k, DT, DE, ell_max, pol, cosmo["A_s"], cosmo["n_s"], prec["k_pivot"])
+    st = np.where(st != 0, st, st2)
     return C, J, st
 
 

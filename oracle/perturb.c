@@ -388,6 +388,23 @@ static int lu_solve(int N, const double *M, double *r, double *LU, int *piv, dou
     return 0;
 }
 
+/* Solve M x = r again with the factors lu_solve left in LU, piv (same two
+   refinement steps). */
+static void lu_resolve(int N, const double *M, const double *LU, const int *piv, double *r, double *res) {
+    double *b = res + N;
+    memcpy(b, r, sizeof(double) * N);
+    lu_apply(N, LU, piv, r);
+    for (int it = 0; it < 2; ++it) {
+        for (int i = 0; i < N; ++i) {
+            long double acc = b[i];
+            for (int j = 0; j < N; ++j) acc -= (long double)M[i * N + j] * r[j];
+            res[i] = (double)acc;
+        }
+        lu_apply(N, LU, piv, res);
+        for (int i = 0; i < N; ++i) r[i] += res[i];
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* ESDIRK: implicit part of ARK4(3)6L[2]SA (Kennedy & Carpenter 2003), gamma = 1/4 */
 /* ------------------------------------------------------------------------- */
@@ -607,6 +624,179 @@ int oracle_perturb(const otab_t *tb, const oprec_t *p, double k, double lna0, in
     free(work);
     free(piv);
     return status;
+}
+
+/* Derivative of a table-dependent quantity from its values at theta +- eps
+   (v1, m1) and, for order 4, at theta +- 2 eps (v2, m2): the central
+   difference (v1 - m1) / (2 eps) or the five-point
+   (8 (v1 - m1) - (v2 - m2)) / (12 eps). */
+static double tdiff(int order, double eps, double v1, double m1, double v2, double m2) {
+    if (order == 4) return (8.0 * (v1 - m1) - (v2 - m2)) / (12.0 * eps);
+    return (v1 - m1) / (2.0 * eps);
+}
+
+/*
+ * Forward-mode tangents of one mode along a fixed step sequence (the start
+ * fixed[0] and the step sizes fixed[1..n_fixed]): the derivative of the
+ * discrete map (initial state, ESDIRK stages, dense output, sources) with
+ * respect to nd parameters (section 3: the paper's forward-mode option).
+ * Parameter d enters only through the tables: tt[(4 d + m)] for m = 0..3 are
+ * the tables at theta_d + eps[d], - eps[d], + 2 eps[d], - 2 eps[d] (the last
+ * two read only for order 4), and each table-dependent quantity at a fixed
+ * state (the right-hand side, the initial state, the sources) is
+ * differentiated by the central (order 2) or five-point (order 4)
+ * difference between them (tdiff).  The state's tangent is carried through
+ * the stages exactly:
+ *   Rdot_s = ydot_n + h sum_{j<s} a_sj Kdot_j,
+ *   (I - h gamma A_s) Ydot_s = Rdot_s + h gamma Adot_s Y_s,
+ *   Kdot_s = Adot_s Y_s + A_s Ydot_s,   ydot_{n+1} = Ydot_5,
+ * and at each output time Sdot = S(ydot) + dS/dtheta at the fixed state (the
+ * sources are linear in the state).  S: [3][n_out]; Sd: [nd][3][n_out].
+ */
+int oracle_perturb_tangent(const otab_t *tb, const otab_t *tt, const double *eps, int nd, int order,
+                           const oprec_t *p, double k, int n_out, const double *lna_out, double *S, double *Sd,
+                           const double *fixed, int n_fixed) {
+    olayout_t L;
+    make_layout(p, &L);
+    const int N = L.N;
+    if (p->lg < 3 || p->ln < 3 || (p->lp != 0 && p->lp < 3) || (p->nq > 0 && p->lq < 3) || p->nq > MAXQ || k <= 0 ||
+        nd < 1 || !fixed || (order != 2 && order != 4))
+        return O_BAD_INPUT;
+    const int nt = order == 4 ? 4 : 2; /* tables per parameter that are read */
+    const size_t nn = (size_t)N * N, nv = (size_t)nd * N;
+    double *work = (double *)calloc(3 * nn + 22 * (size_t)N + 12 * nv, sizeof(double));
+    int *piv = (int *)calloc((size_t)N, sizeof(int));
+    double *A = work, *Mm = A + nn, *LU = Mm + nn;
+    double *y = LU + nn, *f = y + N, *ynew = f + N, *R = ynew + N, *e = R + N, *col = e + N, *K = col + N;
+    double *ytmp = K + 6 * N, *dyt = ytmp + N, *v = dyt + N, *res = v + 4 * N; /* v: 4 N, res: 2 N */
+    double *yd = res + 2 * N, *fd = yd + nv, *ynewd = fd + nv, *Rd = ynewd + nv, *Kd = Rd + nv; /* Kd: 6 nv */
+    double *ytd = Kd + 6 * nv;
+    for (int i = 0; i < 3 * n_out; ++i) S[i] = 0.0;
+    for (size_t i = 0; i < (size_t)nd * 3 * n_out; ++i) Sd[i] = 0.0;
+    int status = O_OK;
+    double t = fixed[0];
+    obg_t b, bt[4];
+    background_at(tb, t, &b);
+    initial_conditions(tb, p, &L, k, &b, y);
+    build_A(tb, p, &L, k, &b, A, e, col);
+    matvec(N, A, y, f);
+    for (int d = 0; d < nd; ++d) {
+        for (int m = 0; m < nt; ++m) {
+            background_at(&tt[4 * d + m], t, &bt[m]);
+            initial_conditions(&tt[4 * d + m], p, &L, k, &bt[m], v + m * N);
+        }
+        for (int i = 0; i < N; ++i)
+            yd[d * N + i] = tdiff(order, eps[d], v[i], v[N + i], v[2 * N + i], v[3 * N + i]);
+        for (int m = 0; m < nt; ++m) rhs(&tt[4 * d + m], p, &L, k, &bt[m], y, v + m * N, NULL, NULL);
+        matvec(N, A, yd + d * N, fd + d * N);
+        for (int i = 0; i < N; ++i)
+            fd[d * N + i] += tdiff(order, eps[d], v[i], v[N + i], v[2 * N + i], v[3 * N + i]);
+    }
+    int jo = 0;
+    while (jo < n_out && lna_out[jo] < t) ++jo;
+    const double gam = 0.25;
+    int na = 0;
+    while (t < 0.0) {
+        if (na >= n_fixed) {
+            status = O_MAX_STEPS;
+            break;
+        }
+        const double h = fixed[1 + na];
+        const int last = t + h >= 0.0;
+        memcpy(K, f, sizeof(double) * N);
+        memcpy(Kd, fd, sizeof(double) * nv);
+        for (int s = 1; s < 6; ++s) {
+            double ts = t + RK_c[s] * h;
+            if (s == 5) ts = last ? 0.0 : t + h;
+            for (int i = 0; i < N; ++i) {
+                double acc = y[i];
+                for (int j = 0; j < s; ++j) acc += h * RK_A[s][j] * K[j * N + i];
+                R[i] = acc;
+            }
+            for (int d = 0; d < nd; ++d)
+                for (int i = 0; i < N; ++i) {
+                    double acc = yd[d * N + i];
+                    for (int j = 0; j < s; ++j) acc += h * RK_A[s][j] * Kd[(size_t)j * nv + d * N + i];
+                    Rd[d * N + i] = acc;
+                }
+            obg_t bs;
+            background_at(tb, ts, &bs);
+            build_A(tb, p, &L, k, &bs, A, e, col);
+            for (size_t i = 0; i < nn; ++i) Mm[i] = -h * gam * A[i];
+            for (int i = 0; i < N; ++i) Mm[i * N + i] += 1.0;
+            if (lu_solve(N, Mm, R, LU, piv, res) != 0) { /* R becomes Y_s */
+                status = O_NONFINITE;
+                break;
+            }
+            matvec(N, A, R, K + s * N);
+            for (int d = 0; d < nd; ++d) {
+                for (int m = 0; m < nt; ++m) {
+                    background_at(&tt[4 * d + m], ts, &bt[m]);
+                    rhs(&tt[4 * d + m], p, &L, k, &bt[m], R, v + m * N, NULL, NULL);
+                }
+                double *Yd = Rd + d * N, *kd = Kd + (size_t)s * nv + d * N;
+                for (int i = 0; i < N; ++i) {
+                    v[i] = tdiff(order, eps[d], v[i], v[N + i], v[2 * N + i], v[3 * N + i]); /* Adot_s Y_s */
+                    Yd[i] += h * gam * v[i];
+                }
+                lu_resolve(N, Mm, LU, piv, Yd, res);
+                matvec(N, A, Yd, kd);
+                for (int i = 0; i < N; ++i) kd[i] += v[i];
+            }
+            if (s == 5) {
+                memcpy(ynew, R, sizeof(double) * N);
+                memcpy(ynewd, Rd, sizeof(double) * nv);
+            }
+        }
+        if (status != O_OK) break;
+        double tn = last ? 0.0 : t + h;
+        if (tn >= 0.0) tn = 0.0;
+        while (jo < n_out && lna_out[jo] <= tn) {
+            const double hh = tn - t;
+            const double th = (hh > 0.0) ? (lna_out[jo] - t) / hh : 1.0;
+            const double h00 = 2 * th * th * th - 3 * th * th + 1, h10 = th * th * th - 2 * th * th + th;
+            const double h01 = -2 * th * th * th + 3 * th * th, h11 = th * th * th - th * th;
+            for (int i = 0; i < N; ++i)
+                ytmp[i] = h00 * y[i] + h10 * hh * f[i] + h01 * ynew[i] + h11 * hh * K[5 * N + i];
+            sources_at(tb, p, &L, k, lna_out[jo], ytmp, dyt, &S[jo], &S[n_out + jo], &S[2 * n_out + jo], NULL);
+            for (int d = 0; d < nd; ++d) {
+                for (int i = 0; i < N; ++i)
+                    ytd[d * N + i] = h00 * yd[d * N + i] + h10 * hh * fd[d * N + i] + h01 * ynewd[d * N + i] +
+                                     h11 * hh * Kd[5 * nv + d * N + i];
+                double sl[3], st[4][3] = {{0}};
+                sources_at(tb, p, &L, k, lna_out[jo], ytd + d * N, dyt, &sl[0], &sl[1], &sl[2], NULL);
+                for (int m = 0; m < nt; ++m)
+                    sources_at(&tt[4 * d + m], p, &L, k, lna_out[jo], ytmp, dyt, &st[m][0], &st[m][1], &st[m][2],
+                               NULL);
+                double *o = Sd + (size_t)d * 3 * n_out;
+                for (int c = 0; c < 3; ++c)
+                    o[c * n_out + jo] = sl[c] + tdiff(order, eps[d], st[0][c], st[1][c], st[2][c], st[3][c]);
+            }
+            ++jo;
+        }
+        ++na;
+        memcpy(y, ynew, sizeof(double) * N);
+        memcpy(f, K + 5 * N, sizeof(double) * N);
+        memcpy(yd, ynewd, sizeof(double) * nv);
+        memcpy(fd, Kd + 5 * nv, sizeof(double) * nv);
+        t = tn;
+    }
+    free(work);
+    free(piv);
+    return status;
+}
+
+/* Forward-mode tangents of all modes (oracle_perturb_tangent), in parallel
+   over k, each mode replaying its own history hist[i][0 .. hn[i]]. */
+int oracle_perturb_many_tangent(const otab_t *tb, const otab_t *tt, const double *eps, int nd, int order,
+                                const oprec_t *p0, int nk, const double *k, int n_out, const double *lna_out,
+                                double *S, double *Sd, int *status, const double *hist, const int *hn, int cap) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = nk - 1; i >= 0; --i)
+        status[i] = oracle_perturb_tangent(tb, tt, eps, nd, order, p0, k[i], n_out, lna_out,
+                                           S + (size_t)i * 3 * n_out, Sd + (size_t)i * nd * 3 * n_out,
+                                           hist + (size_t)i * cap, hn[i]);
+    return 0;
 }
 
 /* All modes of one cosmology, in parallel over k (each mode is independent

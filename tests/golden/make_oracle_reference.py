@@ -1,7 +1,7 @@
 """Write the oracle spectra used by the GPU parity tests at full size.
 
     python tests/golden/make_oracle_reference.py [config1] [config2] [config1_transfer] [config1_jacobian]
-                                                 [tight_config0] [tight_config1]
+                                                 [config1_tangent] [tight_config0] [tight_config1]
 
 Calls only the CPU oracle (package ``oracle``) and the seeded workload
 generator; re-run it whenever the oracle's arithmetic changes.  Outputs, for
@@ -16,6 +16,10 @@ plus, for config 2, the per-mode step counts (oracle_config2_nsteps.npy), and
   tests/golden/oracle_config1_jacobian.npy  dC_l/d(h, omega_b, omega_cdm, ln A_s,
                                       n_s, tau_reio) [6][3][2501] for config 1
                                       (five-point stencil, rel 1e-4, frozen steps)
+  tests/golden/oracle_config1_tangent.npy  the same derivatives by forward mode:
+                                      tangents carried through the frozen-step
+                                      stages, five-point differences of the
+                                      table-dependent quantities only
   tests/golden/oracle_tight_config0.npz, oracle_tight_config1_subset.npz
                                       the tight-tolerance cross-check: config 0
                                       in full and config 1 on eight of its modes,
@@ -55,6 +59,14 @@ def main(which):
     for name in which:
         if name.startswith("tight_"):
             tight(name[len("tight_"):])
+            continue
+        if name.endswith("_tangent"):
+            wl = getattr(W, name.replace("_tangent", ""))()
+            t0 = time.time()
+            C, J, st = O.jacobian_tangent(wl.cosmo, wl.prec, wl.k, wl.n_tau, wl.ell_max, True, rel=1e-4, order=4)
+            assert np.all(st == 0)
+            np.save(os.path.join(HERE, f"oracle_{name}.npy"), J)
+            print(f"wrote oracle_{name}.npy in {time.time() - t0:.1f} s", flush=True)
             continue
         if name.endswith("_jacobian"):
             wl = getattr(W, name.replace("_jacobian", ""))()

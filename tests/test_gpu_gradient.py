@@ -4,7 +4,8 @@ tangents by central differences), against the oracle.
 
   dL/dtheta   against the oracle's frozen-step five-point derivatives (rel
               1e-4) contracted with the same dL/dC_l: per parameter within
-              1e-4 of sum |dL/dC_l| |dC_l/dtheta_p|;
+              1e-4 of sum |dL/dC_l| |dC_l/dtheta_p|; at config 1 also against
+              the oracle's forward-mode tangents;
   dL/dy0      dot products with seeded directions: L is quadratic in the
               sources and the sources are linear in a mode's start state at
               fixed steps, so the oracle's central difference of L along a
@@ -198,7 +199,8 @@ def test_gradient_matches_frozen_step_central_differences(ctx, case):
 def test_gradient_config1(ctx):
     """Config 1 (400 modes, 2000 output times, l <= 2500), fiducial cosmology:
     dL/dtheta for seeded dL/dC_l against the stored oracle derivatives
-    (tests/golden/make_oracle_reference.py) contracted with it."""
+    (tests/golden/make_oracle_reference.py) contracted with it: the
+    frozen-step five-point differences and the forward-mode tangents."""
     import paper_2602_15104_amd as L
     ref = os.path.join(GOLD, "oracle_config1_jacobian.npy")
     assert os.path.exists(ref), "oracle golden missing: run tests/golden/make_oracle_reference.py"
@@ -209,13 +211,16 @@ def test_gradient_config1(ctx):
     _say("gradient config1: 400 modes, 2000 times, l <= 2500")
     _, g, st, _ = _gradient(ctx, [tab], lm, gC)
     assert np.all(st == 0)
-    Jo = np.load(ref)
-    for p in range(6):
-        r = float(np.sum(gC[0] * Jo[p]))
-        scale = float(np.sum(np.abs(gC[0] * Jo[p])))
-        e = abs(g[0, p] - r) / scale
-        _say("config1 gradient param", p, "adjoint", g[0, p], "oracle", r, "err", e)
-        assert e <= 1e-4, (p, e)
+    ref_fw = os.path.join(GOLD, "oracle_config1_tangent.npy")
+    assert os.path.exists(ref_fw), "oracle golden missing: run tests/golden/make_oracle_reference.py config1_tangent"
+    for what, path in (("frozen-step differences", ref), ("forward mode", ref_fw)):
+        Jo = np.load(path)
+        for p in range(6):
+            r = float(np.sum(gC[0] * Jo[p]))
+            scale = float(np.sum(np.abs(gC[0] * Jo[p])))
+            e = abs(g[0, p] - r) / scale
+            _say("config1 gradient param", p, "adjoint", g[0, p], "oracle", what, r, "err", e)
+            assert e <= 1e-4, (what, p, e)
 
 
 def test_gradient_refusals(ctx):
