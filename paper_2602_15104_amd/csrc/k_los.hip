@@ -70,8 +70,22 @@ __device__ inline void seed_miller(double x, double ix, double j0, double j1, in
     double rp = 0.0, rl = 0.0;
     double c = 2.0 * ls + 1.0;  // 2l + 1 of the next step
     const double c_rec = 2.0 * la + 3.0;  // the step at l = l_act + 1
-#pragma unroll 2
-    for (; c > c_rec; c -= 2.0) {
+    // steps in pairs, the two arrays taking turns (no moves): after the first
+    // step of a pair hi holds J_{l-1} and lo J_l, after the second lo holds
+    // J_{l-2} and hi J_{l-1}; one test for the end and one for the rescaling
+    // per pair.  A pair rescales once a value passes 1e200, which leaves
+    // 1e108 for the growth of the next pair (at most ((2l+1)/x)^2); the
+    // values of the recurrence stay far below 1e200 at every x the tables
+    // produce, so the pairs take exactly the single steps' operations.
+    for (; c > c_rec + 2.0; c -= 4.0) {
+        hi = c * ix * lo - hi;
+        lo = (c - 2.0) * ix * hi - lo;
+        if (__builtin_expect(fmax(fabs(lo), fabs(hi)) > 1e200, 0)) {
+            lo *= 1e-250;
+            hi *= 1e-250;
+        }
+    }
+    if (c > c_rec) {
         const double nlo = c * ix * lo - hi;
         hi = lo;
         lo = nlo;
@@ -79,6 +93,7 @@ __device__ inline void seed_miller(double x, double ix, double j0, double j1, in
             lo *= 1e-250;
             hi *= 1e-250;
         }
+        c -= 2.0;
     }
     {  // l = l_act + 1: (hi, lo) becomes (J_{l_act+1}, J_{l_act})
         const double nlo = c * ix * lo - hi;
@@ -94,8 +109,17 @@ __device__ inline void seed_miller(double x, double ix, double j0, double j1, in
         }
         c -= 2.0;
     }
-#pragma unroll 2
-    for (; c > 2.0; c -= 2.0) {  // l = l_act .. 1
+    for (; c > 4.0; c -= 4.0) {  // l = l_act .. 2 in pairs, as above
+        hi = c * ix * lo - hi;
+        lo = (c - 2.0) * ix * hi - lo;
+        if (__builtin_expect(fmax(fabs(lo), fabs(hi)) > 1e200, 0)) {
+            lo *= 1e-250;
+            hi *= 1e-250;
+            rp *= 1e-250;
+            rl *= 1e-250;
+        }
+    }
+    if (c > 2.0) {  // l = 1
         const double nlo = c * ix * lo - hi;
         hi = lo;
         lo = nlo;
